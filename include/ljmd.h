@@ -1,0 +1,179 @@
+/*
+ * ljmd.h -- C ABI of the MI355X (gfx950) Lennard-Jones molecular-dynamics hot path.
+ *
+ * The calls follow the paper's statement of an MD simulation (Section "Capabilities",
+ * Molecular dynamics listing; Section "Python package"): build a system from a periodic
+ * box and particles, set Lennard-Jones epsilon, sigma and r_cut per type pair through a
+ * cell-list neighbour list, set the time step, run a number of NVE steps, and read the
+ * force, energy and virial that the paper's pair-force unit test checks (Section "Software
+ * engineering", Testing).
+ *
+ * Definitions used throughout (the paper names the method; these are the textbook forms):
+ *   minimum image  d = x_j - x_i per axis, reduced into [-L/2, L/2) by adding or
+ *                  subtracting one box length.
+ *   pair energy    u(r) = 4 eps ((s/r)^12 - (s/r)^6) - 4 eps ((s/r_cut)^12 - (s/r_cut)^6)
+ *                  for r < r_cut, else 0 (truncated and shifted).
+ *   pair force     on i from j: 24 eps (2 (s/r)^12 - (s/r)^6) / r^2 * (x_i - x_j), not
+ *                  shifted, zero for r >= r_cut.
+ *   virial         W_ab = sum over pairs (i<j) of (x_i - x_j)_a F_ij,b, stored as
+ *                  (xx, xy, xz, yy, yz, zz).
+ *   neighbour list all j with r^2 < (r_cut_ab + skin)^2, rebuilt when any particle has
+ *                  moved (minimum image) at least skin/2 since the last build.
+ *   step           velocity Verlet: v += dt/(2m) F; x += dt v (wrapped into [0, L), image
+ *                  counters updated); F recomputed; v += dt/(2m) F.
+ *
+ * Conventions
+ *   - Every function returns LJMD_OK (0) or a negative LJMD_E_* status; ljmd_last_error()
+ *     then gives a message. No C++ exception crosses this interface.
+ *   - Host arrays passed in are copied; the caller keeps ownership. Output arrays are
+ *     allocated by the caller, host memory, in input (tag) order: particle k of the
+ *     arrays given to ljmd_system_create is particle k of every output.
+ *   - Device state is owned by the handle and allocated through the configured allocator
+ *     on the configured stream. All device work is enqueued on that stream.
+ *   - A handle must be used by one host thread at a time.
+ *   - Array shapes: positions, velocities and forces are n x 3 doubles, row-major
+ *     (x0 y0 z0 x1 ...); per-particle virials are n x 6 doubles in (xx,xy,xz,yy,yz,zz).
+ */
+#ifndef LJMD_H
+#define LJMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LJMD_OK 0
+#define LJMD_E_INVAL -1     /* null pointer, n < 1, type out of range, dt <= 0, sigma <= 0,
+                               r_cut < 0, non-finite input, unknown option */
+#define LJMD_E_NOMEM -2     /* the allocator returned NULL */
+#define LJMD_E_DEVICE -3    /* no usable GPU, or a HIP runtime error */
+#define LJMD_E_BOX -4       /* max over pairs of (r_cut + skin) exceeds half a box edge */
+#define LJMD_E_NONFINITE -5 /* a force became non-finite (for example overlapping particles) */
+#define LJMD_E_STATE -6     /* a type pair has not been set, or a batch slot is not ready */
+#define LJMD_E_CAPACITY -7  /* batch admission: no free slot or not enough memory budget */
+
+/* precision of the pair arithmetic */
+#define LJMD_FP64 0  /* everything in FP64 */
+#define LJMD_MIXED 1 /* FP32 pair arithmetic; FP64 positions, velocities, integration and
+                        energy/virial sums */
+
+/* Device memory callbacks. alloc returns device memory of at least `bytes` usable on
+ * `stream`, or NULL; free releases it. With both NULL the library uses hipMalloc/hipFree. */
+typedef void *(*ljmd_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*ljmd_free_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+
+typedef struct ljmd_config {
+    double box[3];          /* orthorhombic box edges L_x, L_y, L_z (> 0) */
+    int32_t ntypes;         /* number of particle types, 1..LJMD_MAX_TYPES */
+    double dt;              /* time step (> 0), reduced units */
+    double skin;            /* Verlet skin r_s (>= 0) */
+    int32_t precision;      /* LJMD_FP64 or LJMD_MIXED */
+    int32_t nlist_capacity; /* entries per particle; 0 = sized from the first build */
+    int32_t threads_per_particle; /* lanes per particle in the force kernel: 1,2,4,8,16
+                                     or 0 = autotuned */
+    int32_t block_size;     /* force kernel workgroup size: 64, 128, 192 or 256;
+                               0 = autotuned */
+    int32_t graph_steps;    /* steps per captured HIP graph block (even, >= 2); 0 = 64;
+                               -1 disables graphs */
+    void *stream;           /* hipStream_t; NULL = the default stream */
+    ljmd_alloc_fn alloc;    /* NULL = hipMalloc */
+    ljmd_free_fn free;      /* NULL = hipFree */
+    void *alloc_ctx;        /* passed through to alloc/free */
+} ljmd_config;
+
+#define LJMD_MAX_TYPES 16
+
+typedef struct ljmd_stats {
+    int64_t steps;            /* steps taken since create */
+    int64_t rebuilds;         /* neighbour-list builds (from the device counter) */
+    int32_t max_neighbors;    /* largest list length seen at a build */
+    int32_t nlist_capacity;   /* current entries per particle */
+    int64_t overflow_retries; /* step segments re-run after growing the list */
+    int32_t threads_per_particle;
+    int32_t block_size;
+    int32_t ncell[3];         /* cells per axis */
+    int32_t graph_steps;
+    int64_t device_bytes;     /* device memory held by the handle */
+    int64_t list_entries;     /* entries stored by the last list build (sum over particles) */
+} ljmd_stats;
+
+typedef struct ljmd_system ljmd_system;
+
+/* Create a system of n particles, 1 <= n <= 2^26. pos, vel: n x 3 host doubles (positions
+ * may lie outside the box; they are wrapped, with image counters). type: n host int32 in [0, ntypes).
+ * mass: n host doubles (> 0) or NULL for unit masses. Pair coefficients must then be set
+ * with ljmd_pair_lj_set for every type pair before stepping or reading. *out receives the
+ * handle, or NULL on error. Errors: INVAL, NOMEM, DEVICE. */
+int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos,
+                       const double *vel, const int32_t *type, const double *mass,
+                       ljmd_system **out);
+
+/* Frees all device memory through the same allocator. NULL is ignored. */
+void ljmd_system_destroy(ljmd_system *sys);
+
+/* Set the LJ pair (a, b), symmetric in a and b. r_cut = 0 disables the pair. May be
+ * called at any time (the paper's unit test changes parameters between evaluations); the
+ * list and forces are rebuilt before the next step or read. Errors: INVAL. */
+int ljmd_pair_lj_set(ljmd_system *sys, int32_t a, int32_t b, double epsilon, double sigma,
+                     double r_cut);
+
+/* Advance nsteps velocity-Verlet NVE steps on the configured stream and synchronise once
+ * at the end to report status. nsteps = 0 only makes the list and forces current.
+ * Errors: INVAL, STATE (pair unset), BOX, NONFINITE, NOMEM, DEVICE. On NONFINITE the
+ * state is restored to what it was when the call began. */
+int ljmd_step(ljmd_system *sys, int64_t nsteps);
+
+/* Forces at the current positions, n x 3 host doubles, tag order. */
+int ljmd_get_forces(ljmd_system *sys, double *out);
+
+/* Total shifted LJ potential energy and kinetic energy (sum of m v^2 / 2 over full-step
+ * velocities); either pointer may be NULL. Reduced in FP64 in a fixed order. */
+int ljmd_get_energy(ljmd_system *sys, double *potential, double *kinetic);
+
+/* Virial tensor W (6 doubles, xx xy xz yy yz zz), reduced in FP64 in a fixed order. */
+int ljmd_get_virial(ljmd_system *sys, double *out6);
+
+/* Per-particle halves of each pair's energy (n doubles) and virial (n x 6 doubles), tag
+ * order; either pointer may be NULL. */
+int ljmd_get_per_particle(ljmd_system *sys, double *u, double *w);
+
+/* Checkpoint: positions (wrapped, n x 3), velocities (n x 3), image counters (n x 3 int32)
+ * and the step counter; any pointer may be NULL. */
+int ljmd_get_state(ljmd_system *sys, double *pos, double *vel, int32_t *img, int64_t *step);
+
+/* Resume: replace positions (required; wrapped on upload), velocities (required), image
+ * counters (NULL = all zero; added to the images the wrap produces) and the step counter
+ * (NULL = keep). Types and masses are those given at create. Forces a list rebuild. */
+int ljmd_set_state(ljmd_system *sys, const double *pos, const double *vel, const int32_t *img,
+                   const int64_t *step);
+
+/* The current neighbour list as unordered tag pairs (i < j), 2 x count int32, sorted by
+ * (i, j); pairs = NULL only returns the count. build_pos (n x 3, tag order, nullable)
+ * receives the positions the list was built from. */
+int ljmd_get_neighbor_pairs(ljmd_system *sys, int64_t *count, int32_t *pairs,
+                            double *build_pos);
+
+/* Counters and tuned launch parameters. */
+int ljmd_get_stats(ljmd_system *sys, ljmd_stats *out);
+
+/* Kernel timing for measurement: when on != 0, every launch of the step's dominant kernel
+ * (the fused force + integration kernel) is bracketed by HIP events on the configured
+ * stream and graphs are not used. ljmd_kernel_time returns the launch count and the summed
+ * event time in milliseconds since timing was switched on. */
+int ljmd_set_kernel_timing(ljmd_system *sys, int32_t on);
+int ljmd_kernel_time(ljmd_system *sys, int64_t *launches, double *total_ms);
+
+/* Thread-local message for the last non-zero status returned on this thread. */
+const char *ljmd_last_error(void);
+
+/* Library version string. */
+const char *ljmd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LJMD_H */

@@ -1,0 +1,126 @@
+// Internal definitions shared by the device kernels and the host side of libljmd.
+// Not part of the public C ABI (that is include/ljmd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ljmd {
+
+// Per type pair coefficients of the truncated-and-shifted LJ potential, FP64.
+// rc2 = r_cut^2 and rl2 = (r_cut + skin)^2 are 0 for a disabled pair.
+struct PairCoef {
+    double rc2;
+    double rl2;
+    double lj1;    // 48 eps sig^12   force:  f = r^-2 r^-6 (lj1 r^-6 - lj2)
+    double lj2;    // 24 eps sig^6
+    double lj3;    // 4 eps sig^12    energy: u = r^-6 (lj3 r^-6 - lj4) - shift
+    double lj4;    // 4 eps sig^6
+    double shift;  // 4 eps ((sig/r_cut)^12 - (sig/r_cut)^6)
+    double pad;
+};
+
+// Device status block (one per system).
+struct DevStatus {
+    int rebuild[2];          // rebuild request, indexed by the position buffer just written
+    int status;              // ST_* bits
+    int max_count;           // longest list seen at a build
+    unsigned long long builds;
+    unsigned long long entries;  // list entries written at the last build
+    int one;                 // constant 1: "go" word of an unconditional rebuild
+    int pad;
+};
+
+enum { ST_OVERFLOW = 1, ST_NONFINITE = 2 };
+
+enum { MODE_EVAL = 0, MODE_FUSED = 1, MODE_FINAL = 2 };
+enum { PREC_FP64 = 0, PREC_MIXED = 1 };
+
+constexpr int LJMD_MAX_TYPES_DEV = 16; // equals LJMD_MAX_TYPES of the public header
+constexpr int NL_LDS_ATOMS = 1024;   // staged stencil atoms per build workgroup (32 KiB)
+constexpr int NL_BLOCK = 128;        // build workgroup size
+constexpr int NL_LANES = 4;          // lanes per particle in the build
+constexpr int RED_BLOCK = 256;       // reduction workgroup size
+constexpr int RED_QUANT = 8;         // U, W[6], K
+constexpr int SORT_LDS = 1024;       // in-cell sort capacity per workgroup
+
+// Arguments of the force kernel family (by value).
+struct ForceArgs {
+    const double4 *pos_in;   // x, y, z, type (as double); sorted order
+    double4 *pos_out;        // MODE_FUSED: positions after the drift
+    double4 *vel;            // vx, vy, vz, 1/m
+    int4 *img;               // image counters x, y, z and the tag in w
+    const double4 *xb;       // positions at the last build
+    double4 *force;          // MODE_EVAL / MODE_FINAL output
+    const int *nl_count;
+    const int *nlist;
+    double *u_out;           // per-particle energy half-sums (ENERGY)
+    double *w_out;           // per-particle virial half-sums, 6 per particle (ENERGY)
+    double *ke_out;          // per-particle kinetic energy at the full step (ENERGY, FUSED)
+    const PairCoef *pair;    // ntypes x ntypes
+    int *rebuild_set;        // FUSED: raised when a particle moved >= skin/2
+    int *rebuild_clear;      // FUSED: the other buffer's request, cleared by workgroup 0
+    int *status;
+    PairCoef single;         // pair (0,0) when ntypes == 1
+    double L[3], invL[3];
+    double dt, half_dt, lim2;
+    int n, npad, cap, lshift, ntypes;
+};
+
+struct KickDriftArgs {
+    const double4 *pos_in;
+    double4 *pos_out;
+    double4 *vel;
+    int4 *img;
+    const double4 *xb;
+    const double4 *force;
+    int *rebuild_set;
+    int *rebuild_clear;
+    double L[3], invL[3];
+    double dt, half_dt, lim2;
+    int n;
+};
+
+struct RebuildArgs {
+    const int *go;           // the rebuild runs only if *go != 0
+    const double *rl2_table; // ntypes x ntypes list radii squared
+    double4 *pos;            // current positions (sorted order); rewritten in new order
+    double4 *pos_scr;
+    double4 *vel, *vel_scr;
+    int4 *img, *img_scr;
+    double4 *xb;
+    int *key, *slot, *perm;
+    int *cell_count;         // ncell, zero between builds
+    int *cell_start;         // ncell + 1
+    const int *cell_rank;    // linear cell index -> Morton rank
+    const int *cell_xyz;     // Morton rank -> packed (cx | cy << 10 | cz << 20)
+    int *nl_count, *nlist;
+    const PairCoef *pair;
+    DevStatus *st;
+    double L[3], invL[3], inv_w[3];
+    double single_rl2;
+    int nc[3];
+    int ncell, n, npad, cap, lshift, ntypes;
+    int canonical_mi;        // 1 when some axis has fewer than 3 cells
+};
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_upload(hipStream_t s, const double *pos, const double *vel, const int *type,
+                         const double *mass, double4 *pos4, double4 *vel4, int4 *img, int n,
+                         const double L[3], int set_vel, int set_img, const int *img_in);
+hipError_t launch_kick_drift(hipStream_t s, const KickDriftArgs &a);
+hipError_t launch_force(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                        bool energy, int block);
+hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a);
+hipError_t launch_reduce(hipStream_t s, const double *u, const double *w, const double *ke,
+                         const double4 *vel, int n, double *partials, int nblocks_max,
+                         double *out);
+hipError_t launch_unsort_vec(hipStream_t s, const double4 *src, const int4 *img, int n,
+                             double *dst);
+hipError_t launch_unsort_img(hipStream_t s, const int4 *img, int n, int *dst);
+hipError_t launch_unsort_scalar(hipStream_t s, const double *src, int width, const int4 *img,
+                                int n, double *dst);
+hipError_t launch_fill_status(hipStream_t s, DevStatus *st);
+
+}  // namespace ljmd

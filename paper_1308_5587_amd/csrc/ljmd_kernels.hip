@@ -1,0 +1,824 @@
+// Device kernels of the LJ MD hot path for gfx950 (CDNA4, wave64).
+//
+// This file is compiled with -ffp-contract=off: every fused multiply-add below is written
+// explicitly, and the squared distance that decides list membership and the cutoff is
+// formed as (dx*dx + dy*dy) + dz*dz with separate roundings, the operation order that
+// defines the neighbour list bit for bit.
+//
+// Data layout (sorted order: particles grouped by cell, cells in Morton order):
+//   pos    double4 (x, y, z, type)        two buffers, the step kernel reads one and
+//                                          writes the other
+//   vel    double4 (vx, vy, vz, 1/m)
+//   img    int4    (image x, y, z, tag)
+//   xb     double4 positions at the last list build
+//   nlist  int32 entries, "tiled entry-major": entry k of particle q is stored at
+//          ((k >> s) * npad + q) << s | (k & (2^s - 1)), s = log2(lanes per particle),
+//          so one wavefront's lanes read 64 consecutive entries per iteration.
+#include "ljmd_internal.h"
+
+namespace ljmd {
+
+// ---------------------------------------------------------------- arithmetic helpers
+
+// Minimum image of a coordinate difference d in (-L, L): subtract k L with k = rint(d/L).
+// For |d| away from L/2 by more than a few ulps this equals the branch form "if d >= L/2
+// subtract L, else if d < -L/2 add L" bit for bit (fma(-k, L, d) rounds d - L once, as the
+// branch form does); within a few ulps of L/2 the two may pick different images, both of
+// length ~L/2, which is beyond every cutoff and list radius.
+__device__ __forceinline__ double mi_rint(double d, double L, double invL) {
+    double k = __builtin_rint(d * invL);
+    return __builtin_fma(-k, L, d);
+}
+
+// Branch form of the minimum image, used where a list radius may reach L/2.
+__device__ __forceinline__ double mi_branch(double d, double L) {
+    double h = 0.5 * L;
+    double up = d - L;
+    double dn = d + L;
+    return d >= h ? up : (d < -h ? dn : d);
+}
+
+__device__ __forceinline__ double r2_canon(double x, double y, double z) {
+    double xx = x * x;
+    double yy = y * y;
+    double zz = z * z;
+    double t = xx + yy;
+    return t + zz;
+}
+
+// 1/x to full FP64 precision: hardware reciprocal estimate plus two Newton steps.
+__device__ __forceinline__ double rcp64(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    return y;
+}
+
+// Workgroup b of nb is dispatched to XCD (b mod 8). Map each XCD to a contiguous range
+// of logical tiles so that spatial neighbours share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    int per = nb >> 3, rem = nb & 7;
+    int x = b & 7, idx = b >> 3;
+    return x * per + (x < rem ? x : rem) + idx;
+}
+
+__device__ __forceinline__ void wrap_coord(double &x, int &im, double L) {
+    if (x >= L) {
+        x = x - L;
+        im += 1;
+    } else if (x < 0.0) {
+        x = x + L;
+        im -= 1;
+        if (x >= L) {  // x + L rounded up to L: the particle sits at 0 in its old image
+            x = 0.0;
+            im += 1;
+        }
+    }
+}
+
+__device__ __forceinline__ size_t nl_slot(int q, int k, int npad, int ls) {
+    return ((((size_t)(k >> ls)) * (size_t)npad + (size_t)q) << ls) | (size_t)(k & ((1 << ls) - 1));
+}
+
+// ---------------------------------------------------------------- upload (create / set_state)
+
+// Host arrays (tag order) -> device SoA in tag order, positions wrapped into [0, L):
+// k = floor(x / L) whole boxes are removed, then one-box rounding fix-ups.
+__global__ void k_upload(const double *__restrict__ pos, const double *__restrict__ vel,
+                         const int *__restrict__ type, const double *__restrict__ mass,
+                         double4 *pos4, double4 *vel4, int4 *img, int n, double L0, double L1,
+                         double L2, int set_vel, int set_img, const int *__restrict__ img_in) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    double Ls[3] = {L0, L1, L2};
+    double x[3];
+    int im[3];
+    for (int a = 0; a < 3; ++a) {
+        double v = pos[3 * q + a];
+        double L = Ls[a];
+        double k = floor(v / L);
+        double kl = k * L;
+        v = v - kl;
+        int m = (int)k;
+        if (v >= L) { v = v - L; m += 1; }
+        if (v < 0.0) { v = v + L; m -= 1; if (v >= L) { v = 0.0; m += 1; } }
+        x[a] = v;
+        im[a] = m + (img_in ? img_in[3 * q + a] : 0);
+    }
+    int tag = q;
+    int t = type[q];
+    pos4[q] = make_double4(x[0], x[1], x[2], (double)t);
+    if (set_vel) {
+        double m = mass ? mass[q] : 1.0;
+        vel4[q] = make_double4(vel[3 * q], vel[3 * q + 1], vel[3 * q + 2], 1.0 / m);
+    }
+    if (set_img) img[q] = make_int4(im[0], im[1], im[2], tag);
+}
+
+hipError_t launch_upload(hipStream_t s, const double *pos, const double *vel, const int *type,
+                         const double *mass, double4 *pos4, double4 *vel4, int4 *img, int n,
+                         const double L[3], int set_vel, int set_img, const int *img_in) {
+    int b = 256;
+    hipLaunchKernelGGL(k_upload, dim3((n + b - 1) / b), dim3(b), 0, s, pos, vel, type, mass,
+                       pos4, vel4, img, n, L[0], L[1], L[2], set_vel, set_img, img_in);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- kick + drift
+
+// First half of a velocity-Verlet step from stored forces: v += dt/(2m) F, x += dt v,
+// wrap, then raise the rebuild request if |x - x_build| (min image) >= skin/2.
+__global__ void __launch_bounds__(256) k_kick_drift(const KickDriftArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild_clear = 0;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    bool exceed = false;
+    if (q < a.n) {
+        double4 x = a.pos_in[q];
+        double4 v = a.vel[q];
+        double4 f = a.force[q];
+        double hm = a.half_dt * v.w;
+        v.x = __builtin_fma(hm, f.x, v.x);
+        v.y = __builtin_fma(hm, f.y, v.y);
+        v.z = __builtin_fma(hm, f.z, v.z);
+        int4 im = a.img[q];
+        int4 im0 = im;
+        x.x = __builtin_fma(a.dt, v.x, x.x);
+        x.y = __builtin_fma(a.dt, v.y, x.y);
+        x.z = __builtin_fma(a.dt, v.z, x.z);
+        wrap_coord(x.x, im.x, a.L[0]);
+        wrap_coord(x.y, im.y, a.L[1]);
+        wrap_coord(x.z, im.z, a.L[2]);
+        a.pos_out[q] = x;
+        a.vel[q] = v;
+        if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
+        double4 b = a.xb[q];
+        double dx = mi_rint(x.x - b.x, a.L[0], a.invL[0]);
+        double dy = mi_rint(x.y - b.y, a.L[1], a.invL[1]);
+        double dz = mi_rint(x.z - b.z, a.L[2], a.invL[2]);
+        exceed = r2_canon(dx, dy, dz) >= a.lim2;
+    }
+    const unsigned long long vote = __ballot(exceed);
+    if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1) atomicOr(a.rebuild_set, 1);
+}
+
+hipError_t launch_kick_drift(hipStream_t s, const KickDriftArgs &a) {
+    int b = 256;
+    hipLaunchKernelGGL(k_kick_drift, dim3((a.n + b - 1) / b), dim3(b), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- force kernel family
+
+template <int TPP>
+__device__ __forceinline__ double lane_sum(double v) {
+#pragma unroll
+    for (int o = TPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, TPP);
+    return v;
+}
+template <int TPP>
+__device__ __forceinline__ float lane_sum(float v) {
+#pragma unroll
+    for (int o = TPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, TPP);
+    return v;
+}
+
+// Accumulators of one lane. FP64 path: everything double. Mixed path: force in FP32,
+// energy and virial in FP64.
+template <int PREC>
+struct Acc;
+template <>
+struct Acc<PREC_FP64> {
+    double fx = 0, fy = 0, fz = 0;
+};
+template <>
+struct Acc<PREC_MIXED> {
+    float fx = 0, fy = 0, fz = 0;
+};
+
+// TPP lanes per particle stride through its list; forces are reduced across the lanes
+// with wavefront shuffles; lane 0 then finishes the particle according to MODE.
+template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI>
+__global__ void __launch_bounds__(256) k_force(const ForceArgs a) {
+    __shared__ PairCoef s_pair[MULTI ? LJMD_MAX_TYPES_DEV * LJMD_MAX_TYPES_DEV : 1];
+    if (MULTI) {
+        int nt2 = a.ntypes * a.ntypes;
+        for (int t = threadIdx.x; t < nt2; t += blockDim.x) s_pair[t] = a.pair[t];
+        __syncthreads();
+    }
+    if (MODE == MODE_FUSED && blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild_clear = 0;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int tid = blk * blockDim.x + threadIdx.x;
+    const int q = tid / TPP;
+    const int lane = tid & (TPP - 1);
+    if (q >= a.n) return;  // whole groups of TPP lanes leave together
+
+    const double4 xi = a.pos_in[q];
+    const int ti = MULTI ? (int)xi.w : 0;
+    int cnt = a.nl_count[q];
+    cnt = cnt < a.cap ? cnt : a.cap;
+    const double L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
+    const double iL0 = a.invL[0], iL1 = a.invL[1], iL2 = a.invL[2];
+
+    Acc<PREC> acc;
+    double ue = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
+
+    const size_t stride = (size_t)a.npad << a.lshift;
+    const int *row = a.nlist + nl_slot(q, lane, a.npad, a.lshift);
+    for (int k = lane; k < cnt; k += TPP, row += stride) {
+        const int j = *row;
+        const double4 xj = a.pos_in[j];
+        const double dx = mi_rint(xj.x - xi.x, L0, iL0);
+        const double dy = mi_rint(xj.y - xi.y, L1, iL1);
+        const double dz = mi_rint(xj.z - xi.z, L2, iL2);
+        const double r2 = r2_canon(dx, dy, dz);
+        const PairCoef &c = MULTI ? s_pair[ti * a.ntypes + (int)xj.w] : a.single;
+        if (r2 < c.rc2) {
+            if (PREC == PREC_FP64) {
+                const double r2i = rcp64(r2);
+                const double r6i = r2i * r2i * r2i;
+                const double ff = r2i * r6i * __builtin_fma(c.lj1, r6i, -c.lj2);
+                // force on i is ff * (x_i - x_j) = -ff * d
+                acc.fx = __builtin_fma(-ff, dx, acc.fx);
+                acc.fy = __builtin_fma(-ff, dy, acc.fy);
+                acc.fz = __builtin_fma(-ff, dz, acc.fz);
+                if (ENERGY) {
+                    ue += 0.5 * (r6i * __builtin_fma(c.lj3, r6i, -c.lj4) - c.shift);
+                    const double hf = 0.5 * ff;
+                    w0 = __builtin_fma(hf * dx, dx, w0);
+                    w1 = __builtin_fma(hf * dx, dy, w1);
+                    w2 = __builtin_fma(hf * dx, dz, w2);
+                    w3 = __builtin_fma(hf * dy, dy, w3);
+                    w4 = __builtin_fma(hf * dy, dz, w4);
+                    w5 = __builtin_fma(hf * dz, dz, w5);
+                }
+            } else {
+                // FP32 pair arithmetic on the exactly formed FP64 displacement
+                const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+                const float fr2 = (float)r2;
+                const float r2i = __builtin_amdgcn_rcpf(fr2);
+                const float r6i = r2i * r2i * r2i;
+                const float l1 = (float)c.lj1, l2 = (float)c.lj2;
+                const float ff = r2i * r6i * __builtin_fmaf(l1, r6i, -l2);
+                acc.fx = __builtin_fmaf(-ff, fdx, acc.fx);
+                acc.fy = __builtin_fmaf(-ff, fdy, acc.fy);
+                acc.fz = __builtin_fmaf(-ff, fdz, acc.fz);
+                if (ENERGY) {
+                    const float l3 = (float)c.lj3, l4 = (float)c.lj4;
+                    const float up = r6i * __builtin_fmaf(l3, r6i, -l4);
+                    ue += 0.5 * ((double)up - c.shift);
+                    const double hf = 0.5 * (double)ff;
+                    w0 = __builtin_fma(hf * (double)fdx, (double)fdx, w0);
+                    w1 = __builtin_fma(hf * (double)fdx, (double)fdy, w1);
+                    w2 = __builtin_fma(hf * (double)fdx, (double)fdz, w2);
+                    w3 = __builtin_fma(hf * (double)fdy, (double)fdy, w3);
+                    w4 = __builtin_fma(hf * (double)fdy, (double)fdz, w4);
+                    w5 = __builtin_fma(hf * (double)fdz, (double)fdz, w5);
+                }
+            }
+        }
+    }
+
+    double fx, fy, fz;
+    if (PREC == PREC_FP64) {
+        fx = lane_sum<TPP>((double)acc.fx);
+        fy = lane_sum<TPP>((double)acc.fy);
+        fz = lane_sum<TPP>((double)acc.fz);
+    } else {
+        fx = (double)lane_sum<TPP>((float)acc.fx);
+        fy = (double)lane_sum<TPP>((float)acc.fy);
+        fz = (double)lane_sum<TPP>((float)acc.fz);
+    }
+    if (ENERGY) {
+        ue = lane_sum<TPP>(ue);
+        w0 = lane_sum<TPP>(w0);
+        w1 = lane_sum<TPP>(w1);
+        w2 = lane_sum<TPP>(w2);
+        w3 = lane_sum<TPP>(w3);
+        w4 = lane_sum<TPP>(w4);
+        w5 = lane_sum<TPP>(w5);
+    }
+    if (lane != 0) return;
+
+    const bool finite = __builtin_isfinite(fx) && __builtin_isfinite(fy) && __builtin_isfinite(fz);
+    if (!finite) atomicOr(a.status, ST_NONFINITE);
+    if (ENERGY) {
+        a.u_out[q] = ue;
+        double *w = a.w_out + 6 * (size_t)q;
+        w[0] = w0; w[1] = w1; w[2] = w2; w[3] = w3; w[4] = w4; w[5] = w5;
+    }
+    if (MODE == MODE_EVAL) {
+        a.force[q] = make_double4(fx, fy, fz, 0.0);
+        return;
+    }
+    double4 v = a.vel[q];
+    const double hm = a.half_dt * v.w;
+    // second half kick of the current step: full-step velocity
+    v.x = __builtin_fma(hm, fx, v.x);
+    v.y = __builtin_fma(hm, fy, v.y);
+    v.z = __builtin_fma(hm, fz, v.z);
+    if (MODE == MODE_FINAL) {
+        a.vel[q] = v;
+        a.force[q] = make_double4(fx, fy, fz, 0.0);
+        return;
+    }
+    if (ENERGY) {
+        const double m = 1.0 / v.w;
+        a.ke_out[q] = 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+    }
+    // first half kick and drift of the next step
+    v.x = __builtin_fma(hm, fx, v.x);
+    v.y = __builtin_fma(hm, fy, v.y);
+    v.z = __builtin_fma(hm, fz, v.z);
+    double4 x = xi;
+    x.x = __builtin_fma(a.dt, v.x, x.x);
+    x.y = __builtin_fma(a.dt, v.y, x.y);
+    x.z = __builtin_fma(a.dt, v.z, x.z);
+    int4 im = a.img[q];
+    const int4 im0 = im;
+    wrap_coord(x.x, im.x, L0);
+    wrap_coord(x.y, im.y, L1);
+    wrap_coord(x.z, im.z, L2);
+    a.pos_out[q] = x;
+    a.vel[q] = v;
+    if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
+    const double4 b = a.xb[q];
+    const double ex = mi_rint(x.x - b.x, L0, iL0);
+    const double ey = mi_rint(x.y - b.y, L1, iL1);
+    const double ez = mi_rint(x.z - b.z, L2, iL2);
+    const bool exceed = r2_canon(ex, ey, ez) >= a.lim2;
+    const unsigned long long vote = __ballot(exceed);
+    if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1) atomicOr(a.rebuild_set, 1);
+}
+
+template <int PREC, int TPP, int MODE, bool ENERGY>
+static hipError_t launch_force_t(hipStream_t s, const ForceArgs &a, int block) {
+    size_t threads = (size_t)a.n * TPP;
+    int grid = (int)((threads + block - 1) / block);
+    if (grid < 1) grid = 1;
+    if (a.ntypes > 1)
+        hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, true>), dim3(grid), dim3(block), 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, false>), dim3(grid), dim3(block),
+                           0, s, a);
+    return hipGetLastError();
+}
+
+template <int PREC, int TPP>
+static hipError_t launch_force_m(hipStream_t s, const ForceArgs &a, int mode, bool energy,
+                                 int block) {
+    switch (mode) {
+        case MODE_EVAL:
+            return energy ? launch_force_t<PREC, TPP, MODE_EVAL, true>(s, a, block)
+                          : launch_force_t<PREC, TPP, MODE_EVAL, false>(s, a, block);
+        case MODE_FUSED:
+            return energy ? launch_force_t<PREC, TPP, MODE_FUSED, true>(s, a, block)
+                          : launch_force_t<PREC, TPP, MODE_FUSED, false>(s, a, block);
+        default:
+            return launch_force_t<PREC, TPP, MODE_FINAL, false>(s, a, block);
+    }
+}
+
+template <int PREC>
+static hipError_t launch_force_p(hipStream_t s, const ForceArgs &a, int tpp, int mode,
+                                 bool energy, int block) {
+    switch (tpp) {
+        case 1: return launch_force_m<PREC, 1>(s, a, mode, energy, block);
+        case 2: return launch_force_m<PREC, 2>(s, a, mode, energy, block);
+        case 4: return launch_force_m<PREC, 4>(s, a, mode, energy, block);
+        case 8: return launch_force_m<PREC, 8>(s, a, mode, energy, block);
+        case 16: return launch_force_m<PREC, 16>(s, a, mode, energy, block);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_force(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                        bool energy, int block) {
+    if (block < 64 || block > 256 || (block & 63)) return hipErrorInvalidValue;
+    return prec == PREC_MIXED ? launch_force_p<PREC_MIXED>(s, a, tpp, mode, energy, block)
+                              : launch_force_p<PREC_FP64>(s, a, tpp, mode, energy, block);
+}
+
+// ---------------------------------------------------------------- rebuild: cell binning
+
+// Cell coordinate of a scaled position, clamped into [0, nc - 1] (also for a NaN, which
+// fails the comparison and lands in cell 0).
+__device__ __forceinline__ int cell_coord(double f, int nc) {
+    return f > 0.0 ? (int)fmin(f, (double)(nc - 1)) : 0;
+}
+
+// Cell of each particle; the slot inside its cell comes from an integer atomic counter
+// (the order is made deterministic afterwards by k_cell_sort).
+__global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
+    if (*a.go == 0) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.n) return;
+    const double4 x = a.pos[q];
+    const int cx = cell_coord(x.x * a.inv_w[0], a.nc[0]);
+    const int cy = cell_coord(x.y * a.inv_w[1], a.nc[1]);
+    const int cz = cell_coord(x.z * a.inv_w[2], a.nc[2]);
+    int lin = (cx * a.nc[1] + cy) * a.nc[2] + cz;
+    int r = a.cell_rank[lin];
+    a.key[q] = r;
+    a.slot[q] = atomicAdd(&a.cell_count[r], 1);
+}
+
+// Exclusive scan of the cell counts into cell_start[0..ncell] (one workgroup of 1024
+// threads, each owning a contiguous chunk), then the counts are zeroed for the next build.
+__global__ void __launch_bounds__(1024) k_scan(const RebuildArgs a) {
+    if (*a.go == 0) return;
+    __shared__ int s_sum[1024];
+    const int T = blockDim.x;
+    const int t = threadIdx.x;
+    const int chunk = (a.ncell + T - 1) / T;
+    const int beg = t * chunk;
+    const int end = min(a.ncell, beg + chunk);
+    int sum = 0;
+    for (int c = beg; c < end; ++c) sum += a.cell_count[c];
+    s_sum[t] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the per-thread sums
+    for (int o = 1; o < T; o <<= 1) {
+        int v = t >= o ? s_sum[t - o] : 0;
+        __syncthreads();
+        s_sum[t] += v;
+        __syncthreads();
+    }
+    if (t == 0) a.st->entries = 0ull;
+    int run = s_sum[t] - sum;
+    for (int c = beg; c < end; ++c) {
+        int k = a.cell_count[c];
+        a.cell_start[c] = run;
+        a.cell_count[c] = 0;
+        run += k;
+    }
+    if (t == T - 1) a.cell_start[a.ncell] = s_sum[t];
+}
+
+__global__ void __launch_bounds__(256) k_scatter(const RebuildArgs a) {
+    if (*a.go == 0) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.n) return;
+    a.perm[a.cell_start[a.key[q]] + a.slot[q]] = q;
+}
+
+// Order each cell's members by their previous sorted index (a stable counting sort).
+// One workgroup of 64 lanes per cell; the rank of a member is the number of members with
+// a smaller index.
+__global__ void __launch_bounds__(64) k_cell_sort(const RebuildArgs a) {
+    if (*a.go == 0) return;
+    __shared__ int s_in[SORT_LDS];
+    const int c = blockIdx.x;
+    const int beg = a.cell_start[c];
+    const int m = a.cell_start[c + 1] - beg;
+    if (m <= 1) return;
+    if (m <= SORT_LDS) {
+        for (int t = threadIdx.x; t < m; t += blockDim.x) s_in[t] = a.perm[beg + t];
+        __syncthreads();
+        for (int t = threadIdx.x; t < m; t += blockDim.x) {
+            int v = s_in[t];
+            int rank = 0;
+            for (int u = 0; u < m; ++u) rank += s_in[u] < v;
+            a.perm[beg + rank] = v;
+        }
+    } else if (threadIdx.x == 0) {
+        // pathological occupancy: insertion sort in place by one lane
+        for (int t = 1; t < m; ++t) {
+            int v = a.perm[beg + t];
+            int u = t - 1;
+            while (u >= 0 && a.perm[beg + u] > v) {
+                a.perm[beg + u + 1] = a.perm[beg + u];
+                --u;
+            }
+            a.perm[beg + u + 1] = v;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_permute(const RebuildArgs a) {
+    if (*a.go == 0) return;
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.n) return;
+    int k = a.perm[q];
+    a.pos_scr[q] = a.pos[k];
+    a.vel_scr[q] = a.vel[k];
+    a.img_scr[q] = a.img[k];
+}
+
+// ---------------------------------------------------------------- rebuild: Verlet list
+
+// One workgroup per cell. The atoms of the cell's stencil (27 cells, or its distinct
+// cells when an axis has fewer than 3) are staged in LDS; NL_LANES lanes per particle of
+// the cell scan the staged atoms and append every j != i with r^2 < (r_cut + skin)^2.
+// Appends from the lanes of one particle are compacted with a wavefront ballot so that
+// the entry order (stencil cell, then index) is deterministic. The workgroup also copies
+// its particles' permuted state back into the main arrays and records the build positions.
+template <bool MULTI>
+__device__ __forceinline__ double rl2_of(const RebuildArgs &a, const double *s_rl2, int ti,
+                                         int tj) {
+    return MULTI ? s_rl2[ti * a.ntypes + tj] : a.single_rl2;
+}
+
+template <bool MULTI, bool STAGED>
+__device__ __forceinline__ int scan_stencil(const RebuildArgs &a, const double *s_pair,
+                                            const double4 *s_pos, const int *s_start,
+                                            const int *s_cnt, const int *s_off,
+                                            const double *s_shift, int ns, int q, double4 xi,
+                                            int lane, int gbase, int *rowbase_dummy) {
+    (void)rowbase_dummy;
+    const int ti = MULTI ? (int)xi.w : 0;
+    const unsigned long long gmask = ((1ull << NL_LANES) - 1ull) << gbase;
+    const int wl = threadIdx.x & 63;
+    const unsigned long long below = (1ull << wl) - 1ull;
+    int count = 0;
+    for (int c = 0; c < ns; ++c) {
+        const int m = s_cnt[c];
+        const int jbeg = s_start[c];
+        const int off = s_off[c];
+        const double sx = s_shift[3 * c], sy = s_shift[3 * c + 1], sz = s_shift[3 * c + 2];
+        for (int t0 = 0; t0 < m; t0 += NL_LANES) {
+            const int t = t0 + lane;
+            bool hit = false;
+            int j = 0;
+            if (t < m) {
+                j = jbeg + t;
+                const double4 xj = STAGED ? s_pos[off + t] : a.pos_scr[j];
+                double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+                if (a.canonical_mi) {
+                    dx = mi_branch(dx, a.L[0]);
+                    dy = mi_branch(dy, a.L[1]);
+                    dz = mi_branch(dz, a.L[2]);
+                } else {
+                    dx = dx + sx;  // adding 0.0 is exact
+                    dy = dy + sy;
+                    dz = dz + sz;
+                }
+                const double r2 = r2_canon(dx, dy, dz);
+                hit = (j != q) && (r2 < rl2_of<MULTI>(a, s_pair, ti, MULTI ? (int)xj.w : 0));
+            }
+            const unsigned long long bal = __ballot(hit) & gmask;
+            if (hit) {
+                const int k = count + __popcll(bal & below);
+                if (k < a.cap) a.nlist[nl_slot(q, k, a.npad, a.lshift)] = j;
+            }
+            count += __popcll(bal);
+        }
+    }
+    return count;
+}
+
+template <bool MULTI>
+__global__ void __launch_bounds__(NL_BLOCK) k_nlist(const RebuildArgs a) {
+    if (*a.go == 0) return;
+    __shared__ double4 s_pos[NL_LDS_ATOMS];
+    __shared__ int s_start[27], s_cnt[27], s_off[28];
+    __shared__ double s_shift[81];
+    __shared__ int s_ns;
+    __shared__ int s_max;
+    __shared__ unsigned long long s_entries;
+    __shared__ double s_pair[MULTI ? LJMD_MAX_TYPES_DEV * LJMD_MAX_TYPES_DEV : 1];
+    const int cell = xcd_remap(blockIdx.x, gridDim.x);
+    if (MULTI) {
+        int nt2 = a.ntypes * a.ntypes;
+        for (int t = threadIdx.x; t < nt2; t += blockDim.x) s_pair[t] = a.rl2_table[t];
+    }
+    if (threadIdx.x == 0) {
+        s_max = 0;
+        s_entries = 0ull;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->builds, 1ull);
+    if (threadIdx.x == 0) {
+        const int packed = a.cell_xyz[cell];
+        const int cxyz[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
+        int ns = 0;
+        int seen[27];
+        for (int ox = -1; ox <= 1; ++ox)
+            for (int oy = -1; oy <= 1; ++oy)
+                for (int oz = -1; oz <= 1; ++oz) {
+                    const int o[3] = {ox, oy, oz};
+                    int e[3];
+                    double sh[3];
+                    for (int d = 0; d < 3; ++d) {
+                        int v = cxyz[d] + o[d];
+                        sh[d] = 0.0;
+                        if (v < 0) { v += a.nc[d]; sh[d] = -a.L[d]; }
+                        else if (v >= a.nc[d]) { v -= a.nc[d]; sh[d] = a.L[d]; }
+                        e[d] = v;
+                    }
+                    const int lin = (e[0] * a.nc[1] + e[1]) * a.nc[2] + e[2];
+                    const int r = a.cell_rank[lin];
+                    bool dup = false;
+                    for (int u = 0; u < ns; ++u) dup |= (seen[u] == r);
+                    if (dup) continue;
+                    seen[ns] = r;
+                    s_start[ns] = a.cell_start[r];
+                    s_cnt[ns] = a.cell_start[r + 1] - a.cell_start[r];
+                    s_shift[3 * ns] = sh[0];
+                    s_shift[3 * ns + 1] = sh[1];
+                    s_shift[3 * ns + 2] = sh[2];
+                    ++ns;
+                }
+        int off = 0;
+        for (int u = 0; u < ns; ++u) {
+            s_off[u] = off;
+            off += s_cnt[u];
+        }
+        s_off[ns] = off;
+        s_ns = ns;
+    }
+    __syncthreads();
+    const int ns = s_ns;
+    const int total = s_off[ns];
+    const bool staged = total <= NL_LDS_ATOMS;
+    if (staged) {
+        for (int t = threadIdx.x; t < total; t += blockDim.x) {
+            int c = 0;
+            while (t >= s_off[c + 1]) ++c;
+            s_pos[t] = a.pos_scr[s_start[c] + (t - s_off[c])];
+        }
+    }
+    __syncthreads();
+
+    const int my_beg = a.cell_start[cell];
+    const int my_cnt = a.cell_start[cell + 1] - my_beg;
+    const int lane = threadIdx.x & (NL_LANES - 1);
+    const int group = threadIdx.x / NL_LANES;
+    const int ngroups = blockDim.x / NL_LANES;
+    const int gbase = (threadIdx.x & 63) & ~(NL_LANES - 1);
+    for (int p = group; p < my_cnt; p += ngroups) {
+        const int q = my_beg + p;
+        const double4 xi = a.pos_scr[q];
+        int count;
+        if (staged)
+            count = scan_stencil<MULTI, true>(a, s_pair, s_pos, s_start, s_cnt, s_off, s_shift,
+                                              ns, q, xi, lane, gbase, nullptr);
+        else
+            count = scan_stencil<MULTI, false>(a, s_pair, s_pos, s_start, s_cnt, s_off,
+                                               s_shift, ns, q, xi, lane, gbase, nullptr);
+        if (lane == 0) {
+            a.nl_count[q] = count;
+            if (count > a.cap) atomicOr(&a.st->status, ST_OVERFLOW);
+            atomicMax(&s_max, count);
+            atomicAdd(&s_entries, (unsigned long long)(count < a.cap ? count : a.cap));
+            // the permuted state becomes the main state; this is the new build point
+            a.pos[q] = xi;
+            a.xb[q] = xi;
+            a.vel[q] = a.vel_scr[q];
+            a.img[q] = a.img_scr[q];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_max > 0) {
+        atomicMax(&a.st->max_count, s_max);
+        atomicAdd(&a.st->entries, s_entries);
+    }
+}
+
+hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
+    const int b = 256;
+    const int g = (a.n + b - 1) / b;
+    hipLaunchKernelGGL(k_bin, dim3(g), dim3(b), 0, s, a);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(b), 0, s, a);
+    hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_permute, dim3(g), dim3(b), 0, s, a);
+    if (a.ntypes > 1)
+        hipLaunchKernelGGL(k_nlist<true>, dim3(a.ncell), dim3(NL_BLOCK), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_nlist<false>, dim3(a.ncell), dim3(NL_BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- reductions
+
+// Deterministic FP64 sums of U, W[6] and K: each workgroup adds a fixed strided subset in
+// a fixed order and tree-reduces it in LDS; one workgroup then reduces the partials the
+// same way. K is taken from ke[] when given, else from the stored velocities.
+__global__ void __launch_bounds__(RED_BLOCK) k_reduce_partials(const double *u, const double *w,
+                                                                const double *ke,
+                                                                const double4 *vel, int n,
+                                                                double *partials) {
+    __shared__ double s[RED_QUANT][RED_BLOCK];
+    double acc[RED_QUANT];
+    for (int c = 0; c < RED_QUANT; ++c) acc[c] = 0.0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        acc[0] += u[q];
+        for (int c = 0; c < 6; ++c) acc[1 + c] += w[6 * (size_t)q + c];
+        if (ke) {
+            acc[7] += ke[q];
+        } else {
+            const double4 v = vel[q];
+            const double m = 1.0 / v.w;
+            acc[7] += 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+        }
+    }
+    for (int c = 0; c < RED_QUANT; ++c) s[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int o = RED_BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int c = 0; c < RED_QUANT; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < RED_QUANT; ++c) partials[RED_QUANT * blockIdx.x + c] = s[c][0];
+}
+
+__global__ void __launch_bounds__(RED_BLOCK) k_reduce_final(const double *partials, int np,
+                                                             double *out) {
+    __shared__ double s[RED_QUANT][RED_BLOCK];
+    double acc[RED_QUANT];
+    for (int c = 0; c < RED_QUANT; ++c) acc[c] = 0.0;
+    for (int p = threadIdx.x; p < np; p += blockDim.x)
+        for (int c = 0; c < RED_QUANT; ++c) acc[c] += partials[RED_QUANT * p + c];
+    for (int c = 0; c < RED_QUANT; ++c) s[c][threadIdx.x] = acc[c];
+    __syncthreads();
+    for (int o = RED_BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            for (int c = 0; c < RED_QUANT; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < RED_QUANT; ++c) out[c] = s[c][0];
+}
+
+hipError_t launch_reduce(hipStream_t s, const double *u, const double *w, const double *ke,
+                         const double4 *vel, int n, double *partials, int nblocks_max,
+                         double *out) {
+    int g = (n + RED_BLOCK - 1) / RED_BLOCK;
+    if (g > nblocks_max) g = nblocks_max;
+    if (g < 1) g = 1;
+    hipLaunchKernelGGL(k_reduce_partials, dim3(g), dim3(RED_BLOCK), 0, s, u, w, ke, vel, n,
+                       partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_BLOCK), 0, s, partials, g, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- outputs in tag order
+
+__global__ void k_unsort_vec(const double4 *src, const int4 *img, int n, double *dst) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const double4 v = src[q];
+    const int t = img[q].w;
+    dst[3 * (size_t)t] = v.x;
+    dst[3 * (size_t)t + 1] = v.y;
+    dst[3 * (size_t)t + 2] = v.z;
+}
+
+__global__ void k_unsort_img(const int4 *img, int n, int *dst) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int4 v = img[q];
+    dst[3 * (size_t)v.w] = v.x;
+    dst[3 * (size_t)v.w + 1] = v.y;
+    dst[3 * (size_t)v.w + 2] = v.z;
+}
+
+__global__ void k_unsort_scalar(const double *src, int width, const int4 *img, int n,
+                                double *dst) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n) return;
+    const int t = img[q].w;
+    for (int c = 0; c < width; ++c) dst[(size_t)width * t + c] = src[(size_t)width * q + c];
+}
+
+hipError_t launch_unsort_vec(hipStream_t s, const double4 *src, const int4 *img, int n,
+                             double *dst) {
+    hipLaunchKernelGGL(k_unsort_vec, dim3((n + 255) / 256), dim3(256), 0, s, src, img, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unsort_img(hipStream_t s, const int4 *img, int n, int *dst) {
+    hipLaunchKernelGGL(k_unsort_img, dim3((n + 255) / 256), dim3(256), 0, s, img, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_unsort_scalar(hipStream_t s, const double *src, int width, const int4 *img,
+                                int n, double *dst) {
+    hipLaunchKernelGGL(k_unsort_scalar, dim3((n + 255) / 256), dim3(256), 0, s, src, width,
+                       img, n, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_status(DevStatus *st) {
+    if (threadIdx.x == 0) {
+        st->rebuild[0] = 0;
+        st->rebuild[1] = 0;
+        st->status = 0;
+        st->max_count = 0;
+        st->builds = 0ull;
+        st->entries = 0ull;
+        st->one = 1;
+        st->pad = 0;
+    }
+}
+
+hipError_t launch_fill_status(hipStream_t s, DevStatus *st) {
+    hipLaunchKernelGGL(k_fill_status, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+}  // namespace ljmd

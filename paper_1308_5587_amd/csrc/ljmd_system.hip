@@ -1,0 +1,1020 @@
+// Host side of libljmd: the C ABI of include/ljmd.h for one system.
+//
+// Step structure (velocity Verlet, NVE). With x(t), v(t) and F(t) on the device:
+//   kick-drift kernel        v += dt/2m F(t); x(t+1) = x + dt v, wrapped, written into the
+//                            other position buffer; raises the rebuild request if needed.
+//   gated rebuild kernels    bin -> scan -> scatter -> in-cell sort -> permute -> Verlet
+//                            build; every kernel returns at once unless the request is set.
+//   n-1 times: fused kernel  F(t+1) at x(t+1); v += dt/2m F (full step); v += dt/2m F;
+//                            x(t+2) into the other buffer; rebuild request; gated rebuild.
+//   final kernel             F(t+n); v += dt/2m F; F stored.
+// The repeating unit (fused kernel + gated rebuild) is captured once per starting buffer
+// into a HIP graph of `graph_steps` units. Host and device meet once per call, at the end,
+// to read the status word: on list overflow the call restores its starting state, grows
+// the list and runs again; on a non-finite force it restores and returns an error.
+#include "ljmd_internal.h"
+#include "../../include/ljmd.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+using namespace ljmd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return set_err(LJMD_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+#define CHK(expr)                   \
+    do {                            \
+        int r_ = (expr);            \
+        if (r_ != LJMD_OK) return r_; \
+    } while (0)
+
+uint64_t spread3(uint64_t v) {  // 10-bit value -> every third bit
+    uint64_t r = 0;
+    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+    return r;
+}
+
+struct TuneKey {
+    int prec, multi, nbucket;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(prec, multi, nbucket) < std::tie(o.prec, o.multi, o.nbucket);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;  // -> (tpp, block)
+
+}  // namespace
+
+struct ljmd_system {
+    ljmd_config cfg{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int n = 0, npad = 0;
+    double L[3]{}, invL[3]{};
+    int ntypes = 1;
+    std::vector<double> eps, sig, rc;
+    std::vector<char> is_set;
+    std::vector<int32_t> h_type;
+    std::vector<double> h_mass;
+    bool table_dirty = true;
+    double rl_max = 0.0;
+    PairCoef single{};
+    // device memory
+    std::vector<std::pair<void *, size_t>> allocs;
+    int64_t bytes = 0;
+    PairCoef *d_pair = nullptr;
+    double *d_rl2 = nullptr;
+    int nc[3]{0, 0, 0};
+    int ncell = 0, ncell_alloc = 0;
+    int *d_cell_rank = nullptr, *d_cell_xyz = nullptr, *d_cell_count = nullptr,
+        *d_cell_start = nullptr;
+    double4 *d_pos[2]{}, *d_pos_scr = nullptr, *d_vel = nullptr, *d_vel_scr = nullptr,
+            *d_force = nullptr, *d_xb = nullptr;
+    int4 *d_img = nullptr, *d_img_scr = nullptr;
+    int *d_key = nullptr, *d_slot = nullptr, *d_perm = nullptr;
+    int *d_count = nullptr, *d_nlist = nullptr;
+    int cap = 0;
+    size_t nlist_alloc = 0;
+    double *d_u = nullptr, *d_w = nullptr, *d_ke = nullptr, *d_partials = nullptr,
+           *d_red = nullptr;
+    double *d_stage = nullptr;  // n x 10 doubles of upload/download staging
+    double4 *d_snap_pos = nullptr, *d_snap_vel = nullptr;
+    int4 *d_snap_img = nullptr;
+    DevStatus *d_st = nullptr;
+    int cur = 0;
+    bool list_valid = false, force_valid = false;
+    int64_t steps = 0, overflow_retries = 0;
+    int tpp = 4, lshift = 2, block = 128;
+    int graph_steps = 64;
+    hipGraphExec_t graph[2]{nullptr, nullptr};
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    int64_t t_launches = 0;
+    double t_ms = 0.0;
+    int red_blocks = 1024;
+};
+
+namespace {
+
+int dalloc(ljmd_system *s, void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (s->cfg.alloc) {
+        *p = s->cfg.alloc(bytes, s->stream, s->cfg.alloc_ctx);
+        if (!*p) return set_err(LJMD_E_NOMEM, "allocator returned NULL for %zu bytes", bytes);
+    } else {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess || !*p)
+            return set_err(LJMD_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    s->allocs.emplace_back(*p, bytes);
+    s->bytes += (int64_t)bytes;
+    return LJMD_OK;
+}
+
+void dfree(ljmd_system *s, void *p) {
+    if (!p) return;
+    for (size_t k = 0; k < s->allocs.size(); ++k) {
+        if (s->allocs[k].first == p) {
+            size_t b = s->allocs[k].second;
+            if (s->cfg.free)
+                s->cfg.free(p, b, s->stream, s->cfg.alloc_ctx);
+            else
+                (void)hipFree(p);
+            s->bytes -= (int64_t)b;
+            s->allocs.erase(s->allocs.begin() + (long)k);
+            return;
+        }
+    }
+}
+
+template <class T>
+int dalloc_t(ljmd_system *s, T **p, size_t count) {
+    return dalloc(s, (void **)p, count * sizeof(T));
+}
+
+void drop_graphs(ljmd_system *s) {
+    for (int c = 0; c < 2; ++c)
+        if (s->graph[c]) {
+            (void)hipGraphExecDestroy(s->graph[c]);
+            s->graph[c] = nullptr;
+        }
+}
+
+int sync_status(ljmd_system *s, DevStatus *out) {
+    HIPCHK(hipMemcpyAsync(out, s->d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LJMD_OK;
+}
+
+int clear_status_bits(ljmd_system *s) {
+    // status and max_count words only; requests and counters stay
+    HIPCHK(hipMemsetAsync(&s->d_st->status, 0, 2 * sizeof(int), s->stream));
+    return LJMD_OK;
+}
+
+// ------------------------------------------------------------ pair table and cell grid
+
+int setup_table(ljmd_system *s) {
+    const int nt = s->ntypes;
+    for (int k = 0; k < nt * nt; ++k)
+        if (!s->is_set[k])
+            return set_err(LJMD_E_STATE, "pair (%d,%d) has not been set", k / nt, k % nt);
+    std::vector<PairCoef> tab(nt * nt);
+    std::vector<double> rl2(nt * nt);
+    double rl_max = 0.0;
+    for (int k = 0; k < nt * nt; ++k) {
+        PairCoef c{};
+        const double e = s->eps[k], sg = s->sig[k], r = s->rc[k];
+        if (r > 0.0) {
+            const double rl = r + s->cfg.skin;
+            c.rc2 = r * r;
+            c.rl2 = rl * rl;
+            rl_max = std::max(rl_max, rl);
+            const double s6 = sg * sg * sg * sg * sg * sg;
+            const double s12 = s6 * s6;
+            c.lj1 = 48.0 * e * s12;
+            c.lj2 = 24.0 * e * s6;
+            c.lj3 = 4.0 * e * s12;
+            c.lj4 = 4.0 * e * s6;
+            const double q2 = (sg * sg) / c.rc2;
+            const double q6 = q2 * q2 * q2;
+            c.shift = 4.0 * e * (q6 * q6 - q6);
+        }
+        tab[k] = c;
+        rl2[k] = c.rl2;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (rl_max > 0.5 * s->L[a])
+            return set_err(LJMD_E_BOX, "r_cut + skin = %g exceeds half the box edge %g", rl_max,
+                           s->L[a]);
+    s->rl_max = rl_max;
+    s->single = tab[0];
+    HIPCHK(hipMemcpyAsync(s->d_pair, tab.data(), sizeof(PairCoef) * nt * nt,
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_rl2, rl2.data(), sizeof(double) * nt * nt, hipMemcpyHostToDevice,
+                          s->stream));
+    // cell grid: width >= the largest list radius (a relative margin keeps it strictly
+    // larger, so rounding in the binning can never hide a pair)
+    int nc[3];
+    for (int a = 0; a < 3; ++a) {
+        double r = rl_max > 0.0 ? rl_max * (1.0 + 1e-12) : s->L[a] / 3.0;
+        long v = (long)std::floor(s->L[a] / r);
+        if (v < 1) v = 1;
+        if (v > 1023) v = 1023;
+        nc[a] = (int)v;
+    }
+    const int ncell = nc[0] * nc[1] * nc[2];
+    if (ncell > s->ncell_alloc) {
+        dfree(s, s->d_cell_rank);
+        dfree(s, s->d_cell_xyz);
+        dfree(s, s->d_cell_count);
+        dfree(s, s->d_cell_start);
+        CHK(dalloc_t(s, &s->d_cell_rank, ncell));
+        CHK(dalloc_t(s, &s->d_cell_xyz, ncell));
+        CHK(dalloc_t(s, &s->d_cell_count, ncell));
+        CHK(dalloc_t(s, &s->d_cell_start, ncell + 1));
+        s->ncell_alloc = ncell;
+    }
+    // Morton order of the cells
+    std::vector<std::pair<uint64_t, int>> mort(ncell);
+    for (int x = 0; x < nc[0]; ++x)
+        for (int y = 0; y < nc[1]; ++y)
+            for (int z = 0; z < nc[2]; ++z) {
+                const int lin = (x * nc[1] + y) * nc[2] + z;
+                mort[lin] = {spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), lin};
+            }
+    std::sort(mort.begin(), mort.end());
+    std::vector<int> rank(ncell), xyz(ncell);
+    for (int r = 0; r < ncell; ++r) {
+        const int lin = mort[r].second;
+        rank[lin] = r;
+        const int z = lin % nc[2], y = (lin / nc[2]) % nc[1], x = lin / (nc[1] * nc[2]);
+        xyz[r] = x | (y << 10) | (z << 20);
+    }
+    HIPCHK(hipMemcpyAsync(s->d_cell_rank, rank.data(), sizeof(int) * ncell,
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_cell_xyz, xyz.data(), sizeof(int) * ncell, hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipMemsetAsync(s->d_cell_count, 0, sizeof(int) * ncell, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));  // host vectors go out of scope
+    for (int a = 0; a < 3; ++a) s->nc[a] = nc[a];
+    s->ncell = ncell;
+    s->table_dirty = false;
+    s->list_valid = false;
+    s->force_valid = false;
+    drop_graphs(s);
+    return LJMD_OK;
+}
+
+int ensure_list_alloc(ljmd_system *s, int cap) {
+    // a multiple of 16 keeps every tiled-layout slot of k < cap inside cap * npad
+    cap = std::max(16, (cap + 15) & ~15);
+    const size_t need = (size_t)cap * (size_t)s->npad;
+    if (need > s->nlist_alloc) {
+        dfree(s, s->d_nlist);
+        s->d_nlist = nullptr;
+        s->nlist_alloc = 0;
+        CHK(dalloc_t(s, &s->d_nlist, need));
+        s->nlist_alloc = need;
+    }
+    if (cap != s->cap) drop_graphs(s);
+    s->cap = cap;
+    return LJMD_OK;
+}
+
+int round_cap(double v) {
+    int c = (int)std::ceil(v);
+    c = (c + 15) & ~15;
+    return std::max(c, 16);
+}
+
+// ------------------------------------------------------------ argument blocks
+
+RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
+    RebuildArgs a{};
+    a.go = go;
+    a.rl2_table = s->d_rl2;
+    a.pos = s->d_pos[cur];
+    a.pos_scr = s->d_pos_scr;
+    a.vel = s->d_vel;
+    a.vel_scr = s->d_vel_scr;
+    a.img = s->d_img;
+    a.img_scr = s->d_img_scr;
+    a.xb = s->d_xb;
+    a.key = s->d_key;
+    a.slot = s->d_slot;
+    a.perm = s->d_perm;
+    a.cell_count = s->d_cell_count;
+    a.cell_start = s->d_cell_start;
+    a.cell_rank = s->d_cell_rank;
+    a.cell_xyz = s->d_cell_xyz;
+    a.nl_count = s->d_count;
+    a.nlist = s->d_nlist;
+    a.pair = s->d_pair;
+    a.st = s->d_st;
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = s->L[d];
+        a.invL[d] = s->invL[d];
+        a.inv_w[d] = (double)s->nc[d] / s->L[d];
+        a.nc[d] = s->nc[d];
+    }
+    a.single_rl2 = s->single.rl2;
+    a.ncell = s->ncell;
+    a.n = s->n;
+    a.npad = s->npad;
+    a.cap = s->cap;
+    a.lshift = s->lshift;
+    a.ntypes = s->ntypes;
+    a.canonical_mi = (s->nc[0] < 3 || s->nc[1] < 3 || s->nc[2] < 3) ? 1 : 0;
+    return a;
+}
+
+ForceArgs force_args(ljmd_system *s, int cur) {
+    ForceArgs a{};
+    a.pos_in = s->d_pos[cur];
+    a.pos_out = s->d_pos[cur ^ 1];
+    a.vel = s->d_vel;
+    a.img = s->d_img;
+    a.xb = s->d_xb;
+    a.force = s->d_force;
+    a.nl_count = s->d_count;
+    a.nlist = s->d_nlist;
+    a.u_out = s->d_u;
+    a.w_out = s->d_w;
+    a.ke_out = s->d_ke;
+    a.pair = s->d_pair;
+    a.rebuild_set = &s->d_st->rebuild[cur ^ 1];
+    a.rebuild_clear = &s->d_st->rebuild[cur];
+    a.status = &s->d_st->status;
+    a.single = s->single;
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = s->L[d];
+        a.invL[d] = s->invL[d];
+    }
+    a.dt = s->cfg.dt;
+    a.half_dt = 0.5 * s->cfg.dt;
+    const double lim = 0.5 * s->cfg.skin;
+    a.lim2 = lim * lim;
+    a.n = s->n;
+    a.npad = s->npad;
+    a.cap = s->cap;
+    a.lshift = s->lshift;
+    a.ntypes = s->ntypes;
+    return a;
+}
+
+KickDriftArgs kick_drift_args(ljmd_system *s, int cur) {
+    KickDriftArgs a{};
+    a.pos_in = s->d_pos[cur];
+    a.pos_out = s->d_pos[cur ^ 1];
+    a.vel = s->d_vel;
+    a.img = s->d_img;
+    a.xb = s->d_xb;
+    a.force = s->d_force;
+    a.rebuild_set = &s->d_st->rebuild[cur ^ 1];
+    a.rebuild_clear = &s->d_st->rebuild[cur];
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = s->L[d];
+        a.invL[d] = s->invL[d];
+    }
+    a.dt = s->cfg.dt;
+    a.half_dt = 0.5 * s->cfg.dt;
+    const double lim = 0.5 * s->cfg.skin;
+    a.lim2 = lim * lim;
+    a.n = s->n;
+    return a;
+}
+
+int launch_chk(hipError_t e, const char *what) {
+    if (e != hipSuccess) return set_err(LJMD_E_DEVICE, "launch of %s: %s", what, hipGetErrorString(e));
+    return LJMD_OK;
+}
+
+// unconditional rebuild at the current positions
+int enqueue_forced_rebuild(ljmd_system *s) {
+    RebuildArgs a = rebuild_args(s, &s->d_st->one, s->cur);
+    return launch_chk(launch_rebuild(s->stream, a), "rebuild");
+}
+
+int precision(ljmd_system *s) { return s->cfg.precision == LJMD_MIXED ? PREC_MIXED : PREC_FP64; }
+
+int enqueue_eval(ljmd_system *s, bool energy) {
+    ForceArgs a = force_args(s, s->cur);
+    return launch_chk(launch_force(s->stream, a, precision(s), s->tpp, MODE_EVAL, energy, s->block),
+                      "force eval");
+}
+
+// Build the list at the current positions, growing the capacity until it fits.
+int build_list(ljmd_system *s) {
+    if (s->cap == 0) {
+        int cap = s->cfg.nlist_capacity;
+        if (cap <= 0) {
+            // expected neighbours in the list radius at the mean density, with headroom
+            const double vol = s->L[0] * s->L[1] * s->L[2];
+            const double rho = s->n / vol;
+            const double rl = s->rl_max;
+            const double nbar = rho * 4.18879020478639 * rl * rl * rl;
+            cap = round_cap(1.3 * nbar + 24.0);
+            cap = std::min(cap, std::max(16, ((s->n + 15) & ~15)));
+        }
+        CHK(ensure_list_alloc(s, cap));
+    }
+    for (int attempt = 0; attempt < 8; ++attempt) {
+        CHK(clear_status_bits(s));
+        // a fresh list makes any pending rebuild request moot
+        HIPCHK(hipMemsetAsync(s->d_st->rebuild, 0, 2 * sizeof(int), s->stream));
+        CHK(enqueue_forced_rebuild(s));
+        DevStatus st{};
+        CHK(sync_status(s, &st));
+        if (!(st.status & ST_OVERFLOW)) {
+            s->list_valid = true;
+            s->force_valid = false;
+            return LJMD_OK;
+        }
+        CHK(ensure_list_alloc(s, round_cap(1.25 * st.max_count + 8)));
+        s->overflow_retries += 1;
+    }
+    return set_err(LJMD_E_DEVICE, "neighbour list did not fit after repeated growth");
+}
+
+int tune(ljmd_system *s);
+
+int ensure_ready(ljmd_system *s) {
+    if (s->table_dirty) CHK(setup_table(s));
+    if (s->tpp == 0 || s->block == 0) CHK(tune(s));
+    if (!s->list_valid) CHK(build_list(s));
+    if (!s->force_valid) {
+        CHK(clear_status_bits(s));
+        CHK(enqueue_eval(s, false));
+        DevStatus st{};
+        CHK(sync_status(s, &st));
+        if (st.status & ST_NONFINITE)
+            return set_err(LJMD_E_NONFINITE, "non-finite force at the current positions");
+        s->force_valid = true;
+    }
+    return LJMD_OK;
+}
+
+// ------------------------------------------------------------ autotuner
+
+double time_evals(ljmd_system *s, int reps) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return 1e30;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return 1e30;
+    }
+    double best = 1e30;
+    if (enqueue_eval(s, false) == LJMD_OK) {  // warm
+        (void)hipEventRecord(e0, s->stream);
+        bool ok = true;
+        for (int r = 0; r < reps && ok; ++r) ok = enqueue_eval(s, false) == LJMD_OK;
+        (void)hipEventRecord(e1, s->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) best = ms / reps;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+}
+
+// Choose lanes per particle and workgroup size for the force kernel by timing the
+// force evaluation on this system. Results are kept per (precision, multi-type, size
+// bucket) for the life of the process.
+int tune(ljmd_system *s) {
+    const int want_tpp = s->cfg.threads_per_particle;
+    const int want_block = s->cfg.block_size;
+    int nb = 0;
+    for (int v = s->n; v > 1; v >>= 1) ++nb;
+    TuneKey key{precision(s), s->ntypes > 1 ? 1 : 0, nb};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            s->tpp = want_tpp ? want_tpp : it->second.first;
+            s->block = want_block ? want_block : it->second.second;
+            for (s->lshift = 0; (1 << s->lshift) < s->tpp; ++s->lshift) {}
+            s->list_valid = false;
+            return LJMD_OK;
+        }
+    }
+    const int tpps[] = {1, 2, 4, 8, 16};
+    const int blocks[] = {64, 128, 256};
+    double best = 1e30;
+    int bt = 4, bb = 128;
+    for (int t : tpps) {
+        if (want_tpp && t != want_tpp) continue;
+        s->tpp = t;
+        for (s->lshift = 0; (1 << s->lshift) < t; ++s->lshift) {}
+        s->block = 128;
+        s->list_valid = false;
+        CHK(build_list(s));
+        for (int b : blocks) {
+            if (want_block && b != want_block) continue;
+            s->block = b;
+            const double ms = time_evals(s, 5);
+            if (ms < best) {
+                best = ms;
+                bt = t;
+                bb = b;
+            }
+        }
+    }
+    s->tpp = bt;
+    s->block = bb;
+    for (s->lshift = 0; (1 << s->lshift) < bt; ++s->lshift) {}
+    s->list_valid = false;
+    s->force_valid = false;
+    drop_graphs(s);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {bt, bb};
+    return LJMD_OK;
+}
+
+// ------------------------------------------------------------ stepping
+
+int enqueue_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_index) {
+    ForceArgs fa = force_args(s, cur);
+    if (timed) HIPCHK(hipEventRecord(s->ev[2 * ev_index], st));
+    CHK(launch_chk(launch_force(st, fa, precision(s), s->tpp, MODE_FUSED, false, s->block),
+                   "fused step"));
+    if (timed) HIPCHK(hipEventRecord(s->ev[2 * ev_index + 1], st));
+    RebuildArgs ra = rebuild_args(s, &s->d_st->rebuild[cur ^ 1], cur ^ 1);
+    return launch_chk(launch_rebuild(st, ra), "rebuild");
+}
+
+int capture_graph(ljmd_system *s, int cur) {
+    if (!s->cap_stream) HIPCHK(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+    int c = cur;
+    int rc = LJMD_OK;
+    for (int u = 0; u < s->graph_steps && rc == LJMD_OK; ++u) {
+        rc = enqueue_unit(s, s->cap_stream, c, false, 0);
+        c ^= 1;
+    }
+    hipError_t e = hipStreamEndCapture(s->cap_stream, &g);
+    if (rc != LJMD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return set_err(LJMD_E_DEVICE, "graph capture: %s", hipGetErrorString(e));
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return set_err(LJMD_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    s->graph[cur] = ex;
+    return LJMD_OK;
+}
+
+int ensure_events(ljmd_system *s, int64_t count) {
+    while ((int64_t)s->ev.size() < 2 * count) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        s->ev.push_back(e);
+    }
+    return LJMD_OK;
+}
+
+int snapshot(ljmd_system *s) {
+    const size_t n = (size_t)s->n;
+    HIPCHK(hipMemcpyAsync(s->d_snap_pos, s->d_pos[s->cur], n * sizeof(double4),
+                          hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_snap_vel, s->d_vel, n * sizeof(double4), hipMemcpyDeviceToDevice,
+                          s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_snap_img, s->d_img, n * sizeof(int4), hipMemcpyDeviceToDevice,
+                          s->stream));
+    return LJMD_OK;
+}
+
+int restore(ljmd_system *s, int cur0) {
+    const size_t n = (size_t)s->n;
+    s->cur = cur0;
+    HIPCHK(hipMemcpyAsync(s->d_pos[s->cur], s->d_snap_pos, n * sizeof(double4),
+                          hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_vel, s->d_snap_vel, n * sizeof(double4), hipMemcpyDeviceToDevice,
+                          s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_img, s->d_snap_img, n * sizeof(int4), hipMemcpyDeviceToDevice,
+                          s->stream));
+    s->list_valid = false;
+    s->force_valid = false;
+    return LJMD_OK;
+}
+
+// One attempt at nsteps >= 1 steps from a ready state. Returns OK, or sets *overflow.
+int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
+    *overflow = false;
+    *nonfinite = false;
+    CHK(clear_status_bits(s));
+    // first half step from the stored forces
+    {
+        KickDriftArgs ka = kick_drift_args(s, s->cur);
+        CHK(launch_chk(launch_kick_drift(s->stream, ka), "kick-drift"));
+        s->cur ^= 1;
+        RebuildArgs ra = rebuild_args(s, &s->d_st->rebuild[s->cur], s->cur);
+        CHK(launch_chk(launch_rebuild(s->stream, ra), "rebuild"));
+    }
+    int64_t units = nsteps - 1;
+    const bool use_graph = s->graph_steps > 0 && !s->timing;
+    if (s->timing) CHK(ensure_events(s, units));
+    int64_t done = 0;
+    while (done < units) {
+        if (use_graph && units - done >= s->graph_steps) {
+            if (!s->graph[s->cur]) CHK(capture_graph(s, s->cur));
+            HIPCHK(hipGraphLaunch(s->graph[s->cur], s->stream));
+            done += s->graph_steps;  // graph_steps is even: cur is unchanged
+        } else {
+            CHK(enqueue_unit(s, s->stream, s->cur, s->timing, (int)done));
+            s->cur ^= 1;
+            done += 1;
+        }
+    }
+    ForceArgs fa = force_args(s, s->cur);
+    CHK(launch_chk(launch_force(s->stream, fa, precision(s), s->tpp, MODE_FINAL, false, s->block),
+                   "final"));
+    DevStatus st{};
+    CHK(sync_status(s, &st));
+    if (s->timing) {
+        for (int64_t u = 0; u < units; ++u) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, s->ev[2 * u], s->ev[2 * u + 1]));
+            s->t_ms += ms;
+        }
+        s->t_launches += units;
+    }
+    *overflow = (st.status & ST_OVERFLOW) != 0;
+    *nonfinite = (st.status & ST_NONFINITE) != 0;
+    return LJMD_OK;
+}
+
+bool finite_array(const double *p, size_t k) {
+    for (size_t i = 0; i < k; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char *ljmd_last_error(void) { return g_err.c_str(); }
+
+const char *ljmd_version(void) { return "ljmd 0.1 (gfx950)"; }
+
+int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, const double *vel,
+                       const int32_t *type, const double *mass, ljmd_system **out) {
+    if (out) *out = nullptr;
+    if (!cfg || !pos || !vel || !type || !out) return set_err(LJMD_E_INVAL, "null argument");
+    if (n < 1 || n > (int64_t)(1 << 26)) return set_err(LJMD_E_INVAL, "n = %lld out of range", (long long)n);
+    if (cfg->ntypes < 1 || cfg->ntypes > LJMD_MAX_TYPES)
+        return set_err(LJMD_E_INVAL, "ntypes = %d out of range [1, %d]", cfg->ntypes, LJMD_MAX_TYPES);
+    if (!(cfg->dt > 0.0) || !std::isfinite(cfg->dt)) return set_err(LJMD_E_INVAL, "dt must be > 0");
+    if (!(cfg->skin >= 0.0) || !std::isfinite(cfg->skin)) return set_err(LJMD_E_INVAL, "skin must be >= 0");
+    for (int a = 0; a < 3; ++a)
+        if (!(cfg->box[a] > 0.0) || !std::isfinite(cfg->box[a]))
+            return set_err(LJMD_E_INVAL, "box edge %d must be finite and > 0", a);
+    if (cfg->precision != LJMD_FP64 && cfg->precision != LJMD_MIXED)
+        return set_err(LJMD_E_INVAL, "unknown precision %d", cfg->precision);
+    const int tpp = cfg->threads_per_particle;
+    if (tpp != 0 && tpp != 1 && tpp != 2 && tpp != 4 && tpp != 8 && tpp != 16)
+        return set_err(LJMD_E_INVAL, "threads_per_particle must be 0, 1, 2, 4, 8 or 16");
+    if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 256 || cfg->block_size % 64))
+        return set_err(LJMD_E_INVAL, "block_size must be 0 or 64, 128, 192, 256");
+    if (cfg->graph_steps != 0 && cfg->graph_steps != -1 && (cfg->graph_steps < 2 || cfg->graph_steps % 2))
+        return set_err(LJMD_E_INVAL, "graph_steps must be 0, -1 or an even number >= 2");
+    if (cfg->nlist_capacity < 0) return set_err(LJMD_E_INVAL, "nlist_capacity must be >= 0");
+    if (!!cfg->alloc != !!cfg->free) return set_err(LJMD_E_INVAL, "alloc and free must be given together");
+    if (!finite_array(pos, 3 * (size_t)n) || !finite_array(vel, 3 * (size_t)n))
+        return set_err(LJMD_E_INVAL, "non-finite position or velocity");
+    for (int64_t i = 0; i < n; ++i)
+        if (type[i] < 0 || type[i] >= cfg->ntypes)
+            return set_err(LJMD_E_INVAL, "type[%lld] = %d out of range", (long long)i, type[i]);
+    if (mass)
+        for (int64_t i = 0; i < n; ++i)
+            if (!(mass[i] > 0.0) || !std::isfinite(mass[i]))
+                return set_err(LJMD_E_INVAL, "mass[%lld] must be > 0", (long long)i);
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev < 1) return set_err(LJMD_E_DEVICE, "no HIP device available");
+
+    ljmd_system *s = new (std::nothrow) ljmd_system();
+    if (!s) return set_err(LJMD_E_NOMEM, "host allocation failed");
+    s->cfg = *cfg;
+    (void)hipGetDevice(&s->device);
+    s->stream = (hipStream_t)cfg->stream;
+    s->n = (int)n;
+    s->npad = (int)((n + 63) & ~63LL);
+    for (int a = 0; a < 3; ++a) {
+        s->L[a] = cfg->box[a];
+        s->invL[a] = 1.0 / cfg->box[a];
+    }
+    s->ntypes = cfg->ntypes;
+    const int nt2 = s->ntypes * s->ntypes;
+    s->eps.assign(nt2, 0.0);
+    s->sig.assign(nt2, 1.0);
+    s->rc.assign(nt2, 0.0);
+    s->is_set.assign(nt2, 0);
+    s->h_type.assign(type, type + n);
+    if (mass) s->h_mass.assign(mass, mass + n);
+    s->tpp = tpp;
+    s->block = cfg->block_size;
+    if (s->tpp) for (s->lshift = 0; (1 << s->lshift) < s->tpp; ++s->lshift) {}
+    s->graph_steps = cfg->graph_steps == 0 ? 64 : (cfg->graph_steps < 0 ? 0 : cfg->graph_steps);
+
+    const size_t N = (size_t)n;
+    int rc = LJMD_OK;
+    rc = rc ? rc : dalloc_t(s, &s->d_pair, nt2);
+    rc = rc ? rc : dalloc_t(s, &s->d_rl2, nt2);
+    rc = rc ? rc : dalloc_t(s, &s->d_pos[0], N);
+    rc = rc ? rc : dalloc_t(s, &s->d_pos[1], N);
+    rc = rc ? rc : dalloc_t(s, &s->d_pos_scr, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_vel, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_vel_scr, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_force, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_xb, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_img, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_img_scr, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_key, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_slot, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_perm, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_count, (size_t)s->npad);
+    rc = rc ? rc : dalloc_t(s, &s->d_u, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_w, 6 * N);
+    rc = rc ? rc : dalloc_t(s, &s->d_ke, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_partials, (size_t)RED_QUANT * s->red_blocks);
+    rc = rc ? rc : dalloc_t(s, &s->d_red, (size_t)RED_QUANT);
+    rc = rc ? rc : dalloc_t(s, &s->d_stage, 10 * N);
+    rc = rc ? rc : dalloc_t(s, &s->d_snap_pos, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_snap_vel, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_snap_img, N);
+    rc = rc ? rc : dalloc_t(s, &s->d_st, 1);
+    if (rc != LJMD_OK) {
+        ljmd_system_destroy(s);
+        return rc;
+    }
+    // upload through the staging area: pos (3N) | vel (3N) | mass (N) | type (N ints)
+    double *st_pos = s->d_stage, *st_vel = s->d_stage + 3 * N, *st_mass = s->d_stage + 6 * N;
+    int *st_type = (int *)(s->d_stage + 7 * N);
+    auto fail = [&](int code) {
+        ljmd_system_destroy(s);
+        return code;
+    };
+    if (hipMemcpyAsync(st_pos, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(st_vel, vel, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(st_type, type, N * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        (mass && hipMemcpyAsync(st_mass, mass, N * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess))
+        return fail(set_err(LJMD_E_DEVICE, "host-to-device copy failed"));
+    if (launch_upload(s->stream, st_pos, st_vel, st_type, mass ? st_mass : nullptr, s->d_pos[0],
+                      s->d_vel, s->d_img, s->n, s->L, 1, 1, nullptr) != hipSuccess ||
+        launch_fill_status(s->stream, s->d_st) != hipSuccess)
+        return fail(set_err(LJMD_E_DEVICE, "upload kernel failed"));
+    if (hipStreamSynchronize(s->stream) != hipSuccess)
+        return fail(set_err(LJMD_E_DEVICE, "synchronisation after upload failed"));
+    s->cur = 0;
+    *out = s;
+    return LJMD_OK;
+}
+
+void ljmd_system_destroy(ljmd_system *s) {
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    drop_graphs(s);
+    for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
+    delete s;
+}
+
+int ljmd_pair_lj_set(ljmd_system *s, int32_t a, int32_t b, double epsilon, double sigma, double r_cut) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (a < 0 || b < 0 || a >= s->ntypes || b >= s->ntypes)
+        return set_err(LJMD_E_INVAL, "type pair (%d,%d) out of range", a, b);
+    if (!std::isfinite(epsilon) || !(sigma > 0.0) || !std::isfinite(sigma) || !(r_cut >= 0.0) ||
+        !std::isfinite(r_cut))
+        return set_err(LJMD_E_INVAL, "need finite epsilon, sigma > 0, r_cut >= 0");
+    const int k1 = a * s->ntypes + b, k2 = b * s->ntypes + a;
+    s->eps[k1] = s->eps[k2] = epsilon;
+    s->sig[k1] = s->sig[k2] = sigma;
+    s->rc[k1] = s->rc[k2] = r_cut;
+    s->is_set[k1] = s->is_set[k2] = 1;
+    s->table_dirty = true;
+    s->list_valid = false;
+    s->force_valid = false;
+    return LJMD_OK;
+}
+
+int ljmd_step(ljmd_system *s, int64_t nsteps) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (nsteps < 0) return set_err(LJMD_E_INVAL, "nsteps must be >= 0");
+    CHK(ensure_ready(s));
+    const int64_t seg = 1000000;
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int64_t k = std::min(left, seg);
+        const int cur0 = s->cur;
+        CHK(snapshot(s));
+        for (int attempt = 0;; ++attempt) {
+            bool over = false, nonfin = false;
+            CHK(run_steps(s, k, &over, &nonfin));
+            if (nonfin) {
+                CHK(restore(s, cur0));
+                return set_err(LJMD_E_NONFINITE, "non-finite force during the step; state restored");
+            }
+            if (!over) break;
+            if (attempt >= 8) return set_err(LJMD_E_DEVICE, "list overflow persisted after growth");
+            DevStatus st{};
+            CHK(sync_status(s, &st));
+            CHK(restore(s, cur0));
+            CHK(ensure_list_alloc(s, round_cap(1.25 * st.max_count + 8)));
+            s->overflow_retries += 1;
+            CHK(ensure_ready(s));
+        }
+        s->steps += k;
+        left -= k;
+    }
+    return LJMD_OK;
+}
+
+static int fetch_vec(ljmd_system *s, const double4 *src, double *out) {
+    CHK(launch_chk(launch_unsort_vec(s->stream, src, s->d_img, s->n, s->d_stage), "unsort"));
+    HIPCHK(hipMemcpyAsync(out, s->d_stage, 3 * (size_t)s->n * sizeof(double), hipMemcpyDeviceToHost,
+                          s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LJMD_OK;
+}
+
+int ljmd_get_forces(ljmd_system *s, double *out) {
+    if (!s || !out) return set_err(LJMD_E_INVAL, "null argument");
+    CHK(ensure_ready(s));
+    return fetch_vec(s, s->d_force, out);
+}
+
+static int eval_thermo(ljmd_system *s, double red[RED_QUANT]) {
+    CHK(ensure_ready(s));
+    CHK(enqueue_eval(s, true));
+    CHK(launch_chk(launch_reduce(s->stream, s->d_u, s->d_w, nullptr, s->d_vel, s->n, s->d_partials,
+                                 s->red_blocks, s->d_red),
+                   "reduce"));
+    HIPCHK(hipMemcpyAsync(red, s->d_red, RED_QUANT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LJMD_OK;
+}
+
+int ljmd_get_energy(ljmd_system *s, double *potential, double *kinetic) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    double red[RED_QUANT];
+    CHK(eval_thermo(s, red));
+    if (potential) *potential = red[0];
+    if (kinetic) *kinetic = red[7];
+    return LJMD_OK;
+}
+
+int ljmd_get_virial(ljmd_system *s, double *out6) {
+    if (!s || !out6) return set_err(LJMD_E_INVAL, "null argument");
+    double red[RED_QUANT];
+    CHK(eval_thermo(s, red));
+    for (int c = 0; c < 6; ++c) out6[c] = red[1 + c];
+    return LJMD_OK;
+}
+
+int ljmd_get_per_particle(ljmd_system *s, double *u, double *w) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    CHK(ensure_ready(s));
+    CHK(enqueue_eval(s, true));
+    const size_t N = (size_t)s->n;
+    if (u) {
+        CHK(launch_chk(launch_unsort_scalar(s->stream, s->d_u, 1, s->d_img, s->n, s->d_stage), "unsort"));
+        HIPCHK(hipMemcpyAsync(u, s->d_stage, N * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    if (w) {
+        CHK(launch_chk(launch_unsort_scalar(s->stream, s->d_w, 6, s->d_img, s->n, s->d_stage), "unsort"));
+        HIPCHK(hipMemcpyAsync(w, s->d_stage, 6 * N * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return LJMD_OK;
+}
+
+int ljmd_get_state(ljmd_system *s, double *pos, double *vel, int32_t *img, int64_t *step) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (pos) CHK(fetch_vec(s, s->d_pos[s->cur], pos));
+    if (vel) CHK(fetch_vec(s, s->d_vel, vel));
+    if (img) {
+        CHK(launch_chk(launch_unsort_img(s->stream, s->d_img, s->n, (int *)s->d_stage), "unsort"));
+        HIPCHK(hipMemcpyAsync(img, s->d_stage, 3 * (size_t)s->n * sizeof(int), hipMemcpyDeviceToHost,
+                              s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    if (step) *step = s->steps;
+    return LJMD_OK;
+}
+
+int ljmd_set_state(ljmd_system *s, const double *pos, const double *vel, const int32_t *img,
+                   const int64_t *step) {
+    if (!s || !pos || !vel) return set_err(LJMD_E_INVAL, "positions and velocities are required");
+    const size_t N = (size_t)s->n;
+    if (!finite_array(pos, 3 * N) || !finite_array(vel, 3 * N))
+        return set_err(LJMD_E_INVAL, "non-finite position or velocity");
+    double *st_pos = s->d_stage, *st_vel = s->d_stage + 3 * N, *st_mass = s->d_stage + 6 * N;
+    int *st_type = (int *)(s->d_stage + 7 * N);
+    int *st_img = (int *)(s->d_stage + 8 * N);
+    HIPCHK(hipMemcpyAsync(st_pos, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(st_vel, vel, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(st_type, s->h_type.data(), N * sizeof(int), hipMemcpyHostToDevice, s->stream));
+    if (!s->h_mass.empty())
+        HIPCHK(hipMemcpyAsync(st_mass, s->h_mass.data(), N * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    if (img) HIPCHK(hipMemcpyAsync(st_img, img, 3 * N * sizeof(int), hipMemcpyHostToDevice, s->stream));
+    s->cur = 0;
+    CHK(launch_chk(launch_upload(s->stream, st_pos, st_vel, st_type, s->h_mass.empty() ? nullptr : st_mass,
+                                 s->d_pos[0], s->d_vel, s->d_img, s->n, s->L, 1, 1, img ? st_img : nullptr),
+                   "upload"));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (step) s->steps = *step;
+    s->list_valid = false;
+    s->force_valid = false;
+    return LJMD_OK;
+}
+
+int ljmd_get_neighbor_pairs(ljmd_system *s, int64_t *count, int32_t *pairs, double *build_pos) {
+    if (!s || !count) return set_err(LJMD_E_INVAL, "null argument");
+    CHK(ensure_ready(s));
+    const size_t N = (size_t)s->n;
+    std::vector<int> cnt(N), tag(N);
+    std::vector<int4> img(N);
+    std::vector<int> nl((size_t)s->cap * s->npad);
+    HIPCHK(hipMemcpyAsync(cnt.data(), s->d_count, N * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(img.data(), s->d_img, N * sizeof(int4), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(nl.data(), s->d_nlist, nl.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (size_t q = 0; q < N; ++q) tag[q] = img[q].w;
+    std::vector<std::pair<int, int>> pr;
+    for (size_t q = 0; q < N; ++q) {
+        const int c = std::min(cnt[q], s->cap);
+        for (int k = 0; k < c; ++k) {
+            const size_t slot = ((((size_t)(k >> s->lshift)) * (size_t)s->npad + q) << s->lshift) |
+                                (size_t)(k & ((1 << s->lshift) - 1));
+            const int j = nl[slot];
+            const int a = tag[q], b = tag[j];
+            if (a < b) pr.emplace_back(a, b);
+        }
+    }
+    std::sort(pr.begin(), pr.end());
+    *count = (int64_t)pr.size();
+    if (pairs)
+        for (size_t p = 0; p < pr.size(); ++p) {
+            pairs[2 * p] = pr[p].first;
+            pairs[2 * p + 1] = pr[p].second;
+        }
+    if (build_pos) CHK(fetch_vec(s, s->d_xb, build_pos));
+    return LJMD_OK;
+}
+
+int ljmd_get_stats(ljmd_system *s, ljmd_stats *out) {
+    if (!s || !out) return set_err(LJMD_E_INVAL, "null argument");
+    DevStatus st{};
+    CHK(sync_status(s, &st));
+    std::memset(out, 0, sizeof *out);
+    out->steps = s->steps;
+    out->rebuilds = (int64_t)st.builds;
+    out->max_neighbors = st.max_count;
+    out->nlist_capacity = s->cap;
+    out->overflow_retries = s->overflow_retries;
+    out->threads_per_particle = s->tpp;
+    out->block_size = s->block;
+    for (int a = 0; a < 3; ++a) out->ncell[a] = s->nc[a];
+    out->graph_steps = s->graph_steps;
+    out->device_bytes = s->bytes;
+    out->list_entries = (int64_t)st.entries;
+    return LJMD_OK;
+}
+
+int ljmd_set_kernel_timing(ljmd_system *s, int32_t on) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    s->timing = on != 0;
+    s->t_launches = 0;
+    s->t_ms = 0.0;
+    return LJMD_OK;
+}
+
+int ljmd_kernel_time(ljmd_system *s, int64_t *launches, double *total_ms) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (launches) *launches = s->t_launches;
+    if (total_ms) *total_ms = s->t_ms;
+    return LJMD_OK;
+}
+
+}  // extern "C"

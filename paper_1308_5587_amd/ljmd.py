@@ -1,0 +1,287 @@
+"""Python binding of libljmd (include/ljmd.h): argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of libljmd.so. PyTorch, when it has a
+GPU, only supplies device memory (its caching allocator, through the allocator callbacks
+of ljmd_config) and the stream the library enqueues on. If the shared library is missing
+this module raises instead of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libljmd.so")
+
+LJMD_OK = 0
+LJMD_E_INVAL = -1
+LJMD_E_NOMEM = -2
+LJMD_E_DEVICE = -3
+LJMD_E_BOX = -4
+LJMD_E_NONFINITE = -5
+LJMD_E_STATE = -6
+LJMD_E_CAPACITY = -7
+LJMD_FP64 = 0
+LJMD_MIXED = 1
+LJMD_MAX_TYPES = 16
+
+_ERRNAMES = {LJMD_E_INVAL: "INVAL", LJMD_E_NOMEM: "NOMEM", LJMD_E_DEVICE: "DEVICE",
+             LJMD_E_BOX: "BOX", LJMD_E_NONFINITE: "NONFINITE", LJMD_E_STATE: "STATE",
+             LJMD_E_CAPACITY: "CAPACITY"}
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class LjmdConfig(C.Structure):
+    _fields_ = [("box", C.c_double * 3), ("ntypes", C.c_int32), ("dt", C.c_double),
+                ("skin", C.c_double), ("precision", C.c_int32), ("nlist_capacity", C.c_int32),
+                ("threads_per_particle", C.c_int32), ("block_size", C.c_int32),
+                ("graph_steps", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+class LjmdStats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("rebuilds", C.c_int64), ("max_neighbors", C.c_int32),
+                ("nlist_capacity", C.c_int32), ("overflow_retries", C.c_int64),
+                ("threads_per_particle", C.c_int32), ("block_size", C.c_int32),
+                ("ncell", C.c_int32 * 3), ("graph_steps", C.c_int32),
+                ("device_bytes", C.c_int64), ("list_entries", C.c_int64)]
+
+
+class LjmdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"LJMD_E_{_ERRNAMES.get(code, code)} ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+EXPORTED = [
+    "ljmd_system_create", "ljmd_system_destroy", "ljmd_pair_lj_set", "ljmd_step",
+    "ljmd_get_forces", "ljmd_get_energy", "ljmd_get_virial", "ljmd_get_per_particle",
+    "ljmd_get_state", "ljmd_set_state", "ljmd_get_neighbor_pairs", "ljmd_get_stats",
+    "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_last_error", "ljmd_version",
+]
+
+
+def load(path: str = LIB_PATH):
+    """Load libljmd.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_1308_5587_amd.build_lib.build()")
+    lib = C.CDLL(path)
+    vp, dp, ip, lp = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64)
+    sig = {
+        "ljmd_system_create": ([C.POINTER(LjmdConfig), C.c_int64, dp, dp, ip, dp, C.POINTER(vp)], C.c_int),
+        "ljmd_system_destroy": ([vp], None),
+        "ljmd_pair_lj_set": ([vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double], C.c_int),
+        "ljmd_step": ([vp, C.c_int64], C.c_int),
+        "ljmd_get_forces": ([vp, dp], C.c_int),
+        "ljmd_get_energy": ([vp, dp, dp], C.c_int),
+        "ljmd_get_virial": ([vp, dp], C.c_int),
+        "ljmd_get_per_particle": ([vp, dp, dp], C.c_int),
+        "ljmd_get_state": ([vp, dp, dp, ip, lp], C.c_int),
+        "ljmd_set_state": ([vp, dp, dp, ip, lp], C.c_int),
+        "ljmd_get_neighbor_pairs": ([vp, lp, ip, dp], C.c_int),
+        "ljmd_get_stats": ([vp, C.POINTER(LjmdStats)], C.c_int),
+        "ljmd_set_kernel_timing": ([vp, C.c_int32], C.c_int),
+        "ljmd_kernel_time": ([vp, lp, dp], C.c_int),
+        "ljmd_last_error": ([], C.c_char_p),
+        "ljmd_version": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != LJMD_OK:
+        raise LjmdError(rc, _lib.ljmd_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _torch_cuda():
+    try:
+        import torch
+    except Exception:
+        return None
+    try:
+        if torch.cuda.is_available():
+            return torch
+    except Exception:
+        return None
+    return None
+
+
+class _TorchAllocator:
+    """ljmd allocator callbacks backed by torch's caching allocator."""
+
+    def __init__(self, torch, device):
+        self.torch = torch
+        self.device = device
+
+        def _alloc(nbytes, stream, ctx):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                              stream or 0))
+            except Exception:
+                return None
+
+        def _free(ptr, nbytes, stream, ctx):
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+
+class System:
+    """One LJ system on the GPU (ljmd_system). Arrays in and out are numpy, tag order."""
+
+    def __init__(self, box, pos, vel, types, ntypes=None, pairs=(), dt=0.005, skin=0.4,
+                 precision="fp64", mass=None, nlist_capacity=0, threads_per_particle=0,
+                 block_size=0, graph_steps=0, stream=None, torch_memory=True):
+        lib = load()
+        self._lib = lib
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+        typ = np.ascontiguousarray(types, dtype=np.int32).reshape(-1)
+        self.n = pos.shape[0]
+        if ntypes is None:
+            ntypes = int(typ.max()) + 1 if self.n else 1
+        cfg = LjmdConfig()
+        for a in range(3):
+            cfg.box[a] = float(np.asarray(box, dtype=np.float64).reshape(3)[a])
+        cfg.ntypes = int(ntypes)
+        cfg.dt = float(dt)
+        cfg.skin = float(skin)
+        cfg.precision = {"fp64": LJMD_FP64, "mixed": LJMD_MIXED}[precision]
+        cfg.nlist_capacity = int(nlist_capacity)
+        cfg.threads_per_particle = int(threads_per_particle)
+        cfg.block_size = int(block_size)
+        cfg.graph_steps = int(graph_steps)
+        self._alloc = None
+        torch = _torch_cuda()
+        if torch is not None:
+            dev = torch.cuda.current_device()
+            if stream is None:
+                stream = torch.cuda.current_stream(dev).cuda_stream
+            if torch_memory:
+                self._alloc = _TorchAllocator(torch, dev)
+                cfg.alloc = self._alloc.alloc
+                cfg.free = self._alloc.free
+        cfg.stream = stream if stream else None
+        self._cfg = cfg
+        m = None if mass is None else np.ascontiguousarray(mass, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib.ljmd_system_create(C.byref(cfg), self.n, _dp(pos), _dp(vel), _ip(typ),
+                                      None if m is None else _dp(m), C.byref(h)))
+        self._h = h
+        for (a, b, eps, sig, rc) in pairs:
+            self.pair_lj_set(a, b, eps, sig, rc)
+
+    @classmethod
+    def from_spec(cls, spec, **kw):
+        return cls(spec.box, spec.pos, spec.vel, spec.type, spec.ntypes, spec.pairs, **kw)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.ljmd_system_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pair_lj_set(self, a, b, epsilon, sigma, r_cut):
+        _check(self._lib.ljmd_pair_lj_set(self._h, int(a), int(b), float(epsilon), float(sigma),
+                                          float(r_cut)))
+
+    def step(self, nsteps=1):
+        _check(self._lib.ljmd_step(self._h, int(nsteps)))
+
+    def forces(self):
+        out = np.empty((self.n, 3))
+        _check(self._lib.ljmd_get_forces(self._h, _dp(out)))
+        return out
+
+    def energy(self):
+        u = np.zeros(1)
+        k = np.zeros(1)
+        _check(self._lib.ljmd_get_energy(self._h, _dp(u), _dp(k)))
+        return float(u[0]), float(k[0])
+
+    def virial(self):
+        out = np.empty(6)
+        _check(self._lib.ljmd_get_virial(self._h, _dp(out)))
+        return out
+
+    def per_particle(self):
+        u = np.empty(self.n)
+        w = np.empty((self.n, 6))
+        _check(self._lib.ljmd_get_per_particle(self._h, _dp(u), _dp(w)))
+        return u, w
+
+    def state(self):
+        pos = np.empty((self.n, 3))
+        vel = np.empty((self.n, 3))
+        img = np.empty((self.n, 3), dtype=np.int32)
+        st = C.c_int64(0)
+        _check(self._lib.ljmd_get_state(self._h, _dp(pos), _dp(vel), _ip(img), C.byref(st)))
+        return pos, vel, img, int(st.value)
+
+    def set_state(self, pos, vel, img=None, step=None):
+        pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+        vel = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1, 3)
+        im = None if img is None else np.ascontiguousarray(img, dtype=np.int32).reshape(-1, 3)
+        st = None if step is None else C.byref(C.c_int64(int(step)))
+        _check(self._lib.ljmd_set_state(self._h, _dp(pos), _dp(vel),
+                                        None if im is None else _ip(im), st))
+
+    def neighbor_pairs(self):
+        cnt = C.c_int64(0)
+        _check(self._lib.ljmd_get_neighbor_pairs(self._h, C.byref(cnt), None, None))
+        out = np.empty((cnt.value, 2), dtype=np.int32)
+        xb = np.empty((self.n, 3))
+        _check(self._lib.ljmd_get_neighbor_pairs(self._h, C.byref(cnt), _ip(out), _dp(xb)))
+        return out, xb
+
+    def stats(self):
+        st = LjmdStats()
+        _check(self._lib.ljmd_get_stats(self._h, C.byref(st)))
+        return {f: (list(getattr(st, f)) if f == "ncell" else getattr(st, f))
+                for f, _ in LjmdStats._fields_}
+
+    def set_kernel_timing(self, on=True):
+        _check(self._lib.ljmd_set_kernel_timing(self._h, 1 if on else 0))
+
+    def kernel_time(self):
+        n = C.c_int64(0)
+        ms = C.c_double(0.0)
+        _check(self._lib.ljmd_kernel_time(self._h, C.byref(n), C.byref(ms)))
+        return int(n.value), float(ms.value)
+
+
+def version():
+    return load().ljmd_version().decode()

@@ -1,0 +1,301 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU FP64 oracle on identical
+seeded inputs.
+
+Bars: neighbour lists bit-exact as sorted tag-pair sets; FP64 forces, energies and virials
+within 1e-10 max-norm relative; the mixed form within 1e-5 max-norm relative. Cases span
+several cell tiles and ragged particle counts, boxes with fewer than three cells per axis, a
+two-type mixture with per-pair cutoffs, and the full 1,048,576-particle fluid in the launch
+configuration the benchmark uses."""
+
+import numpy as np
+import pytest
+
+from paper_1308_5587_amd import inputs as gen
+from parity import max_norm_rel, print_case, scalar_rel, sort_pairs, unwrapped
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ljmd_mod():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    from paper_1308_5587_amd import ljmd
+
+    ljmd.load()  # raises if the HIP library is missing
+    return ljmd
+
+
+def _pair(o_sys, g_sys, fp64=True, ff_tol=None):
+    tol = ff_tol if ff_tol is not None else (1e-10 if fp64 else 1e-5)
+    Fo = o_sys.forces()
+    Fg = g_sys.forces()
+    assert max_norm_rel(Fg, Fo) <= tol, max_norm_rel(Fg, Fo)
+    Uo, Ko = o_sys.energy()
+    Ug, Kg = g_sys.energy()
+    assert scalar_rel(Ug, Uo) <= tol, (Ug, Uo)
+    assert scalar_rel(Kg, Ko) <= 1e-12, (Kg, Ko)
+    Wo = o_sys.virial()
+    Wg = g_sys.virial()
+    assert max_norm_rel(Wg, Wo) <= tol, (Wg, Wo)
+    uo, wo = o_sys.per_particle()
+    ug, wg = g_sys.per_particle()
+    assert max_norm_rel(ug, uo) <= tol
+    assert max_norm_rel(wg, wo) <= tol
+
+
+def _list_parity(o_sys, g_sys, pos):
+    po, xbo = o_sys.pairs()
+    pg, xbg = g_sys.neighbor_pairs()
+    assert np.array_equal(xbg, xbo)
+    assert np.array_equal(xbg, pos)
+    a = sort_pairs(po)
+    b = sort_pairs(pg)
+    assert a.shape == b.shape, (a.shape, b.shape)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("n,seed", [(4000, 1), (1, 3), (2, 4), (37, 5), (1001, 6), (6859, 7)])
+def test_fp64_list_and_forces(ljmd_mod, oracle_mod, n, seed):
+    print_case(f"fp64 list+forces n={n} seed={seed}")
+    rho = 0.8442 if n >= 500 else 0.05
+    s = gen.make_lj_fluid(n, rho=rho, T=1.2, seed=seed)
+    if s.box[0] < 2 * 2.9:  # tiny counts: keep the box legal for r_cut + skin
+        L = 6.0
+        s = gen.LJSystemSpec(np.array([L] * 3), np.random.default_rng(seed).uniform(0, L, (n, 3)),
+                             s.vel, s.type, 1, s.pairs)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s)
+    _list_parity(o, g, s.pos)
+    _pair(o, g)
+
+
+def test_small_box_fewer_than_three_cells(ljmd_mod, oracle_mod):
+    # L = 6.58 < 3 (r_cut + skin): two cells per axis, the stencil repeats cells
+    print_case("fp64 small box 2 cells per axis")
+    s = gen.make_lj_fluid(256, rho=256 / 6.58 ** 3, T=1.0, seed=11)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s)
+    assert g.stats()["ncell"] == [2, 2, 2]
+    _list_parity(o, g, s.pos)
+    _pair(o, g)
+
+
+def test_orthorhombic_box(ljmd_mod, oracle_mod):
+    print_case("fp64 orthorhombic")
+    rng = np.random.default_rng(12)
+    box = np.array([9.0, 12.5, 17.25])
+    n = 1500
+    side = 12
+    sites = np.stack(np.meshgrid(np.arange(side), np.arange(side), np.arange(side),
+                                 indexing="ij"), -1).reshape(-1, 3)[:n]
+    pos = (sites + 0.5) / side * box + rng.uniform(-0.05, 0.05, (n, 3))
+    vel = rng.normal(0, 1, (n, 3))
+    pairs = [(0, 0, 1.0, 0.7, 2.5)]
+    o = oracle_mod.OracleSystem(box, pos, vel, np.zeros(n, np.int32), 1, pairs)
+    g = ljmd_mod.System(box, pos, vel, np.zeros(n, np.int32), 1, pairs)
+    _list_parity(o, g, pos)
+    _pair(o, g)
+
+
+def test_ka_mixture(ljmd_mod, oracle_mod):
+    print_case("fp64 KA mixture n=8000")
+    s = gen.make_ka_mixture(8000, seed=2)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s)
+    _list_parity(o, g, s.pos)
+    _pair(o, g)
+
+
+@pytest.mark.parametrize("tpp", [1, 2, 4, 8, 16])
+def test_every_lane_count(ljmd_mod, oracle_mod, tpp):
+    print_case(f"fp64 tpp={tpp}")
+    s = gen.make_lj_fluid(3000, seed=21)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s, threads_per_particle=tpp, block_size=64 * (1 + tpp % 4))
+    _list_parity(o, g, s.pos)
+    _pair(o, g)
+
+
+def test_mixed_forces(ljmd_mod, oracle_mod):
+    print_case("mixed forces n=4000 and KA")
+    s = gen.make_lj_fluid(4000, seed=1)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s, precision="mixed")
+    _list_parity(o, g, s.pos)
+    _pair(o, g, fp64=False)
+    k = gen.make_ka_mixture(8000, seed=4)
+    _pair(oracle_mod.OracleSystem.from_spec(k), ljmd_mod.System.from_spec(k, precision="mixed"),
+          fp64=False)
+
+
+def test_one_and_hundred_steps(ljmd_mod, oracle_mod):
+    print_case("fp64 1 and 100 steps n=4000")
+    s = gen.make_lj_fluid(4000, seed=1)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s)
+    o.step(1)
+    g.step(1)
+    po, vo, io, _ = o.state()
+    pg, vg, ig, st = g.state()
+    assert st == 1
+    assert np.abs(unwrapped(pg, ig, s.box) - unwrapped(po, io, s.box)).max() < 1e-12
+    assert np.abs(vg - vo).max() < 1e-12
+    _pair(o, g)
+    o.step(99)
+    g.step(99)
+    po, vo, io, _ = o.state()
+    pg, vg, ig, st = g.state()
+    assert st == 100
+    assert np.abs(unwrapped(pg, ig, s.box) - unwrapped(po, io, s.box)).max() < 1e-8
+    assert np.abs(vg - vo).max() < 1e-8
+    assert max_norm_rel(g.forces(), o.forces()) < 1e-8
+    assert g.stats()["rebuilds"] >= 5
+
+
+def test_mixed_steps_track_fp64(ljmd_mod, oracle_mod):
+    print_case("mixed 1 and 100 steps")
+    s = gen.make_lj_fluid(4000, seed=1)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s, precision="mixed")
+    o.step(1)
+    g.step(1)
+    assert max_norm_rel(g.forces(), o.forces()) < 1e-5
+    o.step(99)
+    g.step(99)
+    po, _, io, _ = o.state()
+    pg, _, ig, _ = g.state()
+    assert np.abs(unwrapped(pg, ig, s.box) - unwrapped(po, io, s.box)).max() < 1e-3
+
+
+def test_six_particle_parameter_sets(ljmd_mod):
+    """The paper's pair-force unit-test recipe on the GPU path."""
+    from sixparticle import calculator, load_fixture
+
+    print_case("six particle")
+    box, pos, params = load_fixture()
+    g = ljmd_mod.System(box, pos, np.zeros((6, 3)), np.zeros(6, np.int32), 1,
+                        [(0, 0, *params[0])])
+    for (eps, sig, rc) in params:
+        g.pair_lj_set(0, 0, eps, sig, rc)
+        F, U, W, u_i, w_i = calculator(box, pos, eps, sig, rc)
+        assert max_norm_rel(g.forces(), F) < 1e-12
+        assert scalar_rel(g.energy()[0], U) < 1e-12
+        assert max_norm_rel(g.virial(), W) < 1e-12
+        ug, wg = g.per_particle()
+        assert max_norm_rel(ug, u_i) < 1e-12 and max_norm_rel(wg, w_i) < 1e-12
+
+
+def test_free_flight_and_images(ljmd_mod):
+    print_case("free flight")
+    rng = np.random.default_rng(4)
+    n = 500
+    box = np.array([7.0, 8.0, 9.0])
+    pos = rng.uniform(0, 1, (n, 3)) * box
+    vel = rng.normal(0, 30.0, (n, 3))
+    g = ljmd_mod.System(box, pos, vel, np.zeros(n, np.int32), 1, [(0, 0, 0.0, 1.0, 2.5)])
+    g.step(300)
+    x, v, img, st = g.state()
+    assert np.array_equal(v, vel)
+    assert np.all(x >= 0) and np.all(x < box)
+    assert np.abs(unwrapped(x, img, box) - (pos + 300 * 0.005 * vel)).max() < 1e-9
+    assert np.abs(img).max() >= 1
+
+
+def test_determinism_bitwise(ljmd_mod):
+    print_case("determinism")
+    s = gen.make_lj_fluid(20000, seed=8)
+    a = ljmd_mod.System.from_spec(s, threads_per_particle=4, block_size=128)
+    b = ljmd_mod.System.from_spec(s, threads_per_particle=4, block_size=128)
+    a.step(200)
+    b.step(200)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    assert np.array_equal(a.forces(), b.forces())
+    assert a.energy() == b.energy()
+
+
+def test_graph_blocks_match_direct_launches(ljmd_mod):
+    print_case("graph vs direct")
+    s = gen.make_lj_fluid(5000, seed=9)
+    a = ljmd_mod.System.from_spec(s, threads_per_particle=2, block_size=128, graph_steps=8)
+    b = ljmd_mod.System.from_spec(s, threads_per_particle=2, block_size=128, graph_steps=-1)
+    for k in (1, 17, 40, 2):
+        a.step(k)
+        b.step(k)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+
+
+def test_overflow_recovery(ljmd_mod):
+    print_case("overflow recovery")
+    s = gen.make_lj_fluid(4000, seed=10)
+    a = ljmd_mod.System.from_spec(s, threads_per_particle=4, block_size=128)
+    b = ljmd_mod.System.from_spec(s, threads_per_particle=4, block_size=128, nlist_capacity=16)
+    a.step(50)
+    b.step(50)
+    assert b.stats()["overflow_retries"] >= 1
+    pa, va, ia, _ = a.state()
+    pb, vb, ib, _ = b.state()
+    assert np.abs(unwrapped(pa, ia, s.box) - unwrapped(pb, ib, s.box)).max() < 1e-10
+    assert np.abs(va - vb).max() < 1e-10
+
+
+def test_checkpoint_resume(ljmd_mod):
+    print_case("checkpoint resume")
+    s = gen.make_lj_fluid(3000, seed=13)
+    a = ljmd_mod.System.from_spec(s)
+    a.step(30)
+    pos, vel, img, st = a.state()
+    b = ljmd_mod.System.from_spec(s)
+    b.set_state(pos, vel, img, st)
+    a.set_state(pos, vel, img, st)  # same forced rebuild on both
+    a.step(20)
+    b.step(20)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+
+
+def test_error_paths(ljmd_mod):
+    print_case("error paths")
+    E = ljmd_mod
+    # box too small for r_cut + skin
+    g = E.System(np.array([5.0] * 3), np.ones((2, 3)), np.zeros((2, 3)), np.zeros(2, np.int32), 1,
+                 [(0, 0, 1.0, 1.0, 2.5)])
+    with pytest.raises(E.LjmdError) as e:
+        g.step(1)
+    assert e.value.code == E.LJMD_E_BOX
+    # unset pair
+    g = E.System(np.array([9.0] * 3), np.ones((2, 3)), np.zeros((2, 3)), np.array([0, 1], np.int32), 2,
+                 [(0, 0, 1.0, 1.0, 2.5)])
+    with pytest.raises(E.LjmdError) as e:
+        g.forces()
+    assert e.value.code == E.LJMD_E_STATE
+    # overlap: non-finite force
+    g = E.System(np.array([9.0] * 3), np.ones((2, 3)), np.zeros((2, 3)), np.zeros(2, np.int32), 1,
+                 [(0, 0, 1.0, 1.0, 2.5)])
+    with pytest.raises(E.LjmdError) as e:
+        g.step(1)
+    assert e.value.code == E.LJMD_E_NONFINITE
+
+
+def test_full_size_fp64_and_mixed(ljmd_mod, oracle_mod):
+    """N = 1,048,576 at density 0.8442 in the benchmark's launch configuration (autotuned
+    lanes and workgroup, graph blocks): the whole list and all forces against the oracle."""
+    print_case("full size N=1048576")
+    s = gen.make_lj_fluid(1_048_576, rho=0.8442, T=1.2, seed=1)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s)
+    _list_parity(o, g, s.pos)
+    assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
+    Uo, _ = o.energy()
+    assert scalar_rel(g.energy()[0], Uo) <= 1e-10
+    assert max_norm_rel(g.virial(), o.virial()) <= 1e-10
+    m = ljmd_mod.System.from_spec(s, precision="mixed")
+    assert max_norm_rel(m.forces(), o.forces()) <= 1e-5
+    assert max_norm_rel(m.virial(), o.virial()) <= 1e-5
+    # two steps on both paths
+    o.step(2)
+    g.step(2)
+    assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
