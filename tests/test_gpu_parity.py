@@ -77,6 +77,7 @@ def test_small_box_fewer_than_three_cells(ljmd_mod, oracle_mod):
     s = gen.make_lj_fluid(256, rho=256 / 6.58 ** 3, T=1.0, seed=11)
     o = oracle_mod.OracleSystem.from_spec(s)
     g = ljmd_mod.System.from_spec(s)
+    g.step(0)  # lists and cells are set up lazily
     assert g.stats()["ncell"] == [2, 2, 2]
     _list_parity(o, g, s.pos)
     _pair(o, g)
