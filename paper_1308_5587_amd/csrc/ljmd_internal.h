@@ -38,12 +38,12 @@ enum { MODE_EVAL = 0, MODE_FUSED = 1, MODE_FINAL = 2 };
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };
 
 constexpr int LJMD_MAX_TYPES_DEV = 16; // equals LJMD_MAX_TYPES of the public header
-constexpr int NL_LDS_ATOMS = 1024;   // staged stencil atoms per build workgroup (32 KiB)
-constexpr int NL_BLOCK = 128;        // build workgroup size
-constexpr int NL_LANES = 4;          // lanes per particle in the build
 constexpr int RED_BLOCK = 256;       // reduction workgroup size
 constexpr int RED_QUANT = 8;         // U, W[6], K
 constexpr int SORT_LDS = 1024;       // in-cell sort capacity per workgroup
+constexpr int SCAN_TILE = 8192;      // counts per LDS tile of the scan (multiple of 1024)
+constexpr int NL_GRID = 8192;        // build wavefronts (grid-stride over cells)
+constexpr int FORCE_UNROLL = 4;      // list entries in flight per lane in the force kernel
 
 // Arguments of the force kernel family (by value).
 struct ForceArgs {

@@ -78,8 +78,13 @@ __device__ __forceinline__ void wrap_coord(double &x, int &im, double L) {
     }
 }
 
+// List slot of entry k of particle q with 2^ls lanes per particle: lanes own chunks of 4
+// consecutive entries, lane l holds chunks l, l + 2^ls, ...; for chunk index c the lanes
+// of consecutive particles are adjacent, so a wavefront reads 64 x 16 contiguous bytes.
 __device__ __forceinline__ size_t nl_slot(int q, int k, int npad, int ls) {
-    return ((((size_t)(k >> ls)) * (size_t)npad + (size_t)q) << ls) | (size_t)(k & ((1 << ls) - 1));
+    const size_t c = (size_t)(k >> (2 + ls));
+    const size_t l = (size_t)((k >> 2) & ((1 << ls) - 1));
+    return ((((c * (size_t)npad + (size_t)q) << ls) + l) << 2) | (size_t)(k & 3);
 }
 
 // ---------------------------------------------------------------- upload (create / set_state)
@@ -197,6 +202,57 @@ struct Acc<PREC_MIXED> {
     float fx = 0, fy = 0, fz = 0;
 };
 
+// One pair inside the cutoff: add the LJ force on i (and, with ENERGY, half the pair
+// energy and virial) for the displacement d = x_j - x_i with r2 = |d|^2.
+template <int PREC, bool ENERGY>
+__device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double dy, double dz,
+                                          double r2, Acc<PREC> &acc, double &ue, double &w0,
+                                          double &w1, double &w2, double &w3, double &w4,
+                                          double &w5) {
+    if (PREC == PREC_FP64) {
+        const double r2i = rcp64(r2);
+        const double r6i = r2i * r2i * r2i;
+        const double ff = r2i * r6i * __builtin_fma(c.lj1, r6i, -c.lj2);
+        // force on i is ff * (x_i - x_j) = -ff * d
+        acc.fx = __builtin_fma(-ff, dx, acc.fx);
+        acc.fy = __builtin_fma(-ff, dy, acc.fy);
+        acc.fz = __builtin_fma(-ff, dz, acc.fz);
+        if (ENERGY) {
+            ue += 0.5 * (r6i * __builtin_fma(c.lj3, r6i, -c.lj4) - c.shift);
+            const double hf = 0.5 * ff;
+            w0 = __builtin_fma(hf * dx, dx, w0);
+            w1 = __builtin_fma(hf * dx, dy, w1);
+            w2 = __builtin_fma(hf * dx, dz, w2);
+            w3 = __builtin_fma(hf * dy, dy, w3);
+            w4 = __builtin_fma(hf * dy, dz, w4);
+            w5 = __builtin_fma(hf * dz, dz, w5);
+        }
+    } else {
+        // FP32 pair arithmetic on the exactly formed FP64 displacement
+        const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
+        const float fr2 = (float)r2;
+        const float r2i = __builtin_amdgcn_rcpf(fr2);
+        const float r6i = r2i * r2i * r2i;
+        const float l1 = (float)c.lj1, l2 = (float)c.lj2;
+        const float ff = r2i * r6i * __builtin_fmaf(l1, r6i, -l2);
+        acc.fx = __builtin_fmaf(-ff, fdx, acc.fx);
+        acc.fy = __builtin_fmaf(-ff, fdy, acc.fy);
+        acc.fz = __builtin_fmaf(-ff, fdz, acc.fz);
+        if (ENERGY) {
+            const float l3 = (float)c.lj3, l4 = (float)c.lj4;
+            const float up = r6i * __builtin_fmaf(l3, r6i, -l4);
+            ue += 0.5 * ((double)up - c.shift);
+            const double hf = 0.5 * (double)ff;
+            w0 = __builtin_fma(hf * (double)fdx, (double)fdx, w0);
+            w1 = __builtin_fma(hf * (double)fdx, (double)fdy, w1);
+            w2 = __builtin_fma(hf * (double)fdx, (double)fdz, w2);
+            w3 = __builtin_fma(hf * (double)fdy, (double)fdy, w3);
+            w4 = __builtin_fma(hf * (double)fdy, (double)fdz, w4);
+            w5 = __builtin_fma(hf * (double)fdz, (double)fdz, w5);
+        }
+    }
+}
+
 // TPP lanes per particle stride through its list; forces are reduced across the lanes
 // with wavefront shuffles; lane 0 then finishes the particle according to MODE.
 template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI>
@@ -221,62 +277,49 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs a) {
     const double L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
     const double iL0 = a.invL[0], iL1 = a.invL[1], iL2 = a.invL[2];
 
+    // The integration state of the particle does not depend on the pair loop: lane 0 asks
+    // for it now, so the loads complete while the loop runs.
+    double4 v_pre = make_double4(0.0, 0.0, 0.0, 0.0), b_pre = v_pre;
+    int4 im_pre = make_int4(0, 0, 0, 0);
+    if (MODE != MODE_EVAL && lane == 0) {
+        v_pre = a.vel[q];
+        if (MODE == MODE_FUSED) {
+            b_pre = a.xb[q];
+            im_pre = a.img[q];
+        }
+    }
+
     Acc<PREC> acc;
     double ue = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
 
-    const size_t stride = (size_t)a.npad << a.lshift;
-    const int *row = a.nlist + nl_slot(q, lane, a.npad, a.lshift);
-    for (int k = lane; k < cnt; k += TPP, row += stride) {
-        const int j = *row;
-        const double4 xj = a.pos_in[j];
-        const double dx = mi_rint(xj.x - xi.x, L0, iL0);
-        const double dy = mi_rint(xj.y - xi.y, L1, iL1);
-        const double dz = mi_rint(xj.z - xi.z, L2, iL2);
-        const double r2 = r2_canon(dx, dy, dz);
-        const PairCoef &c = MULTI ? s_pair[ti * a.ntypes + (int)xj.w] : a.single;
-        if (r2 < c.rc2) {
-            if (PREC == PREC_FP64) {
-                const double r2i = rcp64(r2);
-                const double r6i = r2i * r2i * r2i;
-                const double ff = r2i * r6i * __builtin_fma(c.lj1, r6i, -c.lj2);
-                // force on i is ff * (x_i - x_j) = -ff * d
-                acc.fx = __builtin_fma(-ff, dx, acc.fx);
-                acc.fy = __builtin_fma(-ff, dy, acc.fy);
-                acc.fz = __builtin_fma(-ff, dz, acc.fz);
-                if (ENERGY) {
-                    ue += 0.5 * (r6i * __builtin_fma(c.lj3, r6i, -c.lj4) - c.shift);
-                    const double hf = 0.5 * ff;
-                    w0 = __builtin_fma(hf * dx, dx, w0);
-                    w1 = __builtin_fma(hf * dx, dy, w1);
-                    w2 = __builtin_fma(hf * dx, dz, w2);
-                    w3 = __builtin_fma(hf * dy, dy, w3);
-                    w4 = __builtin_fma(hf * dy, dz, w4);
-                    w5 = __builtin_fma(hf * dz, dz, w5);
-                }
-            } else {
-                // FP32 pair arithmetic on the exactly formed FP64 displacement
-                const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-                const float fr2 = (float)r2;
-                const float r2i = __builtin_amdgcn_rcpf(fr2);
-                const float r6i = r2i * r2i * r2i;
-                const float l1 = (float)c.lj1, l2 = (float)c.lj2;
-                const float ff = r2i * r6i * __builtin_fmaf(l1, r6i, -l2);
-                acc.fx = __builtin_fmaf(-ff, fdx, acc.fx);
-                acc.fy = __builtin_fmaf(-ff, fdy, acc.fy);
-                acc.fz = __builtin_fmaf(-ff, fdz, acc.fz);
-                if (ENERGY) {
-                    const float l3 = (float)c.lj3, l4 = (float)c.lj4;
-                    const float up = r6i * __builtin_fmaf(l3, r6i, -l4);
-                    ue += 0.5 * ((double)up - c.shift);
-                    const double hf = 0.5 * (double)ff;
-                    w0 = __builtin_fma(hf * (double)fdx, (double)fdx, w0);
-                    w1 = __builtin_fma(hf * (double)fdx, (double)fdy, w1);
-                    w2 = __builtin_fma(hf * (double)fdx, (double)fdz, w2);
-                    w3 = __builtin_fma(hf * (double)fdy, (double)fdy, w3);
-                    w4 = __builtin_fma(hf * (double)fdy, (double)fdz, w4);
-                    w5 = __builtin_fma(hf * (double)fdz, (double)fdz, w5);
-                }
-            }
+    // Each lane takes 4 entries per 16-byte load; the next chunk's load is issued before
+    // the current chunk's positions are gathered and used. The list is streamed once per
+    // step (non-temporal loads).
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i *row4 = reinterpret_cast<const v4i *>(a.nlist) + ((size_t)q << a.lshift) + lane;
+    const size_t cstride = (size_t)a.npad << a.lshift;
+    int k0 = lane * 4;
+    v4i nxt = {q, q, q, q};
+    if (k0 < cnt) nxt = __builtin_nontemporal_load(row4);
+    for (; k0 < cnt; k0 += 4 * TPP) {
+        const v4i cur = nxt;
+        row4 += cstride;
+        if (k0 + 4 * TPP < cnt) nxt = __builtin_nontemporal_load(row4);
+        const int jj[4] = {cur.x, k0 + 1 < cnt ? cur.y : q, k0 + 2 < cnt ? cur.z : q,
+                           k0 + 3 < cnt ? cur.w : q};
+        double4 xj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xj[u] = a.pos_in[jj[u]];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double dx = mi_rint(xj[u].x - xi.x, L0, iL0);
+            const double dy = mi_rint(xj[u].y - xi.y, L1, iL1);
+            const double dz = mi_rint(xj[u].z - xi.z, L2, iL2);
+            const double r2 = r2_canon(dx, dy, dz);
+            const PairCoef &c = MULTI ? s_pair[ti * a.ntypes + (int)xj[u].w] : a.single;
+            // an unused slot points at particle q itself (never a list entry)
+            if (jj[u] != q && r2 < c.rc2)
+                pair_term<PREC, ENERGY>(c, dx, dy, dz, r2, acc, ue, w0, w1, w2, w3, w4, w5);
         }
     }
 
@@ -312,7 +355,7 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs a) {
         a.force[q] = make_double4(fx, fy, fz, 0.0);
         return;
     }
-    double4 v = a.vel[q];
+    double4 v = v_pre;
     const double hm = a.half_dt * v.w;
     // second half kick of the current step: full-step velocity
     v.x = __builtin_fma(hm, fx, v.x);
@@ -335,7 +378,7 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs a) {
     x.x = __builtin_fma(a.dt, v.x, x.x);
     x.y = __builtin_fma(a.dt, v.y, x.y);
     x.z = __builtin_fma(a.dt, v.z, x.z);
-    int4 im = a.img[q];
+    int4 im = im_pre;
     const int4 im0 = im;
     wrap_coord(x.x, im.x, L0);
     wrap_coord(x.y, im.y, L1);
@@ -343,7 +386,7 @@ __global__ void __launch_bounds__(256) k_force(const ForceArgs a) {
     a.pos_out[q] = x;
     a.vel[q] = v;
     if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
-    const double4 b = a.xb[q];
+    const double4 b = b_pre;
     const double ex = mi_rint(x.x - b.x, L0, iL0);
     const double ey = mi_rint(x.y - b.y, L1, iL1);
     const double ez = mi_rint(x.z - b.z, L2, iL2);
@@ -410,51 +453,86 @@ __device__ __forceinline__ int cell_coord(double f, int nc) {
 }
 
 // Cell of each particle; the slot inside its cell comes from an integer atomic counter
-// (the order is made deterministic afterwards by k_cell_sort).
+// (the order is made deterministic afterwards by k_cell_gather). Particles are still in the
+// previous build's cell order, so equal cells come in runs along a wavefront: each run
+// takes its slots with one atomic add by its first lane.
 __global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
     if (*a.go == 0) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.n) return;
-    const double4 x = a.pos[q];
-    const int cx = cell_coord(x.x * a.inv_w[0], a.nc[0]);
-    const int cy = cell_coord(x.y * a.inv_w[1], a.nc[1]);
-    const int cz = cell_coord(x.z * a.inv_w[2], a.nc[2]);
-    int lin = (cx * a.nc[1] + cy) * a.nc[2] + cz;
-    int r = a.cell_rank[lin];
-    a.key[q] = r;
-    a.slot[q] = atomicAdd(&a.cell_count[r], 1);
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int wl = threadIdx.x & 63;
+    int r = -1;
+    if (q < a.n) {
+        const double4 x = a.pos[q];
+        const int cx = cell_coord(x.x * a.inv_w[0], a.nc[0]);
+        const int cy = cell_coord(x.y * a.inv_w[1], a.nc[1]);
+        const int cz = cell_coord(x.z * a.inv_w[2], a.nc[2]);
+        r = a.cell_rank[(cx * a.nc[1] + cy) * a.nc[2] + cz];
+    }
+    const int prev = __shfl_up(r, 1);
+    const bool head = (wl == 0) || (r != prev);
+    const unsigned long long heads = __ballot(head);
+    const unsigned long long le = (wl == 63) ? ~0ull : ((2ull << wl) - 1ull);
+    const int leader = 63 - __clzll(heads & le);
+    const unsigned long long after = heads & ~le;
+    const int next = after ? (__ffsll((long long)after) - 1) : 64;
+    int base = 0;
+    if (head && r >= 0) base = atomicAdd(&a.cell_count[r], next - wl);
+    base = __shfl(base, leader);
+    if (r >= 0) {
+        a.key[q] = r;
+        a.slot[q] = base + (wl - leader);
+    }
 }
 
-// Exclusive scan of the cell counts into cell_start[0..ncell] (one workgroup of 1024
-// threads, each owning a contiguous chunk), then the counts are zeroed for the next build.
+// Exclusive scan of the cell counts into cell_start[0..ncell], one workgroup of 1024
+// threads, in tiles of SCAN_TILE counts staged through LDS with coalesced loads; the counts
+// are zeroed for the next build.
 __global__ void __launch_bounds__(1024) k_scan(const RebuildArgs a) {
     if (*a.go == 0) return;
+    __shared__ int s_val[SCAN_TILE];
     __shared__ int s_sum[1024];
+    __shared__ int s_carry;
     const int T = blockDim.x;
     const int t = threadIdx.x;
-    const int chunk = (a.ncell + T - 1) / T;
-    const int beg = t * chunk;
-    const int end = min(a.ncell, beg + chunk);
-    int sum = 0;
-    for (int c = beg; c < end; ++c) sum += a.cell_count[c];
-    s_sum[t] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the per-thread sums
-    for (int o = 1; o < T; o <<= 1) {
-        int v = t >= o ? s_sum[t - o] : 0;
+    constexpr int PER = SCAN_TILE / 1024;
+    if (t == 0) {
+        s_carry = 0;
+        a.st->entries = 0ull;
+    }
+    for (int base = 0; base < a.ncell; base += SCAN_TILE) {
+        const int len = min(SCAN_TILE, a.ncell - base);
+        for (int u = t; u < SCAN_TILE; u += T) {
+            int v = 0;
+            if (u < len) {
+                v = a.cell_count[base + u];
+                a.cell_count[base + u] = 0;
+            }
+            s_val[u] = v;
+        }
         __syncthreads();
-        s_sum[t] += v;
+        int sum = 0;
+        for (int u = 0; u < PER; ++u) sum += s_val[t * PER + u];
+        s_sum[t] = sum;
+        __syncthreads();
+        for (int o = 1; o < T; o <<= 1) {
+            const int v = t >= o ? s_sum[t - o] : 0;
+            __syncthreads();
+            s_sum[t] += v;
+            __syncthreads();
+        }
+        int run = s_carry + s_sum[t] - sum;
+        for (int u = 0; u < PER; ++u) {
+            const int k = s_val[t * PER + u];
+            s_val[t * PER + u] = run;
+            run += k;
+        }
+        __syncthreads();
+        for (int u = t; u < len; u += T) a.cell_start[base + u] = s_val[u];
+        __syncthreads();
+        if (t == T - 1) s_carry += s_sum[T - 1];
         __syncthreads();
     }
-    if (t == 0) a.st->entries = 0ull;
-    int run = s_sum[t] - sum;
-    for (int c = beg; c < end; ++c) {
-        int k = a.cell_count[c];
-        a.cell_start[c] = run;
-        a.cell_count[c] = 0;
-        run += k;
-    }
-    if (t == T - 1) a.cell_start[a.ncell] = s_sum[t];
+    if (t == 0) a.cell_start[a.ncell] = s_carry;
 }
 
 __global__ void __launch_bounds__(256) k_scatter(const RebuildArgs a) {
@@ -464,215 +542,203 @@ __global__ void __launch_bounds__(256) k_scatter(const RebuildArgs a) {
     a.perm[a.cell_start[a.key[q]] + a.slot[q]] = q;
 }
 
-// Order each cell's members by their previous sorted index (a stable counting sort).
-// One workgroup of 64 lanes per cell; the rank of a member is the number of members with
-// a smaller index.
-__global__ void __launch_bounds__(64) k_cell_sort(const RebuildArgs a) {
+// Order each cell's members by their previous sorted index (a stable counting sort) and
+// gather their state into the new order. One workgroup of 64 lanes per cell (grid-stride);
+// the rank of a member is the number of members with a smaller index.
+__device__ __forceinline__ void gather_member(const RebuildArgs &a, int dst, int k) {
+    a.pos_scr[dst] = a.pos[k];
+    a.vel_scr[dst] = a.vel[k];
+    a.img_scr[dst] = a.img[k];
+}
+
+__global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
     if (*a.go == 0) return;
     __shared__ int s_in[SORT_LDS];
-    const int c = blockIdx.x;
-    const int beg = a.cell_start[c];
-    const int m = a.cell_start[c + 1] - beg;
-    if (m <= 1) return;
-    if (m <= SORT_LDS) {
-        for (int t = threadIdx.x; t < m; t += blockDim.x) s_in[t] = a.perm[beg + t];
-        __syncthreads();
-        for (int t = threadIdx.x; t < m; t += blockDim.x) {
-            int v = s_in[t];
-            int rank = 0;
-            for (int u = 0; u < m; ++u) rank += s_in[u] < v;
-            a.perm[beg + rank] = v;
-        }
-    } else if (threadIdx.x == 0) {
-        // pathological occupancy: insertion sort in place by one lane
-        for (int t = 1; t < m; ++t) {
-            int v = a.perm[beg + t];
-            int u = t - 1;
-            while (u >= 0 && a.perm[beg + u] > v) {
-                a.perm[beg + u + 1] = a.perm[beg + u];
-                --u;
+    for (int c = blockIdx.x; c < a.ncell; c += gridDim.x) {
+        const int beg = a.cell_start[c];
+        const int m = a.cell_start[c + 1] - beg;
+        __syncthreads();  // s_in of the previous cell is no longer read
+        if (m <= SORT_LDS) {
+            for (int t = threadIdx.x; t < m; t += blockDim.x) s_in[t] = a.perm[beg + t];
+            __syncthreads();
+            for (int t = threadIdx.x; t < m; t += blockDim.x) {
+                const int v = s_in[t];
+                int rank = 0;
+                for (int u = 0; u < m; ++u) rank += s_in[u] < v;
+                gather_member(a, beg + rank, v);
             }
-            a.perm[beg + u + 1] = v;
+        } else {
+            if (threadIdx.x == 0) {
+                // pathological occupancy: insertion sort in place by one lane
+                for (int t = 1; t < m; ++t) {
+                    const int v = a.perm[beg + t];
+                    int u = t - 1;
+                    while (u >= 0 && a.perm[beg + u] > v) {
+                        a.perm[beg + u + 1] = a.perm[beg + u];
+                        --u;
+                    }
+                    a.perm[beg + u + 1] = v;
+                }
+            }
+            __syncthreads();
+            for (int t = threadIdx.x; t < m; t += blockDim.x)
+                gather_member(a, beg + t, a.perm[beg + t]);
         }
     }
 }
 
-__global__ void __launch_bounds__(256) k_permute(const RebuildArgs a) {
-    if (*a.go == 0) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= a.n) return;
-    int k = a.perm[q];
-    a.pos_scr[q] = a.pos[k];
-    a.vel_scr[q] = a.vel[k];
-    a.img_scr[q] = a.img[k];
-}
-
 // ---------------------------------------------------------------- rebuild: Verlet list
 
-// One workgroup per cell. The atoms of the cell's stencil (27 cells, or its distinct
-// cells when an axis has fewer than 3) are staged in LDS; NL_LANES lanes per particle of
-// the cell scan the staged atoms and append every j != i with r^2 < (r_cut + skin)^2.
-// Appends from the lanes of one particle are compacted with a wavefront ballot so that
-// the entry order (stencil cell, then index) is deterministic. The workgroup also copies
-// its particles' permuted state back into the main arrays and records the build positions.
+// One wavefront per cell (grid-stride over cells in XCD-contiguous order). The cell's
+// particles are split into groups of L lanes, L = 64 / (particles in the cell) clamped to
+// [1, 32], so nearly every lane has work. Each group walks the atoms of the 27 stencil
+// cells (their distinct cells when an axis has fewer than 3) L at a time and appends every
+// j != i with r^2 < (r_cut + skin)^2. All groups read the same candidates at the same time,
+// so the position loads coalesce. Appends of one group are compacted with a wavefront
+// ballot: the entry order (stencil cell, then index) is deterministic. The wavefront also
+// copies its particles' permuted state back into the main arrays and records the build
+// positions.
+//
+// Distances: for an axis with at least 3 cells the periodic image of a stencil cell is
+// known, and fl(fl(x_j - x_i) + s) with s in {-L, 0, L} equals the branch-form minimum
+// image bit for bit for every pair that can be listed; cells away from the box faces need
+// no shift at all. With fewer than 3 cells on some axis the branch form is applied.
 template <bool MULTI>
 __device__ __forceinline__ double rl2_of(const RebuildArgs &a, const double *s_rl2, int ti,
                                          int tj) {
     return MULTI ? s_rl2[ti * a.ntypes + tj] : a.single_rl2;
 }
 
-template <bool MULTI, bool STAGED>
-__device__ __forceinline__ int scan_stencil(const RebuildArgs &a, const double *s_pair,
-                                            const double4 *s_pos, const int *s_start,
-                                            const int *s_cnt, const int *s_off,
-                                            const double *s_shift, int ns, int q, double4 xi,
-                                            int lane, int gbase, int *rowbase_dummy) {
-    (void)rowbase_dummy;
-    const int ti = MULTI ? (int)xi.w : 0;
-    const unsigned long long gmask = ((1ull << NL_LANES) - 1ull) << gbase;
-    const int wl = threadIdx.x & 63;
-    const unsigned long long below = (1ull << wl) - 1ull;
-    int count = 0;
-    for (int c = 0; c < ns; ++c) {
-        const int m = s_cnt[c];
-        const int jbeg = s_start[c];
-        const int off = s_off[c];
-        const double sx = s_shift[3 * c], sy = s_shift[3 * c + 1], sz = s_shift[3 * c + 2];
-        for (int t0 = 0; t0 < m; t0 += NL_LANES) {
-            const int t = t0 + lane;
-            bool hit = false;
-            int j = 0;
-            if (t < m) {
-                j = jbeg + t;
-                const double4 xj = STAGED ? s_pos[off + t] : a.pos_scr[j];
-                double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
-                if (a.canonical_mi) {
-                    dx = mi_branch(dx, a.L[0]);
-                    dy = mi_branch(dy, a.L[1]);
-                    dz = mi_branch(dz, a.L[2]);
-                } else {
-                    dx = dx + sx;  // adding 0.0 is exact
-                    dy = dy + sy;
-                    dz = dz + sz;
-                }
-                const double r2 = r2_canon(dx, dy, dz);
-                hit = (j != q) && (r2 < rl2_of<MULTI>(a, s_pair, ti, MULTI ? (int)xj.w : 0));
-            }
-            const unsigned long long bal = __ballot(hit) & gmask;
-            if (hit) {
-                const int k = count + __popcll(bal & below);
-                if (k < a.cap) a.nlist[nl_slot(q, k, a.npad, a.lshift)] = j;
-            }
-            count += __popcll(bal);
-        }
-    }
-    return count;
-}
-
 template <bool MULTI>
-__global__ void __launch_bounds__(NL_BLOCK) k_nlist(const RebuildArgs a) {
+__global__ void __launch_bounds__(64) k_nlist(const RebuildArgs a) {
     if (*a.go == 0) return;
-    __shared__ double4 s_pos[NL_LDS_ATOMS];
-    __shared__ int s_start[27], s_cnt[27], s_off[28];
+    __shared__ int s_start[27], s_cnt[27], s_rank[27], s_has[27];
     __shared__ double s_shift[81];
-    __shared__ int s_ns;
-    __shared__ int s_max;
-    __shared__ unsigned long long s_entries;
-    __shared__ double s_pair[MULTI ? LJMD_MAX_TYPES_DEV * LJMD_MAX_TYPES_DEV : 1];
-    const int cell = xcd_remap(blockIdx.x, gridDim.x);
+    __shared__ int s_ns, s_interior;
+    __shared__ double s_rl2[MULTI ? LJMD_MAX_TYPES_DEV * LJMD_MAX_TYPES_DEV : 1];
     if (MULTI) {
-        int nt2 = a.ntypes * a.ntypes;
-        for (int t = threadIdx.x; t < nt2; t += blockDim.x) s_pair[t] = a.rl2_table[t];
-    }
-    if (threadIdx.x == 0) {
-        s_max = 0;
-        s_entries = 0ull;
+        const int nt2 = a.ntypes * a.ntypes;
+        for (int t = threadIdx.x; t < nt2; t += blockDim.x) s_rl2[t] = a.rl2_table[t];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->builds, 1ull);
-    if (threadIdx.x == 0) {
-        const int packed = a.cell_xyz[cell];
-        const int cxyz[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
-        int ns = 0;
-        int seen[27];
-        for (int ox = -1; ox <= 1; ++ox)
-            for (int oy = -1; oy <= 1; ++oy)
-                for (int oz = -1; oz <= 1; ++oz) {
-                    const int o[3] = {ox, oy, oz};
-                    int e[3];
-                    double sh[3];
-                    for (int d = 0; d < 3; ++d) {
-                        int v = cxyz[d] + o[d];
-                        sh[d] = 0.0;
-                        if (v < 0) { v += a.nc[d]; sh[d] = -a.L[d]; }
-                        else if (v >= a.nc[d]) { v -= a.nc[d]; sh[d] = a.L[d]; }
-                        e[d] = v;
-                    }
-                    const int lin = (e[0] * a.nc[1] + e[1]) * a.nc[2] + e[2];
-                    const int r = a.cell_rank[lin];
+    const int wl = threadIdx.x;  // one wavefront
+    const unsigned long long below = (1ull << wl) - 1ull;
+    int my_max = 0;
+    unsigned long long my_entries = 0ull;
+
+    for (int cell = xcd_remap(blockIdx.x, gridDim.x); cell < a.ncell; cell += gridDim.x) {
+        __syncthreads();  // the previous cell's stencil is no longer read
+        if (wl < 27) {
+            const int packed = a.cell_xyz[cell];
+            const int cxyz[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
+            const int o[3] = {wl / 9 - 1, (wl / 3) % 3 - 1, wl % 3 - 1};
+            int e[3];
+            int has = 0;
+            for (int d = 0; d < 3; ++d) {
+                int v = cxyz[d] + o[d];
+                double sh = 0.0;
+                if (v < 0) { v += a.nc[d]; sh = -a.L[d]; has = 1; }
+                else if (v >= a.nc[d]) { v -= a.nc[d]; sh = a.L[d]; has = 1; }
+                e[d] = v;
+                s_shift[3 * wl + d] = sh;
+            }
+            const int r = a.cell_rank[(e[0] * a.nc[1] + e[1]) * a.nc[2] + e[2]];
+            s_rank[wl] = r;
+            s_has[wl] = has;
+            s_start[wl] = a.cell_start[r];
+            s_cnt[wl] = a.cell_start[r + 1] - a.cell_start[r];
+        }
+        __syncthreads();
+        if (wl == 0) {
+            int ns = 27, any = 0;
+            if (a.canonical_mi) {
+                // fewer than 3 cells on some axis: keep the first occurrence of each cell
+                ns = 0;
+                for (int t = 0; t < 27; ++t) {
                     bool dup = false;
-                    for (int u = 0; u < ns; ++u) dup |= (seen[u] == r);
+                    for (int u = 0; u < t; ++u) dup |= (s_rank[u] == s_rank[t]);
                     if (dup) continue;
-                    seen[ns] = r;
-                    s_start[ns] = a.cell_start[r];
-                    s_cnt[ns] = a.cell_start[r + 1] - a.cell_start[r];
-                    s_shift[3 * ns] = sh[0];
-                    s_shift[3 * ns + 1] = sh[1];
-                    s_shift[3 * ns + 2] = sh[2];
+                    s_start[ns] = s_start[t];
+                    s_cnt[ns] = s_cnt[t];
                     ++ns;
                 }
-        int off = 0;
-        for (int u = 0; u < ns; ++u) {
-            s_off[u] = off;
-            off += s_cnt[u];
+            } else {
+                for (int t = 0; t < 27; ++t) any |= s_has[t];
+            }
+            s_ns = ns;
+            s_interior = (!a.canonical_mi && !any) ? 1 : 0;
         }
-        s_off[ns] = off;
-        s_ns = ns;
-    }
-    __syncthreads();
-    const int ns = s_ns;
-    const int total = s_off[ns];
-    const bool staged = total <= NL_LDS_ATOMS;
-    if (staged) {
-        for (int t = threadIdx.x; t < total; t += blockDim.x) {
-            int c = 0;
-            while (t >= s_off[c + 1]) ++c;
-            s_pos[t] = a.pos_scr[s_start[c] + (t - s_off[c])];
+        __syncthreads();
+        const int ns = s_ns;
+        const bool interior = s_interior != 0;
+        const int beg = a.cell_start[cell];
+        const int cnt = a.cell_start[cell + 1] - beg;
+        if (cnt == 0) continue;
+        int L = 64 / cnt;
+        L = L < 1 ? 1 : (L > 32 ? 32 : L);
+        const int G = 64 / L;
+        const int group = wl / L;
+        const int lane = wl - group * L;
+        const unsigned long long gmask = group < G ? (((1ull << L) - 1ull) << (group * L)) : 0ull;
+        for (int p0 = 0; p0 < cnt; p0 += G) {
+            const int p = p0 + group;
+            const bool active = group < G && p < cnt;
+            const int q = beg + (active ? p : 0);
+            const double4 xi = a.pos_scr[q];
+            const int ti = MULTI ? (int)xi.w : 0;
+            int count = 0;
+            for (int c = 0; c < ns; ++c) {
+                const int m = s_cnt[c];
+                const int jb = s_start[c];
+                const double sx = s_shift[3 * c], sy = s_shift[3 * c + 1], sz = s_shift[3 * c + 2];
+                for (int t0 = 0; t0 < m; t0 += L) {
+                    const int t = t0 + lane;
+                    const bool valid = active && t < m;
+                    const int j = jb + (valid ? t : 0);
+                    const double4 xj = a.pos_scr[j];
+                    double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+                    if (a.canonical_mi) {
+                        dx = mi_branch(dx, a.L[0]);
+                        dy = mi_branch(dy, a.L[1]);
+                        dz = mi_branch(dz, a.L[2]);
+                    } else if (!interior) {
+                        dx = dx + sx;  // adding 0.0 is exact
+                        dy = dy + sy;
+                        dz = dz + sz;
+                    }
+                    const double r2 = r2_canon(dx, dy, dz);
+                    const bool hit = valid && j != q &&
+                                     r2 < rl2_of<MULTI>(a, s_rl2, ti, MULTI ? (int)xj.w : 0);
+                    const unsigned long long bal = __ballot(hit) & gmask;
+                    if (hit) {
+                        const int k = count + __popcll(bal & below);
+                        if (k < a.cap) a.nlist[nl_slot(q, k, a.npad, a.lshift)] = j;
+                    }
+                    count += __popcll(bal);
+                }
+            }
+            if (active && lane == 0) {
+                a.nl_count[q] = count;
+                if (count > a.cap) atomicOr(&a.st->status, ST_OVERFLOW);
+                my_max = count > my_max ? count : my_max;
+                my_entries += (unsigned long long)(count < a.cap ? count : a.cap);
+                // the permuted state becomes the main state; this is the new build point
+                a.pos[q] = xi;
+                a.xb[q] = xi;
+                a.vel[q] = a.vel_scr[q];
+                a.img[q] = a.img_scr[q];
+            }
         }
     }
-    __syncthreads();
-
-    const int my_beg = a.cell_start[cell];
-    const int my_cnt = a.cell_start[cell + 1] - my_beg;
-    const int lane = threadIdx.x & (NL_LANES - 1);
-    const int group = threadIdx.x / NL_LANES;
-    const int ngroups = blockDim.x / NL_LANES;
-    const int gbase = (threadIdx.x & 63) & ~(NL_LANES - 1);
-    for (int p = group; p < my_cnt; p += ngroups) {
-        const int q = my_beg + p;
-        const double4 xi = a.pos_scr[q];
-        int count;
-        if (staged)
-            count = scan_stencil<MULTI, true>(a, s_pair, s_pos, s_start, s_cnt, s_off, s_shift,
-                                              ns, q, xi, lane, gbase, nullptr);
-        else
-            count = scan_stencil<MULTI, false>(a, s_pair, s_pos, s_start, s_cnt, s_off,
-                                               s_shift, ns, q, xi, lane, gbase, nullptr);
-        if (lane == 0) {
-            a.nl_count[q] = count;
-            if (count > a.cap) atomicOr(&a.st->status, ST_OVERFLOW);
-            atomicMax(&s_max, count);
-            atomicAdd(&s_entries, (unsigned long long)(count < a.cap ? count : a.cap));
-            // the permuted state becomes the main state; this is the new build point
-            a.pos[q] = xi;
-            a.xb[q] = xi;
-            a.vel[q] = a.vel_scr[q];
-            a.img[q] = a.img_scr[q];
-        }
+    // wavefront reductions of the build statistics, one atomic each per workgroup
+    for (int o = 32; o > 0; o >>= 1) {
+        const int om = __shfl_xor(my_max, o);
+        my_max = om > my_max ? om : my_max;
+        my_entries += __shfl_xor(my_entries, o);
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && s_max > 0) {
-        atomicMax(&a.st->max_count, s_max);
-        atomicAdd(&a.st->entries, s_entries);
+    if (wl == 0 && my_max > 0) {
+        atomicMax(&a.st->max_count, my_max);
+        atomicAdd(&a.st->entries, my_entries);
     }
 }
 
@@ -682,12 +748,12 @@ hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
     hipLaunchKernelGGL(k_bin, dim3(g), dim3(b), 0, s, a);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(b), 0, s, a);
-    hipLaunchKernelGGL(k_cell_sort, dim3(a.ncell), dim3(64), 0, s, a);
-    hipLaunchKernelGGL(k_permute, dim3(g), dim3(b), 0, s, a);
+    hipLaunchKernelGGL(k_cell_gather, dim3(a.ncell < 8192 ? a.ncell : 8192), dim3(64), 0, s, a);
+    const int gn = a.ncell < NL_GRID ? a.ncell : NL_GRID;
     if (a.ntypes > 1)
-        hipLaunchKernelGGL(k_nlist<true>, dim3(a.ncell), dim3(NL_BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_nlist<true>, dim3(gn), dim3(64), 0, s, a);
     else
-        hipLaunchKernelGGL(k_nlist<false>, dim3(a.ncell), dim3(NL_BLOCK), 0, s, a);
+        hipLaunchKernelGGL(k_nlist<false>, dim3(gn), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 

@@ -277,8 +277,9 @@ int setup_table(ljmd_system *s) {
 }
 
 int ensure_list_alloc(ljmd_system *s, int cap) {
-    // a multiple of 16 keeps every tiled-layout slot of k < cap inside cap * npad
-    cap = std::max(16, (cap + 15) & ~15);
+    // a multiple of 64 (4 entries x up to 16 lanes) keeps every slot of k < cap inside
+    // cap * npad for every lane count
+    cap = std::max(64, (cap + 63) & ~63);
     const size_t need = (size_t)cap * (size_t)s->npad;
     if (need > s->nlist_alloc) {
         dfree(s, s->d_nlist);
@@ -294,8 +295,8 @@ int ensure_list_alloc(ljmd_system *s, int cap) {
 
 int round_cap(double v) {
     int c = (int)std::ceil(v);
-    c = (c + 15) & ~15;
-    return std::max(c, 16);
+    c = (c + 63) & ~63;
+    return std::max(c, 64);
 }
 
 // ------------------------------------------------------------ argument blocks
@@ -965,8 +966,9 @@ int ljmd_get_neighbor_pairs(ljmd_system *s, int64_t *count, int32_t *pairs, doub
     for (size_t q = 0; q < N; ++q) {
         const int c = std::min(cnt[q], s->cap);
         for (int k = 0; k < c; ++k) {
-            const size_t slot = ((((size_t)(k >> s->lshift)) * (size_t)s->npad + q) << s->lshift) |
-                                (size_t)(k & ((1 << s->lshift) - 1));
+            const size_t c = (size_t)(k >> (2 + s->lshift));
+            const size_t l = (size_t)((k >> 2) & ((1 << s->lshift) - 1));
+            const size_t slot = ((((c * (size_t)s->npad + q) << s->lshift) + l) << 2) | (size_t)(k & 3);
             const int j = nl[slot];
             const int a = tag[q], b = tag[j];
             if (a < b) pr.emplace_back(a, b);
