@@ -74,7 +74,7 @@ typedef struct ljmd_config {
     int32_t nlist_capacity; /* entries per particle; 0 = sized from the first build */
     int32_t threads_per_particle; /* lanes per particle in the force kernel: 1,2,4,8,16
                                      or 0 = autotuned */
-    int32_t block_size;     /* force kernel workgroup size: 64, 128, 192 or 256;
+    int32_t block_size;     /* force kernel workgroup size: a multiple of 64 up to 512;
                                0 = autotuned */
     int32_t graph_steps;    /* steps per captured HIP graph block (even, >= 2); 0 = 64;
                                -1 disables graphs */

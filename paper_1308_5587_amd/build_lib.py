@@ -27,15 +27,19 @@ def _hipcc():
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile the sources into `out` (default: the in-tree libljmd.so); `defines` are
+    extra -D flags for building variants."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    objdir = os.path.join(HERE, "_build")
+    tag = "" if out == LIB else "_" + os.path.splitext(os.path.basename(out))[0]
+    objdir = os.path.join(HERE, "_build" + tag)
     os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *HIPFLAGS, *["-D" + d for d in defines], "-c", os.path.join(CSRC, src),
+               "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -45,13 +49,13 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
         objs = list(ex.map(compile_one, srcs))
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

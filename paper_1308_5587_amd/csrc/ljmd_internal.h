@@ -32,7 +32,31 @@ struct DevStatus {
     int pad;
 };
 
-enum { ST_OVERFLOW = 1, ST_NONFINITE = 2 };
+enum { ST_OVERFLOW = 1, ST_NONFINITE = 2, ST_TILE = 4 };
+
+// Bricks: aligned groups of up to 2 x 2 x 2 cells whose cells are consecutive in the cell
+// order. A brick's halo is every cell within one cell of it (up to 4 x 4 x 4 = 64 cells);
+// the atoms of the halo, concatenated in halo order, form the brick's tile, and list
+// entries are 16-bit indices into that tile.
+struct BrickInfo {
+    int first_cell;  // rank of the brick's first cell (its (0,0,0) corner)
+    int ncell;       // cells in the brick (1..8)
+    int nhalo;       // halo cells (<= HALO_MAX)
+    int dims;        // halo extents hx | hy << 4 | hz << 8, brick extents ex << 12 | ey << 16 | ez << 20
+};
+// Halo cell: its rank and the periodic image it is seen in from the brick, per axis a
+// value in {-1, 0, 1} stored as (s + 1) in two bits: sx | sy << 2 | sz << 4.
+struct HaloCell {
+    int rank;
+    int shift;
+};
+constexpr int HALO_MAX = 64;
+constexpr int TILE_MAX = 2560;        // tile atoms staged in LDS at most (FP64 SoA: 60 KiB)
+constexpr int TILE_INDEX_MAX = 65535; // 16-bit tile indices
+#ifndef LJMD_FORCE_BATCH
+#define LJMD_FORCE_BATCH 4
+#endif
+constexpr int FORCE_BATCH = LJMD_FORCE_BATCH;  // neighbour positions requested together (1, 2, 4, 8)
 
 enum { MODE_EVAL = 0, MODE_FUSED = 1, MODE_FINAL = 2 };
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };
@@ -42,8 +66,24 @@ constexpr int RED_BLOCK = 256;       // reduction workgroup size
 constexpr int RED_QUANT = 8;         // U, W[6], K
 constexpr int SORT_LDS = 1024;       // in-cell sort capacity per workgroup
 constexpr int SCAN_TILE = 8192;      // counts per LDS tile of the scan (multiple of 1024)
-constexpr int NL_GRID = 8192;        // build wavefronts (grid-stride over cells)
-constexpr int FORCE_UNROLL = 4;      // list entries in flight per lane in the force kernel
+
+// Dynamic LDS of the force kernel: tile x, y, z (FP64), then types and the pair table
+// when there are several types.
+__host__ __device__ inline size_t force_lds_bytes(int tile_cap, int ntypes) {
+    size_t b = (size_t)tile_cap * 3 * sizeof(double);
+    if (ntypes > 1)
+        b += (size_t)((tile_cap + 1) / 2) * sizeof(double) +
+             (size_t)ntypes * ntypes * sizeof(PairCoef);
+    return b;
+}
+
+// Dynamic LDS of the list build: tile x, y, z (FP64), then types and the list radii.
+__host__ __device__ inline size_t nlist_lds_bytes(int tile_cap, int ntypes) {
+    size_t b = (size_t)tile_cap * 3 * sizeof(double);
+    if (ntypes > 1)
+        b += (size_t)((tile_cap + 1) / 2) * sizeof(double) + (size_t)ntypes * ntypes * sizeof(double);
+    return b;
+}
 
 // Arguments of the force kernel family (by value).
 struct ForceArgs {
@@ -54,7 +94,10 @@ struct ForceArgs {
     const double4 *xb;       // positions at the last build
     double4 *force;          // MODE_EVAL / MODE_FINAL output
     const int *nl_count;
-    const int *nlist;
+    const uint16_t *nlist;   // 16-bit tile indices
+    const BrickInfo *bricks;
+    const HaloCell *halo;    // HALO_MAX per brick
+    const int *cell_start;
     double *u_out;           // per-particle energy half-sums (ENERGY)
     double *w_out;           // per-particle virial half-sums, 6 per particle (ENERGY)
     double *ke_out;          // per-particle kinetic energy at the full step (ENERGY, FUSED)
@@ -66,6 +109,7 @@ struct ForceArgs {
     double L[3], invL[3];
     double dt, half_dt, lim2;
     int n, npad, cap, lshift, ntypes;
+    int nbrick, tile_cap;
 };
 
 struct KickDriftArgs {
@@ -95,7 +139,10 @@ struct RebuildArgs {
     int *cell_start;         // ncell + 1
     const int *cell_rank;    // linear cell index -> Morton rank
     const int *cell_xyz;     // Morton rank -> packed (cx | cy << 10 | cz << 20)
-    int *nl_count, *nlist;
+    int *nl_count;
+    uint16_t *nlist;
+    const BrickInfo *bricks;
+    const HaloCell *halo;
     const PairCoef *pair;
     DevStatus *st;
     double L[3], invL[3], inv_w[3];
@@ -103,6 +150,7 @@ struct RebuildArgs {
     int nc[3];
     int ncell, n, npad, cap, lshift, ntypes;
     int canonical_mi;        // 1 when some axis has fewer than 3 cells
+    int nbrick, tile_cap;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -122,5 +170,6 @@ hipError_t launch_unsort_img(hipStream_t s, const int4 *img, int n, int *dst);
 hipError_t launch_unsort_scalar(hipStream_t s, const double *src, int width, const int4 *img,
                                 int n, double *dst);
 hipError_t launch_fill_status(hipStream_t s, DevStatus *st);
+hipError_t launch_decode_list(hipStream_t s, const RebuildArgs &a, int *out);
 
 }  // namespace ljmd

@@ -5,15 +5,14 @@
 // formed as (dx*dx + dy*dy) + dz*dz with separate roundings, the operation order that
 // defines the neighbour list bit for bit.
 //
-// Data layout (sorted order: particles grouped by cell, cells in Morton order):
+// Data layout (sorted order: particles grouped by cell; cells grouped into 2 x 2 x 2
+// bricks, bricks in Morton order, cells in Morton order inside a brick):
 //   pos    double4 (x, y, z, type)        two buffers, the step kernel reads one and
 //                                          writes the other
 //   vel    double4 (vx, vy, vz, 1/m)
 //   img    int4    (image x, y, z, tag)
 //   xb     double4 positions at the last list build
-//   nlist  int32 entries, "tiled entry-major": entry k of particle q is stored at
-//          ((k >> s) * npad + q) << s | (k & (2^s - 1)), s = log2(lanes per particle),
-//          so one wavefront's lanes read 64 consecutive entries per iteration.
+//   nlist  uint16 indices into the particle's brick tile (see nl_slot for the layout).
 #include "ljmd_internal.h"
 
 namespace ljmd {
@@ -78,13 +77,84 @@ __device__ __forceinline__ void wrap_coord(double &x, int &im, double L) {
     }
 }
 
-// List slot of entry k of particle q with 2^ls lanes per particle: lanes own chunks of 4
-// consecutive entries, lane l holds chunks l, l + 2^ls, ...; for chunk index c the lanes
-// of consecutive particles are adjacent, so a wavefront reads 64 x 16 contiguous bytes.
+// List slot of entry k of particle q with 2^ls lanes per particle: lanes own chunks of 8
+// consecutive 16-bit entries, lane l holds chunks l, l + 2^ls, ...; for chunk index c the
+// lanes of consecutive particles are adjacent, so a wavefront reads 64 x 16 contiguous bytes.
 __device__ __forceinline__ size_t nl_slot(int q, int k, int npad, int ls) {
-    const size_t c = (size_t)(k >> (2 + ls));
-    const size_t l = (size_t)((k >> 2) & ((1 << ls) - 1));
-    return ((((c * (size_t)npad + (size_t)q) << ls) + l) << 2) | (size_t)(k & 3);
+    const size_t c = (size_t)(k >> (3 + ls));
+    const size_t l = (size_t)((k >> 3) & ((1 << ls) - 1));
+    return ((((c * (size_t)npad + (size_t)q) << ls) + l) << 3) | (size_t)(k & 7);
+}
+
+// ---------------------------------------------------------------- brick tiles
+
+// Offsets of a brick's tile: tile atom k belongs to halo cell h with off[h] <= k < off[h+1]
+// and is the particle start[h] + (k - off[h]) of the sorted order.
+struct TileSmem {
+    int off[HALO_MAX + 1];
+    int start[HALO_MAX];
+    int shift[HALO_MAX];
+    int nhalo;
+    int total;
+};
+
+// Wavefront 0 reads the halo cells (lane h, h < nhalo) and scans their atom counts.
+__device__ __forceinline__ void tile_setup(const BrickInfo &bi, const HaloCell *halo_b,
+                                           const int *cell_start, TileSmem &t) {
+    if (threadIdx.x < 64) {
+        const int h = threadIdx.x;
+        int cnt = 0;
+        if (h < bi.nhalo) {
+            const HaloCell hc = halo_b[h];
+            const int st = cell_start[hc.rank];
+            cnt = cell_start[hc.rank + 1] - st;
+            t.start[h] = st;
+            t.shift[h] = hc.shift;
+        }
+        int v = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(v, o);
+            if (h >= o) v += u;
+        }
+        t.off[h + 1] = v;
+        if (h == 0) {
+            t.off[0] = 0;
+            t.nhalo = bi.nhalo;
+        }
+        if (h == 63) t.total = v;
+    }
+    __syncthreads();
+}
+
+// Halo cell of tile atom k (0 <= k < total): the h with off[h] <= k < off[h+1].
+__device__ __forceinline__ int tile_cell(const TileSmem &t, int k) {
+    int lo = 0, hi = t.nhalo;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (t.off[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int tile_global(const TileSmem &t, int k) {
+    const int h = tile_cell(t, k);
+    return t.start[h] + (k - t.off[h]);
+}
+
+// Copy the tile's positions (and types) into LDS, structure of arrays.
+template <bool MULTI>
+__device__ __forceinline__ void tile_stage(const TileSmem &t, const double4 *pos, double *sx,
+                                           double *sy, double *sz, int *sty) {
+    for (int k = threadIdx.x; k < t.total; k += blockDim.x) {
+        const double4 p = pos[tile_global(t, k)];
+        sx[k] = p.x;
+        sy[k] = p.y;
+        sz[k] = p.z;
+        if (MULTI) sty[k] = (int)p.w;
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- upload (create / set_state)
@@ -253,159 +323,215 @@ __device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double d
     }
 }
 
-// TPP lanes per particle stride through its list; forces are reduced across the lanes
-// with wavefront shuffles; lane 0 then finishes the particle according to MODE.
-template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI>
-__global__ void __launch_bounds__(256) k_force(const ForceArgs a) {
-    __shared__ PairCoef s_pair[MULTI ? LJMD_MAX_TYPES_DEV * LJMD_MAX_TYPES_DEV : 1];
-    if (MULTI) {
-        int nt2 = a.ntypes * a.ntypes;
-        for (int t = threadIdx.x; t < nt2; t += blockDim.x) s_pair[t] = a.pair[t];
-        __syncthreads();
-    }
-    if (MODE == MODE_FUSED && blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild_clear = 0;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int tid = blk * blockDim.x + threadIdx.x;
-    const int q = tid / TPP;
-    const int lane = tid & (TPP - 1);
-    if (q >= a.n) return;  // whole groups of TPP lanes leave together
-
-    const double4 xi = a.pos_in[q];
-    const int ti = MULTI ? (int)xi.w : 0;
-    int cnt = a.nl_count[q];
-    cnt = cnt < a.cap ? cnt : a.cap;
+// The particle passes of one brick; STAGED selects neighbour positions from the LDS tile
+// (plain LDS reads) or, for a tile larger than the LDS allocation, from global memory.
+template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI, bool STAGED>
+__device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem &t,
+                                             const double *__restrict__ sx,
+                                             const double *__restrict__ sy,
+                                             const double *__restrict__ sz,
+                                             const int *__restrict__ sty,
+                                             const PairCoef *s_pair, int first, int natoms) {
+    const int per_pass = blockDim.x / TPP;
+    const int g = threadIdx.x / TPP;
+    const int lane = threadIdx.x & (TPP - 1);
     const double L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
     const double iL0 = a.invL[0], iL1 = a.invL[1], iL2 = a.invL[2];
-
-    // The integration state of the particle does not depend on the pair loop: lane 0 asks
-    // for it now, so the loads complete while the loop runs.
-    double4 v_pre = make_double4(0.0, 0.0, 0.0, 0.0), b_pre = v_pre;
-    int4 im_pre = make_int4(0, 0, 0, 0);
-    if (MODE != MODE_EVAL && lane == 0) {
-        v_pre = a.vel[q];
-        if (MODE == MODE_FUSED) {
-            b_pre = a.xb[q];
-            im_pre = a.img[q];
-        }
-    }
-
-    Acc<PREC> acc;
-    double ue = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
-
-    // Each lane takes 4 entries per 16-byte load; the next chunk's load is issued before
-    // the current chunk's positions are gathered and used. The list is streamed once per
-    // step (non-temporal loads).
     typedef int v4i __attribute__((ext_vector_type(4)));
-    const v4i *row4 = reinterpret_cast<const v4i *>(a.nlist) + ((size_t)q << a.lshift) + lane;
-    const size_t cstride = (size_t)a.npad << a.lshift;
-    int k0 = lane * 4;
-    v4i nxt = {q, q, q, q};
-    if (k0 < cnt) nxt = __builtin_nontemporal_load(row4);
-    for (; k0 < cnt; k0 += 4 * TPP) {
-        const v4i cur = nxt;
-        row4 += cstride;
-        if (k0 + 4 * TPP < cnt) nxt = __builtin_nontemporal_load(row4);
-        const int jj[4] = {cur.x, k0 + 1 < cnt ? cur.y : q, k0 + 2 < cnt ? cur.z : q,
-                           k0 + 3 < cnt ? cur.w : q};
-        double4 xj[4];
+    const size_t cstride = (size_t)a.npad << a.lshift;  // 16-byte chunks between rounds
+
+    for (int p0 = 0; p0 < natoms; p0 += per_pass) {
+        const int p = p0 + g;
+        const bool active = p < natoms;
+        const int q = first + (active ? p : 0);
+        const double4 xi = a.pos_in[q];
+        const int ti = MULTI ? (int)xi.w : 0;
+        int cnt = active ? a.nl_count[q] : 0;
+        cnt = cnt < a.cap ? cnt : a.cap;
+
+        // the integration state does not depend on the pair loop: request it now
+        double4 v_pre = make_double4(0.0, 0.0, 0.0, 0.0), b_pre = v_pre;
+        int4 im_pre = make_int4(0, 0, 0, 0);
+        if (MODE != MODE_EVAL && active && lane == 0) {
+            v_pre = a.vel[q];
+            if (MODE == MODE_FUSED) {
+                b_pre = a.xb[q];
+                im_pre = a.img[q];
+            }
+        }
+
+        Acc<PREC> acc;
+        double ue = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
+        const v4i *row = reinterpret_cast<const v4i *>(a.nlist) + ((size_t)q << a.lshift) + lane;
+        int k0 = lane * 8;
+        v4i nxt = {0, 0, 0, 0};
+        if (k0 < cnt) nxt = __builtin_nontemporal_load(row);
+        for (; k0 < cnt; k0 += 8 * TPP) {
+            const v4i cur = nxt;
+            row += cstride;
+            if (k0 + 8 * TPP < cnt) nxt = __builtin_nontemporal_load(row);
+            const int e[8] = {cur.x & 0xffff, (cur.x >> 16) & 0xffff, cur.y & 0xffff,
+                              (cur.y >> 16) & 0xffff, cur.z & 0xffff, (cur.z >> 16) & 0xffff,
+                              cur.w & 0xffff, (cur.w >> 16) & 0xffff};
+            // entries in groups of FORCE_BATCH: all neighbour positions of the group are
+            // requested first, then the arithmetic runs on them
 #pragma unroll
-        for (int u = 0; u < 4; ++u) xj[u] = a.pos_in[jj[u]];
+            for (int u0 = 0; u0 < 8; u0 += FORCE_BATCH) {
+                double px[FORCE_BATCH], py[FORCE_BATCH], pz[FORCE_BATCH];
+                int pt[FORCE_BATCH];
+                bool pv[FORCE_BATCH];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const double dx = mi_rint(xj[u].x - xi.x, L0, iL0);
-            const double dy = mi_rint(xj[u].y - xi.y, L1, iL1);
-            const double dz = mi_rint(xj[u].z - xi.z, L2, iL2);
-            const double r2 = r2_canon(dx, dy, dz);
-            const PairCoef &c = MULTI ? s_pair[ti * a.ntypes + (int)xj[u].w] : a.single;
-            // an unused slot points at particle q itself (never a list entry)
-            if (jj[u] != q && r2 < c.rc2)
-                pair_term<PREC, ENERGY>(c, dx, dy, dz, r2, acc, ue, w0, w1, w2, w3, w4, w5);
+                for (int v = 0; v < FORCE_BATCH; ++v) {
+                    const int u = u0 + v;
+                    pv[v] = k0 + u < cnt && e[u] < t.total;
+                    const int idx = pv[v] ? e[u] : 0;
+                    pt[v] = 0;
+                    if (STAGED) {
+                        px[v] = sx[idx];
+                        py[v] = sy[idx];
+                        pz[v] = sz[idx];
+                        if (MULTI) pt[v] = sty[idx];
+                    } else {
+                        const double4 pj = a.pos_in[tile_global(t, idx)];
+                        px[v] = pj.x;
+                        py[v] = pj.y;
+                        pz[v] = pj.z;
+                        pt[v] = (int)pj.w;
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < FORCE_BATCH; ++v) {
+                    const double dx = mi_rint(px[v] - xi.x, L0, iL0);
+                    const double dy = mi_rint(py[v] - xi.y, L1, iL1);
+                    const double dz = mi_rint(pz[v] - xi.z, L2, iL2);
+                    const double r2 = r2_canon(dx, dy, dz);
+                    const PairCoef &c = MULTI ? s_pair[ti * a.ntypes + pt[v]] : a.single;
+                    if (pv[v] && r2 < c.rc2)
+                        pair_term<PREC, ENERGY>(c, dx, dy, dz, r2, acc, ue, w0, w1, w2, w3, w4, w5);
+                }
+            }
+        }
+
+        double fx, fy, fz;
+        if (PREC == PREC_FP64) {
+            fx = lane_sum<TPP>((double)acc.fx);
+            fy = lane_sum<TPP>((double)acc.fy);
+            fz = lane_sum<TPP>((double)acc.fz);
+        } else {
+            fx = (double)lane_sum<TPP>((float)acc.fx);
+            fy = (double)lane_sum<TPP>((float)acc.fy);
+            fz = (double)lane_sum<TPP>((float)acc.fz);
+        }
+        if (ENERGY) {
+            ue = lane_sum<TPP>(ue);
+            w0 = lane_sum<TPP>(w0);
+            w1 = lane_sum<TPP>(w1);
+            w2 = lane_sum<TPP>(w2);
+            w3 = lane_sum<TPP>(w3);
+            w4 = lane_sum<TPP>(w4);
+            w5 = lane_sum<TPP>(w5);
+        }
+        bool exceed = false;
+        if (active && lane == 0) {
+            const bool finite =
+                __builtin_isfinite(fx) && __builtin_isfinite(fy) && __builtin_isfinite(fz);
+            if (!finite) atomicOr(a.status, ST_NONFINITE);
+            if (ENERGY) {
+                a.u_out[q] = ue;
+                double *w = a.w_out + 6 * (size_t)q;
+                w[0] = w0; w[1] = w1; w[2] = w2; w[3] = w3; w[4] = w4; w[5] = w5;
+            }
+            if (MODE == MODE_EVAL) {
+                a.force[q] = make_double4(fx, fy, fz, 0.0);
+            } else {
+                double4 v = v_pre;
+                const double hm = a.half_dt * v.w;
+                // second half kick of the current step: full-step velocity
+                v.x = __builtin_fma(hm, fx, v.x);
+                v.y = __builtin_fma(hm, fy, v.y);
+                v.z = __builtin_fma(hm, fz, v.z);
+                if (MODE == MODE_FINAL) {
+                    a.vel[q] = v;
+                    a.force[q] = make_double4(fx, fy, fz, 0.0);
+                } else {
+                    if (ENERGY) {
+                        const double m = 1.0 / v.w;
+                        a.ke_out[q] = 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+                    }
+                    // first half kick and drift of the next step
+                    v.x = __builtin_fma(hm, fx, v.x);
+                    v.y = __builtin_fma(hm, fy, v.y);
+                    v.z = __builtin_fma(hm, fz, v.z);
+                    double4 x = xi;
+                    x.x = __builtin_fma(a.dt, v.x, x.x);
+                    x.y = __builtin_fma(a.dt, v.y, x.y);
+                    x.z = __builtin_fma(a.dt, v.z, x.z);
+                    int4 im = im_pre;
+                    const int4 im0 = im;
+                    wrap_coord(x.x, im.x, L0);
+                    wrap_coord(x.y, im.y, L1);
+                    wrap_coord(x.z, im.z, L2);
+                    a.pos_out[q] = x;
+                    a.vel[q] = v;
+                    if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
+                    const double ex = mi_rint(x.x - b_pre.x, L0, iL0);
+                    const double ey = mi_rint(x.y - b_pre.y, L1, iL1);
+                    const double ez = mi_rint(x.z - b_pre.z, L2, iL2);
+                    exceed = r2_canon(ex, ey, ez) >= a.lim2;
+                }
+            }
+        }
+        if (MODE == MODE_FUSED) {
+            const unsigned long long vote = __ballot(exceed);
+            if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1)
+                atomicOr(a.rebuild_set, 1);
         }
     }
+}
 
-    double fx, fy, fz;
-    if (PREC == PREC_FP64) {
-        fx = lane_sum<TPP>((double)acc.fx);
-        fy = lane_sum<TPP>((double)acc.fy);
-        fz = lane_sum<TPP>((double)acc.fz);
-    } else {
-        fx = (double)lane_sum<TPP>((float)acc.fx);
-        fy = (double)lane_sum<TPP>((float)acc.fy);
-        fz = (double)lane_sum<TPP>((float)acc.fz);
-    }
-    if (ENERGY) {
-        ue = lane_sum<TPP>(ue);
-        w0 = lane_sum<TPP>(w0);
-        w1 = lane_sum<TPP>(w1);
-        w2 = lane_sum<TPP>(w2);
-        w3 = lane_sum<TPP>(w3);
-        w4 = lane_sum<TPP>(w4);
-        w5 = lane_sum<TPP>(w5);
-    }
-    if (lane != 0) return;
+// One workgroup per brick. The brick's tile (the atoms of its halo cells, FP64 structure of
+// arrays) is staged in LDS; TPP lanes per particle of the brick stride through the
+// particle's list of 16-bit tile indices, 8 per 16-byte load, gathering neighbour
+// positions from LDS. Forces are reduced across the lanes with wavefront shuffles; lane 0
+// then finishes the particle according to MODE. If a tile is larger than the LDS
+// allocation, the positions are read from global memory through the tile offsets instead.
+template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI>
+__global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
+    extern __shared__ double dyn_smem[];
+    __shared__ TileSmem t;
+    double *sx = dyn_smem;
+    double *sy = sx + a.tile_cap;
+    double *sz = sy + a.tile_cap;
+    int *sty = reinterpret_cast<int *>(sz + a.tile_cap);
+    PairCoef *s_pair = reinterpret_cast<PairCoef *>(sz + a.tile_cap + (a.tile_cap + 1) / 2);
+    if (MULTI)
+        for (int k = threadIdx.x; k < a.ntypes * a.ntypes; k += blockDim.x) s_pair[k] = a.pair[k];
+    if (MODE == MODE_FUSED && blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild_clear = 0;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const BrickInfo bi = a.bricks[b];
+    tile_setup(bi, a.halo + (size_t)b * HALO_MAX, a.cell_start, t);
+    const bool staged = t.total <= a.tile_cap;
+    if (staged) tile_stage<MULTI>(t, a.pos_in, sx, sy, sz, sty);
 
-    const bool finite = __builtin_isfinite(fx) && __builtin_isfinite(fy) && __builtin_isfinite(fz);
-    if (!finite) atomicOr(a.status, ST_NONFINITE);
-    if (ENERGY) {
-        a.u_out[q] = ue;
-        double *w = a.w_out + 6 * (size_t)q;
-        w[0] = w0; w[1] = w1; w[2] = w2; w[3] = w3; w[4] = w4; w[5] = w5;
-    }
-    if (MODE == MODE_EVAL) {
-        a.force[q] = make_double4(fx, fy, fz, 0.0);
-        return;
-    }
-    double4 v = v_pre;
-    const double hm = a.half_dt * v.w;
-    // second half kick of the current step: full-step velocity
-    v.x = __builtin_fma(hm, fx, v.x);
-    v.y = __builtin_fma(hm, fy, v.y);
-    v.z = __builtin_fma(hm, fz, v.z);
-    if (MODE == MODE_FINAL) {
-        a.vel[q] = v;
-        a.force[q] = make_double4(fx, fy, fz, 0.0);
-        return;
-    }
-    if (ENERGY) {
-        const double m = 1.0 / v.w;
-        a.ke_out[q] = 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
-    }
-    // first half kick and drift of the next step
-    v.x = __builtin_fma(hm, fx, v.x);
-    v.y = __builtin_fma(hm, fy, v.y);
-    v.z = __builtin_fma(hm, fz, v.z);
-    double4 x = xi;
-    x.x = __builtin_fma(a.dt, v.x, x.x);
-    x.y = __builtin_fma(a.dt, v.y, x.y);
-    x.z = __builtin_fma(a.dt, v.z, x.z);
-    int4 im = im_pre;
-    const int4 im0 = im;
-    wrap_coord(x.x, im.x, L0);
-    wrap_coord(x.y, im.y, L1);
-    wrap_coord(x.z, im.z, L2);
-    a.pos_out[q] = x;
-    a.vel[q] = v;
-    if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
-    const double4 b = b_pre;
-    const double ex = mi_rint(x.x - b.x, L0, iL0);
-    const double ey = mi_rint(x.y - b.y, L1, iL1);
-    const double ez = mi_rint(x.z - b.z, L2, iL2);
-    const bool exceed = r2_canon(ex, ey, ez) >= a.lim2;
-    const unsigned long long vote = __ballot(exceed);
-    if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1) atomicOr(a.rebuild_set, 1);
+    const int first = a.cell_start[bi.first_cell];
+    const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
+    if (staged)
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true>(a, t, sx, sy, sz, sty, s_pair, first,
+                                                           natoms);
+    else
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, false>(a, t, sx, sy, sz, sty, s_pair, first,
+                                                            natoms);
 }
 
 template <int PREC, int TPP, int MODE, bool ENERGY>
 static hipError_t launch_force_t(hipStream_t s, const ForceArgs &a, int block) {
-    size_t threads = (size_t)a.n * TPP;
-    int grid = (int)((threads + block - 1) / block);
-    if (grid < 1) grid = 1;
+    const size_t smem = force_lds_bytes(a.tile_cap, a.ntypes);
     if (a.ntypes > 1)
-        hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, true>), dim3(grid), dim3(block), 0,
-                           s, a);
+        hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, true>), dim3(a.nbrick), dim3(block),
+                           smem, s, a);
     else
-        hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, false>), dim3(grid), dim3(block),
-                           0, s, a);
+        hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, false>), dim3(a.nbrick), dim3(block),
+                           smem, s, a);
     return hipGetLastError();
 }
 
@@ -439,7 +565,7 @@ static hipError_t launch_force_p(hipStream_t s, const ForceArgs &a, int tpp, int
 
 hipError_t launch_force(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
                         bool energy, int block) {
-    if (block < 64 || block > 256 || (block & 63)) return hipErrorInvalidValue;
+    if (block < 64 || block > 512 || (block & 63)) return hipErrorInvalidValue;
     return prec == PREC_MIXED ? launch_force_p<PREC_MIXED>(s, a, tpp, mode, energy, block)
                               : launch_force_p<PREC_FP64>(s, a, tpp, mode, energy, block);
 }
@@ -589,97 +715,39 @@ __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
 
 // ---------------------------------------------------------------- rebuild: Verlet list
 
-// One wavefront per cell (grid-stride over cells in XCD-contiguous order). The cell's
-// particles are split into groups of L lanes, L = 64 / (particles in the cell) clamped to
-// [1, 32], so nearly every lane has work. Each group walks the atoms of the 27 stencil
-// cells (their distinct cells when an axis has fewer than 3) L at a time and appends every
-// j != i with r^2 < (r_cut + skin)^2. All groups read the same candidates at the same time,
-// so the position loads coalesce. Appends of one group are compacted with a wavefront
-// ballot: the entry order (stencil cell, then index) is deterministic. The wavefront also
-// copies its particles' permuted state back into the main arrays and records the build
-// positions.
-//
-// Distances: for an axis with at least 3 cells the periodic image of a stencil cell is
-// known, and fl(fl(x_j - x_i) + s) with s in {-L, 0, L} equals the branch-form minimum
-// image bit for bit for every pair that can be listed; cells away from the box faces need
-// no shift at all. With fewer than 3 cells on some axis the branch form is applied.
-template <bool MULTI>
-__device__ __forceinline__ double rl2_of(const RebuildArgs &a, const double *s_rl2, int ti,
-                                         int tj) {
-    return MULTI ? s_rl2[ti * a.ntypes + tj] : a.single_rl2;
-}
-
-template <bool MULTI>
-__global__ void __launch_bounds__(64) k_nlist(const RebuildArgs a) {
-    if (*a.go == 0) return;
-    __shared__ int s_start[27], s_cnt[27], s_rank[27], s_has[27];
-    __shared__ double s_shift[81];
-    __shared__ int s_ns, s_interior;
-    __shared__ double s_rl2[MULTI ? LJMD_MAX_TYPES_DEV * LJMD_MAX_TYPES_DEV : 1];
-    if (MULTI) {
-        const int nt2 = a.ntypes * a.ntypes;
-        for (int t = threadIdx.x; t < nt2; t += blockDim.x) s_rl2[t] = a.rl2_table[t];
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->builds, 1ull);
-    const int wl = threadIdx.x;  // one wavefront
+// The cells of one brick, one wavefront per cell; STAGED selects candidate positions from
+// the LDS tile (plain LDS reads) or, for a tile larger than the LDS allocation, from global
+// memory.
+template <bool MULTI, bool STAGED>
+__device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem &t,
+                                            const BrickInfo &bi, const double *__restrict__ sx,
+                                            const double *__restrict__ sy,
+                                            const double *__restrict__ sz,
+                                            const int *__restrict__ sty, const double *s_rl2,
+                                            int &my_max, unsigned long long &my_entries) {
+    const int hy = (bi.dims >> 4) & 15, hz = (bi.dims >> 8) & 15;
+    const int fpk = a.cell_xyz[bi.first_cell];
+    const int wl = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nwave = blockDim.x >> 6;
     const unsigned long long below = (1ull << wl) - 1ull;
-    int my_max = 0;
-    unsigned long long my_entries = 0ull;
-
-    for (int cell = xcd_remap(blockIdx.x, gridDim.x); cell < a.ncell; cell += gridDim.x) {
-        __syncthreads();  // the previous cell's stencil is no longer read
-        if (wl < 27) {
-            const int packed = a.cell_xyz[cell];
-            const int cxyz[3] = {packed & 1023, (packed >> 10) & 1023, (packed >> 20) & 1023};
-            const int o[3] = {wl / 9 - 1, (wl / 3) % 3 - 1, wl % 3 - 1};
-            int e[3];
-            int has = 0;
-            for (int d = 0; d < 3; ++d) {
-                int v = cxyz[d] + o[d];
-                double sh = 0.0;
-                if (v < 0) { v += a.nc[d]; sh = -a.L[d]; has = 1; }
-                else if (v >= a.nc[d]) { v -= a.nc[d]; sh = a.L[d]; has = 1; }
-                e[d] = v;
-                s_shift[3 * wl + d] = sh;
-            }
-            const int r = a.cell_rank[(e[0] * a.nc[1] + e[1]) * a.nc[2] + e[2]];
-            s_rank[wl] = r;
-            s_has[wl] = has;
-            s_start[wl] = a.cell_start[r];
-            s_cnt[wl] = a.cell_start[r + 1] - a.cell_start[r];
-        }
-        __syncthreads();
-        if (wl == 0) {
-            int ns = 27, any = 0;
-            if (a.canonical_mi) {
-                // fewer than 3 cells on some axis: keep the first occurrence of each cell
-                ns = 0;
-                for (int t = 0; t < 27; ++t) {
-                    bool dup = false;
-                    for (int u = 0; u < t; ++u) dup |= (s_rank[u] == s_rank[t]);
-                    if (dup) continue;
-                    s_start[ns] = s_start[t];
-                    s_cnt[ns] = s_cnt[t];
-                    ++ns;
-                }
-            } else {
-                for (int t = 0; t < 27; ++t) any |= s_has[t];
-            }
-            s_ns = ns;
-            s_interior = (!a.canonical_mi && !any) ? 1 : 0;
-        }
-        __syncthreads();
-        const int ns = s_ns;
-        const bool interior = s_interior != 0;
-        const int beg = a.cell_start[cell];
-        const int cnt = a.cell_start[cell + 1] - beg;
+    const int nst = a.canonical_mi ? t.nhalo : 27;
+    for (int ci = wave; ci < bi.ncell; ci += nwave) {
+        const int rank = bi.first_cell + ci;
+        const int pk = a.cell_xyz[rank];
+        const int lx = (pk & 1023) - (fpk & 1023);
+        const int ly = ((pk >> 10) & 1023) - ((fpk >> 10) & 1023);
+        const int lz = ((pk >> 20) & 1023) - ((fpk >> 20) & 1023);
+        const int beg = a.cell_start[rank];
+        const int cnt = a.cell_start[rank + 1] - beg;
         if (cnt == 0) continue;
-        int L = 64 / cnt;
-        L = L < 1 ? 1 : (L > 32 ? 32 : L);
-        const int G = 64 / L;
-        const int group = wl / L;
-        const int lane = wl - group * L;
-        const unsigned long long gmask = group < G ? (((1ull << L) - 1ull) << (group * L)) : 0ull;
+        int Ln = 64 / cnt;
+        Ln = Ln < 1 ? 1 : (Ln > 32 ? 32 : Ln);
+        const int G = 64 / Ln;
+        const int group = wl / Ln;
+        const int lane = wl - group * Ln;
+        const unsigned long long gmask =
+            group < G ? (((1ull << Ln) - 1ull) << (group * Ln)) : 0ull;
         for (int p0 = 0; p0 < cnt; p0 += G) {
             const int p = p0 + group;
             const bool active = group < G && p < cnt;
@@ -687,32 +755,53 @@ __global__ void __launch_bounds__(64) k_nlist(const RebuildArgs a) {
             const double4 xi = a.pos_scr[q];
             const int ti = MULTI ? (int)xi.w : 0;
             int count = 0;
-            for (int c = 0; c < ns; ++c) {
-                const int m = s_cnt[c];
-                const int jb = s_start[c];
-                const double sx = s_shift[3 * c], sy = s_shift[3 * c + 1], sz = s_shift[3 * c + 2];
-                for (int t0 = 0; t0 < m; t0 += L) {
-                    const int t = t0 + lane;
-                    const bool valid = active && t < m;
-                    const int j = jb + (valid ? t : 0);
-                    const double4 xj = a.pos_scr[j];
-                    double dx = xj.x - xi.x, dy = xj.y - xi.y, dz = xj.z - xi.z;
+            for (int s = 0; s < nst; ++s) {
+                const int h = a.canonical_mi
+                                  ? s
+                                  : ((lx + s / 9) * hy + (ly + (s / 3) % 3)) * hz + (lz + s % 3);
+                const int o = t.off[h];
+                const int m = t.off[h + 1] - o;
+                const int jst = t.start[h];
+                const int code = t.shift[h];
+                const bool shifted = !a.canonical_mi && code != 21;  // 21: no shift on any axis
+                const double shx = (double)((code & 3) - 1) * a.L[0];
+                const double shy = (double)(((code >> 2) & 3) - 1) * a.L[1];
+                const double shz = (double)(((code >> 4) & 3) - 1) * a.L[2];
+                for (int t0 = 0; t0 < m; t0 += Ln) {
+                    const int tt = t0 + lane;
+                    const bool valid = active && tt < m;
+                    const int tv = valid ? tt : 0;
+                    double xjx, xjy, xjz;
+                    int tj = 0;
+                    if (STAGED) {
+                        xjx = sx[o + tv];
+                        xjy = sy[o + tv];
+                        xjz = sz[o + tv];
+                        if (MULTI) tj = sty[o + tv];
+                    } else {
+                        const double4 pj = a.pos_scr[jst + tv];
+                        xjx = pj.x;
+                        xjy = pj.y;
+                        xjz = pj.z;
+                        tj = (int)pj.w;
+                    }
+                    double dx = xjx - xi.x, dy = xjy - xi.y, dz = xjz - xi.z;
                     if (a.canonical_mi) {
                         dx = mi_branch(dx, a.L[0]);
                         dy = mi_branch(dy, a.L[1]);
                         dz = mi_branch(dz, a.L[2]);
-                    } else if (!interior) {
-                        dx = dx + sx;  // adding 0.0 is exact
-                        dy = dy + sy;
-                        dz = dz + sz;
+                    } else if (shifted) {
+                        dx = dx + shx;  // adding 0.0 is exact
+                        dy = dy + shy;
+                        dz = dz + shz;
                     }
                     const double r2 = r2_canon(dx, dy, dz);
-                    const bool hit = valid && j != q &&
-                                     r2 < rl2_of<MULTI>(a, s_rl2, ti, MULTI ? (int)xj.w : 0);
+                    const double rl2 = MULTI ? s_rl2[ti * a.ntypes + tj] : a.single_rl2;
+                    const bool hit = valid && (jst + tt) != q && r2 < rl2;
                     const unsigned long long bal = __ballot(hit) & gmask;
                     if (hit) {
                         const int k = count + __popcll(bal & below);
-                        if (k < a.cap) a.nlist[nl_slot(q, k, a.npad, a.lshift)] = j;
+                        if (k < a.cap) a.nlist[nl_slot(q, k, a.npad, a.lshift)] = (uint16_t)(o + tt);
                     }
                     count += __popcll(bal);
                 }
@@ -722,15 +811,73 @@ __global__ void __launch_bounds__(64) k_nlist(const RebuildArgs a) {
                 if (count > a.cap) atomicOr(&a.st->status, ST_OVERFLOW);
                 my_max = count > my_max ? count : my_max;
                 my_entries += (unsigned long long)(count < a.cap ? count : a.cap);
-                // the permuted state becomes the main state; this is the new build point
-                a.pos[q] = xi;
-                a.xb[q] = xi;
-                a.vel[q] = a.vel_scr[q];
-                a.img[q] = a.img_scr[q];
             }
         }
     }
-    // wavefront reductions of the build statistics, one atomic each per workgroup
+}
+
+// One workgroup per brick: the brick's tile (its halo cells' atoms at the new sorted order)
+// is staged in LDS, then each wavefront takes the brick's cells in turn. A cell's particles
+// are split into groups of L lanes, L = 64 / (particles in the cell) clamped to [1, 32],
+// so nearly every lane has work. Each group walks the atoms of the particle's 27 stencil
+// cells (the brick's distinct halo cells when an axis has fewer than 3 cells) L at a time,
+// reading them from LDS (all groups read the same atoms at once), and appends the tile index
+// of every j != i with r^2 < (r_cut + skin)^2. Appends of one group are compacted with a
+// wavefront ballot, so the entry order (stencil cell, then index) is deterministic. The
+// workgroup also copies its particles' permuted state back into the main arrays and records
+// the build positions.
+//
+// Distances: for an axis with at least 3 cells the periodic image of a halo cell is known,
+// and fl(fl(x_j - x_i) + s) with s in {-L, 0, L} equals the branch-form minimum image bit
+// for bit for every pair that can be listed; unshifted halo cells need no addition at all.
+// With fewer than 3 cells on some axis the branch form is applied directly.
+template <bool MULTI>
+__global__ void __launch_bounds__(256) k_nlist(const RebuildArgs a) {
+    if (*a.go == 0) return;
+    extern __shared__ double dyn_smem[];
+    __shared__ TileSmem t;
+    double *sx = dyn_smem;
+    double *sy = sx + a.tile_cap;
+    double *sz = sy + a.tile_cap;
+    int *sty = reinterpret_cast<int *>(sz + a.tile_cap);
+    double *s_rl2 = sz + a.tile_cap + (a.tile_cap + 1) / 2;
+    if (MULTI)
+        for (int k = threadIdx.x; k < a.ntypes * a.ntypes; k += blockDim.x) s_rl2[k] = a.rl2_table[k];
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->builds, 1ull);
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const BrickInfo bi = a.bricks[b];
+    tile_setup(bi, a.halo + (size_t)b * HALO_MAX, a.cell_start, t);
+    // the permuted state of the brick's particles becomes the main state and the new build
+    // point (coalesced copy; tile staging below reads pos_scr, not pos)
+    {
+        const int first = a.cell_start[bi.first_cell];
+        const int last = a.cell_start[bi.first_cell + bi.ncell];
+        for (int q = first + (int)threadIdx.x; q < last; q += blockDim.x) {
+            const double4 x = a.pos_scr[q];
+            a.pos[q] = x;
+            a.xb[q] = x;
+            a.vel[q] = a.vel_scr[q];
+            a.img[q] = a.img_scr[q];
+        }
+        if (t.total > TILE_INDEX_MAX) {
+            // 16-bit tile indices cannot address this tile: no list for the brick
+            for (int q = first + (int)threadIdx.x; q < last; q += blockDim.x) a.nl_count[q] = 0;
+            if (threadIdx.x == 0) atomicOr(&a.st->status, ST_TILE);
+            return;
+        }
+    }
+    const bool staged = t.total <= a.tile_cap;
+    if (staged) tile_stage<MULTI>(t, a.pos_scr, sx, sy, sz, sty);
+
+    const int wl = threadIdx.x & 63;
+    int my_max = 0;
+    unsigned long long my_entries = 0ull;
+    if (staged)
+        nlist_cells<MULTI, true>(a, t, bi, sx, sy, sz, sty, s_rl2, my_max, my_entries);
+    else
+        nlist_cells<MULTI, false>(a, t, bi, sx, sy, sz, sty, s_rl2, my_max, my_entries);
+
+    // wavefront reductions of the build statistics, one atomic each per wavefront
     for (int o = 32; o > 0; o >>= 1) {
         const int om = __shfl_xor(my_max, o);
         my_max = om > my_max ? om : my_max;
@@ -742,6 +889,27 @@ __global__ void __launch_bounds__(64) k_nlist(const RebuildArgs a) {
     }
 }
 
+// Global indices of every list entry (for inspection): out[q * cap + k].
+__global__ void __launch_bounds__(256) k_decode_list(const RebuildArgs a, int *out) {
+    __shared__ TileSmem t;
+    const BrickInfo bi = a.bricks[blockIdx.x];
+    tile_setup(bi, a.halo + (size_t)blockIdx.x * HALO_MAX, a.cell_start, t);
+    const int first = a.cell_start[bi.first_cell];
+    const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
+    for (int p = threadIdx.x; p < natoms; p += blockDim.x) {
+        const int q = first + p;
+        int cnt = a.nl_count[q];
+        cnt = cnt < a.cap ? cnt : a.cap;
+        for (int k = 0; k < cnt; ++k)
+            out[(size_t)q * a.cap + k] = tile_global(t, a.nlist[nl_slot(q, k, a.npad, a.lshift)]);
+    }
+}
+
+hipError_t launch_decode_list(hipStream_t s, const RebuildArgs &a, int *out) {
+    hipLaunchKernelGGL(k_decode_list, dim3(a.nbrick), dim3(256), 0, s, a, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
     const int b = 256;
     const int g = (a.n + b - 1) / b;
@@ -749,11 +917,11 @@ hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(b), 0, s, a);
     hipLaunchKernelGGL(k_cell_gather, dim3(a.ncell < 8192 ? a.ncell : 8192), dim3(64), 0, s, a);
-    const int gn = a.ncell < NL_GRID ? a.ncell : NL_GRID;
+    const size_t smem = nlist_lds_bytes(a.tile_cap, a.ntypes);
     if (a.ntypes > 1)
-        hipLaunchKernelGGL(k_nlist<true>, dim3(gn), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_nlist<true>, dim3(a.nbrick), dim3(256), smem, s, a);
     else
-        hipLaunchKernelGGL(k_nlist<false>, dim3(gn), dim3(64), 0, s, a);
+        hipLaunchKernelGGL(k_nlist<false>, dim3(a.nbrick), dim3(256), smem, s, a);
     return hipGetLastError();
 }
 

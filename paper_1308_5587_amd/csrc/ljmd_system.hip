@@ -100,8 +100,14 @@ struct ljmd_system {
             *d_force = nullptr, *d_xb = nullptr;
     int4 *d_img = nullptr, *d_img_scr = nullptr;
     int *d_key = nullptr, *d_slot = nullptr, *d_perm = nullptr;
-    int *d_count = nullptr, *d_nlist = nullptr;
+    int *d_count = nullptr;
+    uint16_t *d_nlist = nullptr;
     int cap = 0;
+    BrickInfo *d_bricks = nullptr;
+    HaloCell *d_halo = nullptr;
+    int nbrick = 0, nbrick_alloc = 0, tile_cap = 0;
+    bool canonical = false;
+    size_t lds_limit = 64 * 1024;
     size_t nlist_alloc = 0;
     double *d_u = nullptr, *d_w = nullptr, *d_ke = nullptr, *d_partials = nullptr,
            *d_red = nullptr;
@@ -245,21 +251,111 @@ int setup_table(ljmd_system *s) {
         CHK(dalloc_t(s, &s->d_cell_start, ncell + 1));
         s->ncell_alloc = ncell;
     }
-    // Morton order of the cells
-    std::vector<std::pair<uint64_t, int>> mort(ncell);
-    for (int x = 0; x < nc[0]; ++x)
-        for (int y = 0; y < nc[1]; ++y)
-            for (int z = 0; z < nc[2]; ++z) {
-                const int lin = (x * nc[1] + y) * nc[2] + z;
-                mort[lin] = {spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), lin};
+    // Bricks of up to 2 x 2 x 2 cells (one cell wide on an axis with fewer than 4 cells,
+    // single cells when some axis has fewer than 3), bricks in Morton order, cells in
+    // Morton order inside their brick: every brick is a contiguous range of cell ranks.
+    const bool canonical = nc[0] < 3 || nc[1] < 3 || nc[2] < 3;
+    int ext[3], nb[3];
+    for (int a = 0; a < 3; ++a) {
+        ext[a] = (!canonical && nc[a] >= 4) ? 2 : 1;
+        nb[a] = (nc[a] + ext[a] - 1) / ext[a];
+    }
+    const int nbrick = nb[0] * nb[1] * nb[2];
+    std::vector<std::pair<uint64_t, int>> bmort(nbrick);
+    for (int x = 0; x < nb[0]; ++x)
+        for (int y = 0; y < nb[1]; ++y)
+            for (int z = 0; z < nb[2]; ++z) {
+                const int lin = (x * nb[1] + y) * nb[2] + z;
+                bmort[lin] = {spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), lin};
             }
-    std::sort(mort.begin(), mort.end());
+    std::sort(bmort.begin(), bmort.end());
     std::vector<int> rank(ncell), xyz(ncell);
-    for (int r = 0; r < ncell; ++r) {
-        const int lin = mort[r].second;
-        rank[lin] = r;
-        const int z = lin % nc[2], y = (lin / nc[2]) % nc[1], x = lin / (nc[1] * nc[2]);
-        xyz[r] = x | (y << 10) | (z << 20);
+    std::vector<BrickInfo> bricks(nbrick);
+    std::vector<int> brick_lo(3 * nbrick), brick_n(3 * nbrick);
+    int next = 0;
+    for (int bo = 0; bo < nbrick; ++bo) {
+        const int lin = bmort[bo].second;
+        const int bz = lin % nb[2], by = (lin / nb[2]) % nb[1], bx = lin / (nb[1] * nb[2]);
+        const int lo[3] = {bx * ext[0], by * ext[1], bz * ext[2]};
+        int cn[3];
+        for (int a = 0; a < 3; ++a) cn[a] = std::min(ext[a], nc[a] - lo[a]);
+        BrickInfo &bi = bricks[bo];
+        bi.first_cell = next;
+        bi.ncell = 0;
+        for (int c = 0; c < 8; ++c) {
+            const int l[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+            if (l[0] >= cn[0] || l[1] >= cn[1] || l[2] >= cn[2]) continue;
+            const int x = lo[0] + l[0], y = lo[1] + l[1], z = lo[2] + l[2];
+            rank[(x * nc[1] + y) * nc[2] + z] = next;
+            xyz[next] = x | (y << 10) | (z << 20);
+            ++next;
+            ++bi.ncell;
+        }
+        for (int a = 0; a < 3; ++a) {
+            brick_lo[3 * bo + a] = lo[a];
+            brick_n[3 * bo + a] = cn[a];
+        }
+    }
+    // halo of each brick: cells lo-1 .. lo+n per axis, seen in the periodic image given by
+    // the wrap; duplicates (fewer than 3 cells on an axis) keep their first occurrence
+    std::vector<HaloCell> halo((size_t)nbrick * HALO_MAX);
+    int max_halo = 0;
+    for (int bo = 0; bo < nbrick; ++bo) {
+        BrickInfo &bi = bricks[bo];
+        int hd[3];
+        for (int a = 0; a < 3; ++a) hd[a] = brick_n[3 * bo + a] + 2;
+        bi.dims = hd[0] | (hd[1] << 4) | (hd[2] << 8) | (brick_n[3 * bo] << 12) |
+                  (brick_n[3 * bo + 1] << 16) | (brick_n[3 * bo + 2] << 20);
+        int nh = 0;
+        for (int hx = 0; hx < hd[0]; ++hx)
+            for (int hy = 0; hy < hd[1]; ++hy)
+                for (int hz = 0; hz < hd[2]; ++hz) {
+                    const int hc[3] = {hx, hy, hz};
+                    int e[3], code = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        int v = brick_lo[3 * bo + a] + hc[a] - 1;
+                        int sh = 0;
+                        if (v < 0) { v += nc[a]; sh = -1; }
+                        else if (v >= nc[a]) { v -= nc[a]; sh = 1; }
+                        e[a] = v;
+                        code |= (sh + 1) << (2 * a);
+                    }
+                    const int r = rank[(e[0] * nc[1] + e[1]) * nc[2] + e[2]];
+                    bool dup = false;
+                    if (canonical)
+                        for (int u = 0; u < nh; ++u) dup |= halo[(size_t)bo * HALO_MAX + u].rank == r;
+                    if (dup) continue;
+                    halo[(size_t)bo * HALO_MAX + nh] = HaloCell{r, code};
+                    ++nh;
+                }
+        bi.nhalo = nh;
+        max_halo = std::max(max_halo, nh);
+    }
+    if (nbrick > s->nbrick_alloc) {
+        dfree(s, s->d_bricks);
+        dfree(s, s->d_halo);
+        CHK(dalloc_t(s, &s->d_bricks, nbrick));
+        CHK(dalloc_t(s, &s->d_halo, (size_t)nbrick * HALO_MAX));
+        s->nbrick_alloc = nbrick;
+    }
+    HIPCHK(hipMemcpyAsync(s->d_bricks, bricks.data(), sizeof(BrickInfo) * nbrick,
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_halo, halo.data(), sizeof(HaloCell) * (size_t)nbrick * HALO_MAX,
+                          hipMemcpyHostToDevice, s->stream));
+    s->nbrick = nbrick;
+    s->canonical = canonical;
+    // LDS tile capacity: the expected halo occupancy with headroom, within the LDS a
+    // workgroup may use (larger tiles are read from global memory instead)
+    {
+        const double per_cell = (double)s->n / ncell;
+        const double expect = max_halo * per_cell;
+        int cap = (int)std::ceil(1.35 * expect + 128.0);
+        cap = (cap + 63) & ~63;
+        cap = std::min(cap, TILE_MAX);
+        const size_t limit = std::min<size_t>(s->lds_limit, 64 * 1024) - 4096;
+        while (cap > 64 && std::max(force_lds_bytes(cap, s->ntypes), nlist_lds_bytes(cap, s->ntypes)) > limit)
+            cap -= 64;
+        s->tile_cap = cap;
     }
     HIPCHK(hipMemcpyAsync(s->d_cell_rank, rank.data(), sizeof(int) * ncell,
                           hipMemcpyHostToDevice, s->stream));
@@ -277,9 +373,10 @@ int setup_table(ljmd_system *s) {
 }
 
 int ensure_list_alloc(ljmd_system *s, int cap) {
-    // a multiple of 64 (4 entries x up to 16 lanes) keeps every slot of k < cap inside
-    // cap * npad for every lane count
-    cap = std::max(64, (cap + 63) & ~63);
+    // a multiple of 8 x lanes per particle (whole chunks of 8 entries per lane) keeps every
+    // slot of k < cap inside cap * npad
+    const int unit = 8 << s->lshift;
+    cap = std::max(unit, (cap + unit - 1) / unit * unit);
     const size_t need = (size_t)cap * (size_t)s->npad;
     if (need > s->nlist_alloc) {
         dfree(s, s->d_nlist);
@@ -293,11 +390,7 @@ int ensure_list_alloc(ljmd_system *s, int cap) {
     return LJMD_OK;
 }
 
-int round_cap(double v) {
-    int c = (int)std::ceil(v);
-    c = (c + 63) & ~63;
-    return std::max(c, 64);
-}
+int round_cap(double v) { return std::max(8, (int)std::ceil(v)); }
 
 // ------------------------------------------------------------ argument blocks
 
@@ -336,7 +429,11 @@ RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
     a.cap = s->cap;
     a.lshift = s->lshift;
     a.ntypes = s->ntypes;
-    a.canonical_mi = (s->nc[0] < 3 || s->nc[1] < 3 || s->nc[2] < 3) ? 1 : 0;
+    a.canonical_mi = s->canonical ? 1 : 0;
+    a.bricks = s->d_bricks;
+    a.halo = s->d_halo;
+    a.nbrick = s->nbrick;
+    a.tile_cap = s->tile_cap;
     return a;
 }
 
@@ -350,6 +447,11 @@ ForceArgs force_args(ljmd_system *s, int cur) {
     a.force = s->d_force;
     a.nl_count = s->d_count;
     a.nlist = s->d_nlist;
+    a.bricks = s->d_bricks;
+    a.halo = s->d_halo;
+    a.cell_start = s->d_cell_start;
+    a.nbrick = s->nbrick;
+    a.tile_cap = s->tile_cap;
     a.u_out = s->d_u;
     a.w_out = s->d_w;
     a.ke_out = s->d_ke;
@@ -437,6 +539,10 @@ int build_list(ljmd_system *s) {
         CHK(enqueue_forced_rebuild(s));
         DevStatus st{};
         CHK(sync_status(s, &st));
+        if (st.status & ST_TILE)
+            return set_err(LJMD_E_BOX, "a brick holds more than %d atoms in its halo cells: "
+                                       "particle density too high for 16-bit tile indices",
+                           TILE_INDEX_MAX);
         if (!(st.status & ST_OVERFLOW)) {
             s->list_valid = true;
             s->force_valid = false;
@@ -506,20 +612,22 @@ int tune(ljmd_system *s) {
             s->tpp = want_tpp ? want_tpp : it->second.first;
             s->block = want_block ? want_block : it->second.second;
             for (s->lshift = 0; (1 << s->lshift) < s->tpp; ++s->lshift) {}
+            if (s->cap) CHK(ensure_list_alloc(s, s->cap));
             s->list_valid = false;
             return LJMD_OK;
         }
     }
-    const int tpps[] = {1, 2, 4, 8, 16};
-    const int blocks[] = {64, 128, 256};
+    const int tpps[] = {1, 2, 4, 8};
+    const int blocks[] = {128, 256, 512};
     double best = 1e30;
     int bt = 4, bb = 128;
     for (int t : tpps) {
         if (want_tpp && t != want_tpp) continue;
         s->tpp = t;
         for (s->lshift = 0; (1 << s->lshift) < t; ++s->lshift) {}
-        s->block = 128;
+        s->block = 256;
         s->list_valid = false;
+        if (s->cap) CHK(ensure_list_alloc(s, s->cap));  // re-round for this lane count
         CHK(build_list(s));
         for (int b : blocks) {
             if (want_block && b != want_block) continue;
@@ -535,6 +643,7 @@ int tune(ljmd_system *s) {
     s->tpp = bt;
     s->block = bb;
     for (s->lshift = 0; (1 << s->lshift) < bt; ++s->lshift) {}
+    if (s->cap) CHK(ensure_list_alloc(s, s->cap));
     s->list_valid = false;
     s->force_valid = false;
     drop_graphs(s);
@@ -655,7 +764,7 @@ int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
         s->t_launches += units;
     }
     *overflow = (st.status & ST_OVERFLOW) != 0;
-    *nonfinite = (st.status & ST_NONFINITE) != 0;
+    *nonfinite = (st.status & (ST_NONFINITE | ST_TILE)) != 0;
     return LJMD_OK;
 }
 
@@ -692,8 +801,8 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
     const int tpp = cfg->threads_per_particle;
     if (tpp != 0 && tpp != 1 && tpp != 2 && tpp != 4 && tpp != 8 && tpp != 16)
         return set_err(LJMD_E_INVAL, "threads_per_particle must be 0, 1, 2, 4, 8 or 16");
-    if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 256 || cfg->block_size % 64))
-        return set_err(LJMD_E_INVAL, "block_size must be 0 or 64, 128, 192, 256");
+    if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 512 || cfg->block_size % 64))
+        return set_err(LJMD_E_INVAL, "block_size must be 0 or a multiple of 64 up to 512");
     if (cfg->graph_steps != 0 && cfg->graph_steps != -1 && (cfg->graph_steps < 2 || cfg->graph_steps % 2))
         return set_err(LJMD_E_INVAL, "graph_steps must be 0, -1 or an even number >= 2");
     if (cfg->nlist_capacity < 0) return set_err(LJMD_E_INVAL, "nlist_capacity must be >= 0");
@@ -716,6 +825,13 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
     if (!s) return set_err(LJMD_E_NOMEM, "host allocation failed");
     s->cfg = *cfg;
     (void)hipGetDevice(&s->device);
+    {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) ==
+                hipSuccess &&
+            v > 0)
+            s->lds_limit = (size_t)v;
+    }
     s->stream = (hipStream_t)cfg->stream;
     s->n = (int)n;
     s->npad = (int)((n + 63) & ~63LL);
@@ -832,7 +948,12 @@ int ljmd_step(ljmd_system *s, int64_t nsteps) {
             bool over = false, nonfin = false;
             CHK(run_steps(s, k, &over, &nonfin));
             if (nonfin) {
+                DevStatus st{};
+                CHK(sync_status(s, &st));
                 CHK(restore(s, cur0));
+                if (st.status & ST_TILE)
+                    return set_err(LJMD_E_BOX, "a brick holds more than %d atoms in its halo "
+                                               "cells; state restored", TILE_INDEX_MAX);
                 return set_err(LJMD_E_NONFINITE, "non-finite force during the step; state restored");
             }
             if (!over) break;
@@ -954,23 +1075,27 @@ int ljmd_get_neighbor_pairs(ljmd_system *s, int64_t *count, int32_t *pairs, doub
     if (!s || !count) return set_err(LJMD_E_INVAL, "null argument");
     CHK(ensure_ready(s));
     const size_t N = (size_t)s->n;
-    std::vector<int> cnt(N), tag(N);
+    // global index of every entry, row q at q * cap, decoded on the device
+    int *d_out = nullptr;
+    CHK(dalloc_t(s, &d_out, N * (size_t)s->cap));
+    RebuildArgs ra = rebuild_args(s, &s->d_st->one, s->cur);
+    int rc = launch_chk(launch_decode_list(s->stream, ra, d_out), "decode list");
+    std::vector<int> cnt(N), ent(N * (size_t)s->cap);
     std::vector<int4> img(N);
-    std::vector<int> nl((size_t)s->cap * s->npad);
-    HIPCHK(hipMemcpyAsync(cnt.data(), s->d_count, N * sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(img.data(), s->d_img, N * sizeof(int4), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipMemcpyAsync(nl.data(), s->d_nlist, nl.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    for (size_t q = 0; q < N; ++q) tag[q] = img[q].w;
+    if (rc == LJMD_OK &&
+        (hipMemcpyAsync(cnt.data(), s->d_count, N * sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+         hipMemcpyAsync(img.data(), s->d_img, N * sizeof(int4), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+         hipMemcpyAsync(ent.data(), d_out, ent.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+         hipStreamSynchronize(s->stream) != hipSuccess))
+        rc = set_err(LJMD_E_DEVICE, "copy of the decoded list failed");
+    dfree(s, d_out);
+    if (rc != LJMD_OK) return rc;
     std::vector<std::pair<int, int>> pr;
     for (size_t q = 0; q < N; ++q) {
         const int c = std::min(cnt[q], s->cap);
         for (int k = 0; k < c; ++k) {
-            const size_t c = (size_t)(k >> (2 + s->lshift));
-            const size_t l = (size_t)((k >> 2) & ((1 << s->lshift) - 1));
-            const size_t slot = ((((c * (size_t)s->npad + q) << s->lshift) + l) << 2) | (size_t)(k & 3);
-            const int j = nl[slot];
-            const int a = tag[q], b = tag[j];
+            const int j = ent[q * (size_t)s->cap + k];
+            const int a = img[q].w, b = img[j].w;
             if (a < b) pr.emplace_back(a, b);
         }
     }

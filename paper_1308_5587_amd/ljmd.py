@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libljmd.so")
+# LJMD_LIBRARY may name another build of the same library (for A/B timing of variants).
+LIB_PATH = os.environ.get("LJMD_LIBRARY") or os.path.join(HERE, "libljmd.so")
 
 LJMD_OK = 0
 LJMD_E_INVAL = -1
