@@ -42,8 +42,18 @@ struct BrickInfo {
     int first_cell;  // rank of the brick's first cell (its (0,0,0) corner)
     int ncell;       // cells in the brick (1..8)
     int nhalo;       // halo cells (<= HALO_MAX)
-    int dims;        // halo extents hx | hy << 4 | hz << 8, brick extents ex << 12 | ey << 16 | ez << 20
+    int dims;        // halo extents hx | hy << 4 | hz << 8, brick extents ex << 12 | ey << 16 | ez << 20,
+                     // bit 24 + a: axis a needs no minimum image (see MI_FREE)
 };
+// Bit 24 + a of BrickInfo::dims is set when, on axis a, the brick's halo lies in cells
+// 1 .. n_cell - 2 and n_cell >= 10. Between builds no particle moves more than skin/2 <
+// one cell, so no halo particle can have wrapped, and every listed pair is closer than
+// 4 cells + skin < L/2 on that axis: the plain difference x_j - x_i already is the minimum
+// image, bit for bit.
+constexpr int MI_FREE_SHIFT = 24;
+// Per-brick tile table written by the list build: offsets off[0..64], starts start[0..63],
+// halo count.
+constexpr int TILE_TAB = 2 * 64 + 2;
 // Halo cell: its rank and the periodic image it is seen in from the brick, per axis a
 // value in {-1, 0, 1} stored as (s + 1) in two bits: sx | sy << 2 | sz << 4.
 struct HaloCell {
@@ -98,6 +108,7 @@ struct ForceArgs {
     const BrickInfo *bricks;
     const HaloCell *halo;    // HALO_MAX per brick
     const int *cell_start;
+    const int *tile_tab;     // TILE_TAB ints per brick, written by the build
     double *u_out;           // per-particle energy half-sums (ENERGY)
     double *w_out;           // per-particle virial half-sums, 6 per particle (ENERGY)
     double *ke_out;          // per-particle kinetic energy at the full step (ENERGY, FUSED)
@@ -143,6 +154,7 @@ struct RebuildArgs {
     uint16_t *nlist;
     const BrickInfo *bricks;
     const HaloCell *halo;
+    int *tile_tab;
     const PairCoef *pair;
     DevStatus *st;
     double L[3], invL[3], inv_w[3];

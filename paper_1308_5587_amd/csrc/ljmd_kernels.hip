@@ -143,18 +143,50 @@ __device__ __forceinline__ int tile_global(const TileSmem &t, int k) {
     return t.start[h] + (k - t.off[h]);
 }
 
-// Copy the tile's positions (and types) into LDS, structure of arrays.
+// Copy the tile's positions (and types) into LDS, structure of arrays: blockDim / 64
+// consecutive threads copy one halo cell's atoms (consecutive in memory).
 template <bool MULTI>
 __device__ __forceinline__ void tile_stage(const TileSmem &t, const double4 *pos, double *sx,
                                            double *sy, double *sz, int *sty) {
-    for (int k = threadIdx.x; k < t.total; k += blockDim.x) {
-        const double4 p = pos[tile_global(t, k)];
-        sx[k] = p.x;
-        sy[k] = p.y;
-        sz[k] = p.z;
-        if (MULTI) sty[k] = (int)p.w;
+    const int per = blockDim.x >= 64 ? (int)blockDim.x / 64 : 1;
+    const int sub = threadIdx.x % per;
+    for (int h = threadIdx.x / per; h < t.nhalo; h += (int)blockDim.x / per) {
+        const int o = t.off[h];
+        const int m = t.off[h + 1] - o;
+        const double4 *src = pos + t.start[h];
+        for (int k = sub; k < m; k += per) {
+            const double4 p = src[k];
+            sx[o + k] = p.x;
+            sy[o + k] = p.y;
+            sz[o + k] = p.z;
+            if (MULTI) sty[o + k] = (int)p.w;
+        }
     }
     __syncthreads();
+}
+
+// Load a brick's tile offsets from the table written by the list build.
+__device__ __forceinline__ void tile_load(const int *tab, TileSmem &t) {
+    for (int k = threadIdx.x; k < TILE_TAB; k += blockDim.x) {
+        const int v = tab[k];
+        if (k <= 64) t.off[k] = v;
+        else if (k < 129) t.start[k - 65] = v;
+        else t.nhalo = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) t.total = t.off[t.nhalo];
+    __syncthreads();
+}
+
+// Store a brick's tile offsets for the force kernels (after tile_setup).
+__device__ __forceinline__ void tile_save(const TileSmem &t, int *tab) {
+    for (int k = threadIdx.x; k < TILE_TAB; k += blockDim.x) {
+        int v;
+        if (k <= 64) v = t.off[k];
+        else if (k < 129) v = (k - 65 < t.nhalo) ? t.start[k - 65] : 0;
+        else v = t.nhalo;
+        tab[k] = v;
+    }
 }
 
 // ---------------------------------------------------------------- upload (create / set_state)
@@ -325,7 +357,7 @@ __device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double d
 
 // The particle passes of one brick; STAGED selects neighbour positions from the LDS tile
 // (plain LDS reads) or, for a tile larger than the LDS allocation, from global memory.
-template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI, bool STAGED>
+template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI, bool STAGED, bool NO_MI>
 __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem &t,
                                              const double *__restrict__ sx,
                                              const double *__restrict__ sy,
@@ -401,9 +433,9 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                 }
 #pragma unroll
                 for (int v = 0; v < FORCE_BATCH; ++v) {
-                    const double dx = mi_rint(px[v] - xi.x, L0, iL0);
-                    const double dy = mi_rint(py[v] - xi.y, L1, iL1);
-                    const double dz = mi_rint(pz[v] - xi.z, L2, iL2);
+                    const double dx = NO_MI ? px[v] - xi.x : mi_rint(px[v] - xi.x, L0, iL0);
+                    const double dy = NO_MI ? py[v] - xi.y : mi_rint(py[v] - xi.y, L1, iL1);
+                    const double dz = NO_MI ? pz[v] - xi.z : mi_rint(pz[v] - xi.z, L2, iL2);
                     const double r2 = r2_canon(dx, dy, dz);
                     const PairCoef &c = MULTI ? s_pair[ti * a.ntypes + pt[v]] : a.single;
                     if (pv[v] && r2 < c.rc2)
@@ -509,18 +541,22 @@ __global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
     if (MODE == MODE_FUSED && blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild_clear = 0;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BrickInfo bi = a.bricks[b];
-    tile_setup(bi, a.halo + (size_t)b * HALO_MAX, a.cell_start, t);
+    tile_load(a.tile_tab + (size_t)b * TILE_TAB, t);
     const bool staged = t.total <= a.tile_cap;
     if (staged) tile_stage<MULTI>(t, a.pos_in, sx, sy, sz, sty);
 
     const int first = a.cell_start[bi.first_cell];
     const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
-    if (staged)
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true>(a, t, sx, sy, sz, sty, s_pair, first,
-                                                           natoms);
+    const int mif = (bi.dims >> MI_FREE_SHIFT) & 7;
+    if (staged && mif == 7)
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, true>(a, t, sx, sy, sz, sty, s_pair,
+                                                                 first, natoms);
+    else if (staged)
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, false>(a, t, sx, sy, sz, sty, s_pair,
+                                                                  first, natoms);
     else
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, false>(a, t, sx, sy, sz, sty, s_pair, first,
-                                                            natoms);
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, false, false>(a, t, sx, sy, sz, sty, s_pair,
+                                                                   first, natoms);
 }
 
 template <int PREC, int TPP, int MODE, bool ENERGY>
@@ -730,7 +766,6 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
     const int wl = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwave = blockDim.x >> 6;
-    const unsigned long long below = (1ull << wl) - 1ull;
     const int nst = a.canonical_mi ? t.nhalo : 27;
     for (int ci = wave; ci < bi.ncell; ci += nwave) {
         const int rank = bi.first_cell + ci;
@@ -800,7 +835,11 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                     const bool hit = valid && (jst + tt) != q && r2 < rl2;
                     const unsigned long long bal = __ballot(hit) & gmask;
                     if (hit) {
-                        const int k = count + __popcll(bal & below);
+                        // hits of lower lanes of the group: mbcnt counts the set bits of
+                        // bal below this lane
+                        const int k = count + (int)__builtin_amdgcn_mbcnt_hi(
+                                                  (unsigned)(bal >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
                         if (k < a.cap) a.nlist[nl_slot(q, k, a.npad, a.lshift)] = (uint16_t)(o + tt);
                     }
                     count += __popcll(bal);
@@ -832,7 +871,7 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
 // for bit for every pair that can be listed; unshifted halo cells need no addition at all.
 // With fewer than 3 cells on some axis the branch form is applied directly.
 template <bool MULTI>
-__global__ void __launch_bounds__(256) k_nlist(const RebuildArgs a) {
+__global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
     if (*a.go == 0) return;
     extern __shared__ double dyn_smem[];
     __shared__ TileSmem t;
@@ -847,6 +886,7 @@ __global__ void __launch_bounds__(256) k_nlist(const RebuildArgs a) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BrickInfo bi = a.bricks[b];
     tile_setup(bi, a.halo + (size_t)b * HALO_MAX, a.cell_start, t);
+    tile_save(t, a.tile_tab + (size_t)b * TILE_TAB);
     // the permuted state of the brick's particles becomes the main state and the new build
     // point (coalesced copy; tile staging below reads pos_scr, not pos)
     {
@@ -919,9 +959,9 @@ hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
     hipLaunchKernelGGL(k_cell_gather, dim3(a.ncell < 8192 ? a.ncell : 8192), dim3(64), 0, s, a);
     const size_t smem = nlist_lds_bytes(a.tile_cap, a.ntypes);
     if (a.ntypes > 1)
-        hipLaunchKernelGGL(k_nlist<true>, dim3(a.nbrick), dim3(256), smem, s, a);
+        hipLaunchKernelGGL(k_nlist<true>, dim3(a.nbrick), dim3(512), smem, s, a);
     else
-        hipLaunchKernelGGL(k_nlist<false>, dim3(a.nbrick), dim3(256), smem, s, a);
+        hipLaunchKernelGGL(k_nlist<false>, dim3(a.nbrick), dim3(512), smem, s, a);
     return hipGetLastError();
 }
 

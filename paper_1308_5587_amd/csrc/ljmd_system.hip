@@ -105,6 +105,7 @@ struct ljmd_system {
     int cap = 0;
     BrickInfo *d_bricks = nullptr;
     HaloCell *d_halo = nullptr;
+    int *d_tile_tab = nullptr;
     int nbrick = 0, nbrick_alloc = 0, tile_cap = 0;
     bool canonical = false;
     size_t lds_limit = 64 * 1024;
@@ -306,6 +307,11 @@ int setup_table(ljmd_system *s) {
         for (int a = 0; a < 3; ++a) hd[a] = brick_n[3 * bo + a] + 2;
         bi.dims = hd[0] | (hd[1] << 4) | (hd[2] << 8) | (brick_n[3 * bo] << 12) |
                   (brick_n[3 * bo + 1] << 16) | (brick_n[3 * bo + 2] << 20);
+        for (int a = 0; a < 3; ++a) {
+            const int lo = brick_lo[3 * bo + a], hi = lo + brick_n[3 * bo + a];
+            if (!canonical && nc[a] >= 10 && lo - 1 >= 1 && hi <= nc[a] - 2)
+                bi.dims |= 1 << (MI_FREE_SHIFT + a);
+        }
         int nh = 0;
         for (int hx = 0; hx < hd[0]; ++hx)
             for (int hy = 0; hy < hd[1]; ++hy)
@@ -334,8 +340,10 @@ int setup_table(ljmd_system *s) {
     if (nbrick > s->nbrick_alloc) {
         dfree(s, s->d_bricks);
         dfree(s, s->d_halo);
+        dfree(s, s->d_tile_tab);
         CHK(dalloc_t(s, &s->d_bricks, nbrick));
         CHK(dalloc_t(s, &s->d_halo, (size_t)nbrick * HALO_MAX));
+        CHK(dalloc_t(s, &s->d_tile_tab, (size_t)nbrick * TILE_TAB));
         s->nbrick_alloc = nbrick;
     }
     HIPCHK(hipMemcpyAsync(s->d_bricks, bricks.data(), sizeof(BrickInfo) * nbrick,
@@ -432,6 +440,7 @@ RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
     a.canonical_mi = s->canonical ? 1 : 0;
     a.bricks = s->d_bricks;
     a.halo = s->d_halo;
+    a.tile_tab = s->d_tile_tab;
     a.nbrick = s->nbrick;
     a.tile_cap = s->tile_cap;
     return a;
@@ -450,6 +459,7 @@ ForceArgs force_args(ljmd_system *s, int cur) {
     a.bricks = s->d_bricks;
     a.halo = s->d_halo;
     a.cell_start = s->d_cell_start;
+    a.tile_tab = s->d_tile_tab;
     a.nbrick = s->nbrick;
     a.tile_cap = s->tile_cap;
     a.u_out = s->d_u;
