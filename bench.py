@@ -9,9 +9,18 @@ bracketed by device synchronisation. Prints ONE JSON line on stdout (progress on
 
 Also reported on that line:
   roofline      the fused force + integration kernel: algorithmic bytes per launch
-                (N * (4 * mean list length + 128)) over its mean launch time, measured with
-                HIP events on the library's stream, against 8 TB/s.
+                (N * (2 * mean list length + 128): 16-bit list entries plus the per-atom
+                state) over its mean launch time, measured with HIP events on the library's
+                stream, against 8 TB/s.
   mixed         the same workload with FP32 pair arithmetic (FP64 integration and sums).
+  batched       512 independent replicas (N uniform in [256, 8192], density in [0.6, 0.9],
+                T in [0.8, 1.5]) advanced together in 100-step graph blocks, mixed
+                precision, beside a sample of the same replicas run one by one on the plain
+                FP64 path.
+  served        Poisson request streams (N log-uniform in [512, 65536], density 0.8442,
+                T 1.2, 1000-10000 steps) through the continuous-batching loop: p50/p99
+                latency and atom-steps/s, beside the same stream served one request at a
+                time on the plain FP64 path.
   cpu_baseline  the CPU FP64 oracle on a bounded sample of the same workload, on this host.
 """
 
@@ -21,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -28,6 +39,7 @@ if ROOT not in sys.path:
 METRIC = "atom-steps/s: LJ N=1M FP64 vs mixed; batched replicas; serve p50/p99"
 HBM_PEAK_GBS = 8000.0
 STATE_BYTES = 128  # count 4, x+type 28, v 24, x_build 24 read; x 24, v 24 written
+LIST_ENTRY_BYTES = 2  # 16-bit tile index per list entry
 
 
 def log(msg):
@@ -58,7 +70,7 @@ def run_gpu(spec, precision, steps, warmup, timing_steps):
     st2 = g.stats()
     n = spec.n
     mean_list = st2["list_entries"] / n
-    per_atom = 4.0 * mean_list + STATE_BYTES
+    per_atom = LIST_ENTRY_BYTES * mean_list + STATE_BYTES
     avg_ms = ms / max(1, launches)
     achieved = n * per_atom / (avg_ms * 1e-3) / 1e9
     rebuilds = st1["rebuilds"] - st0["rebuilds"]
@@ -99,6 +111,100 @@ def run_cpu_baseline(spec, steps):
                       f"{builds} list builds in total"}
 
 
+def _replica_spec(p, inputs):
+    return inputs.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed)
+
+
+def run_alone_timed(spec, nsteps, precision):
+    """One replica on the single-system path: wall time of step(nsteps) after setup."""
+    import torch
+
+    from paper_1308_5587_amd import ljmd
+
+    g = ljmd.System.from_spec(spec, precision=precision)
+    g.step(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(nsteps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g.close()
+    return dt
+
+
+def run_batched(count, block_steps, blocks, sample):
+    import torch
+
+    from paper_1308_5587_amd import inputs, ljmd
+
+    params = inputs.make_replica_specs(count, seed=0)
+    specs = [_replica_spec(p, inputs) for p in params]
+    atoms = sum(s.n for s in specs)
+    nsteps = (blocks + 1) * block_steps
+    probe = ljmd.Batch(1 << 30, 1, precision="mixed", block_steps=block_steps)
+    budget = int(1.25 * sum(probe.footprint(s) for s in specs)) + (64 << 20)
+    probe.close()
+    b = ljmd.Batch(budget, count, precision="mixed", block_steps=block_steps)
+    t0 = time.perf_counter()
+    slots = [b.admit(s, nsteps) for s in specs]
+    torch.cuda.synchronize()
+    t_admit = time.perf_counter() - t0
+    b.run_block()  # warm-up block (captures the graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(blocks):
+        b.run_block()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert len(b.poll()) == count
+    for s in slots:
+        assert b.slot_steps(s) == nsteps
+    b.close()
+    # a sample of the same replicas, one by one on the plain FP64 path
+    idx = np.random.default_rng(5).choice(count, size=min(sample, count), replace=False)
+    work = sum(specs[k].n for k in idx) * block_steps * blocks
+    t1 = sum(run_alone_timed(specs[k], block_steps * blocks, "fp64") for k in idx)
+    value = atoms * block_steps * blocks / wall
+    alone = work / t1
+    return {"value": value, "unit": "atom-steps/s", "replicas": count, "atoms": atoms,
+            "block_steps": block_steps, "blocks": blocks, "ms_per_block": 1e3 * wall / blocks,
+            "admit_s": t_admit, "dtype": "f32 pair / f64 state",
+            "one_by_one_fp64": {"value": alone, "unit": "atom-steps/s", "replicas": len(idx),
+                                "steps": block_steps * blocks},
+            "speedup_vs_one_by_one_fp64": value / alone}
+
+
+def run_served(rates, count, block_steps):
+    from paper_1308_5587_amd import inputs, ljmd, serve
+
+    out = []
+    for rate in rates:
+        arrivals = inputs.make_arrivals(count, rate, seed=2)
+        mk = lambda p: inputs.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed)  # noqa: E731
+        reqs = serve.requests_from_arrivals(arrivals, mk)
+        b = ljmd.Batch(16 << 30, 64, precision="mixed", block_steps=block_steps)
+        rep = serve.serve(b, reqs).summary()
+        b.close()
+        log(f"[bench] served rate={rate}/s: p50 {rep['p50_latency_s']:.3f} s, "
+            f"p99 {rep['p99_latency_s']:.3f} s, {rep['atom_steps_per_s']:.4g} atom-steps/s")
+
+        def alone(spec, nsteps):
+            g = ljmd.System.from_spec(spec, precision="fp64")
+            g.step(nsteps)
+            g.close()
+
+        reqs1 = serve.requests_from_arrivals(arrivals, mk)
+        base = serve.serve_one_by_one(alone, reqs1).summary()
+        log(f"[bench] one by one fp64 rate={rate}/s: p50 {base['p50_latency_s']:.3f} s, "
+            f"p99 {base['p99_latency_s']:.3f} s, {base['atom_steps_per_s']:.4g} atom-steps/s")
+        out.append({"rate_per_s": rate, "requests": count, **{k: rep[k] for k in (
+            "p50_latency_s", "p99_latency_s", "mean_latency_s", "atom_steps_per_s", "wall_s",
+            "peak_resident")},
+            "one_by_one_fp64": {k: base[k] for k in ("p50_latency_s", "p99_latency_s",
+                                                     "atom_steps_per_s", "wall_s")}})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +215,12 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-blocks", type=int, default=5)
+    ap.add_argument("--batched-sample", type=int, default=32)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rates", type=str, default="4,16")
+    ap.add_argument("--serve-count", type=int, default=32)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: multi-GPU runs (--gpus > 1) are not part of "
@@ -131,6 +243,16 @@ def main():
         log("[bench] mixed")
         mixed = run_gpu(spec, "mixed", args.steps, args.warmup, args.timing_steps)
         log(f"[bench] mixed {mixed['value']:.4g} atom-steps/s")
+    batched = None
+    if not args.no_batched:
+        log("[bench] batched: 512 replicas")
+        batched = run_batched(512, 100, args.batched_blocks, args.batched_sample)
+        log(f"[bench] batched {batched['value']:.4g} atom-steps/s "
+            f"(one by one fp64 {batched['one_by_one_fp64']['value']:.4g})")
+    served = None
+    if not args.no_serve:
+        rates = [float(r) for r in args.serve_rates.split(",") if r]
+        served = run_served(rates, args.serve_count, 100)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu oracle, {args.cpu_steps} steps")
@@ -170,6 +292,10 @@ def main():
                          "kernel_avg_ms": mixed["kernel_avg_ms"],
                          "threads_per_particle": mixed["threads_per_particle"],
                          "block_size": mixed["block_size"]}
+    if batched is not None:
+        line["batched"] = batched
+    if served is not None:
+        line["served"] = served
     print(json.dumps(line), flush=True)
 
 

@@ -166,6 +166,85 @@ int ljmd_get_stats(ljmd_system *sys, ljmd_stats *out);
 int ljmd_set_kernel_timing(ljmd_system *sys, int32_t on);
 int ljmd_kernel_time(ljmd_system *sys, int64_t *launches, double *total_ms);
 
+/* ------------------------------------------------------------------ batched replicas
+ *
+ * A batch advances many independent single-box LJ systems ("replicas") of uneven size
+ * together: every step is one launch of the fused force/integration kernel over the bricks
+ * of all replicas, plus the list-rebuild kernels, each gated per replica by that replica's
+ * own rebuild request, all captured in HIP graphs of block_steps steps. Every replica runs
+ * exactly the arithmetic it would run alone (same kernels, same per-replica parameters, no
+ * cross-replica reductions), so its trajectory does not depend on its neighbours in the
+ * batch. Replicas are admitted into free slots while others run and are retired when their
+ * requested number of steps is done; their state stays on the device in between. This is
+ * the paper's "many independent simulations" use of one GPU (Section "Performance") turned
+ * into continuous batching. */
+
+typedef struct ljmd_batch ljmd_batch;
+
+typedef struct ljmd_batch_config {
+    int64_t budget_bytes;   /* device memory the batch may use for replica state */
+    int32_t max_slots;      /* replicas resident at once (>= 1) */
+    int32_t precision;      /* LJMD_FP64 or LJMD_MIXED, for every replica */
+    double dt;              /* time step for every replica */
+    double skin;            /* Verlet skin for every replica */
+    int32_t block_steps;    /* steps per ljmd_batch_run_block (even, >= 2); 0 = 100 */
+    int32_t threads_per_particle; /* 0 = autotuned on the first block */
+    int32_t block_size;     /* 0 = autotuned */
+    int32_t nlist_capacity; /* entries per particle; 0 = automatic */
+    void *stream;           /* hipStream_t; NULL = default stream */
+    ljmd_alloc_fn alloc;    /* NULL = hipMalloc */
+    ljmd_free_fn free;
+    void *alloc_ctx;
+} ljmd_batch_config;
+
+/* One replica request: an orthorhombic box and N particles (host arrays, copied at
+ * admission), a pair table of ntypes x ntypes LJ coefficients (row-major eps, sigma,
+ * r_cut, each ntypes*ntypes doubles, symmetric), and the number of NVE steps to run. */
+typedef struct ljmd_replica_spec {
+    double box[3];
+    int64_t n;
+    const double *pos;      /* n x 3 */
+    const double *vel;      /* n x 3 */
+    const int32_t *type;    /* n, or NULL for all type 0 */
+    int32_t ntypes;
+    const double *eps;      /* ntypes x ntypes */
+    const double *sigma;    /* ntypes x ntypes */
+    const double *r_cut;    /* ntypes x ntypes */
+    int64_t nsteps;         /* >= 1 */
+} ljmd_replica_spec;
+
+/* Create an empty batch. Errors: INVAL, NOMEM, DEVICE. */
+int ljmd_batch_create(const ljmd_batch_config *cfg, ljmd_batch **out);
+
+/* Device bytes a replica would hold in this batch (state, cells, bricks, list). */
+int ljmd_batch_footprint(const ljmd_batch *b, const ljmd_replica_spec *spec, int64_t *bytes);
+
+/* Admit a replica into a free slot: upload, first list build, first forces and the first
+ * half step. *slot receives the slot id. Errors: CAPACITY (no free slot or not enough of
+ * the budget left), INVAL, BOX, NONFINITE, DEVICE. */
+int ljmd_batch_admit(ljmd_batch *b, const ljmd_replica_spec *spec, int32_t *slot);
+
+/* Advance every running replica by up to block_steps steps (a replica stops exactly at its
+ * requested count). Enqueued on the batch stream; synchronises once at the end. */
+int ljmd_batch_run_block(ljmd_batch *b);
+
+/* Slots whose replica has finished: done[0..*ndone) (done sized max_slots). */
+int ljmd_batch_poll(ljmd_batch *b, int32_t *done, int32_t *ndone);
+
+/* Results of a slot, tag order; any pointer may be NULL: positions (wrapped), velocities
+ * and forces (n x 3), energy[2] = {potential, kinetic}, virial[6]. Errors: STATE if the slot
+ * is empty. */
+int ljmd_batch_read(ljmd_batch *b, int32_t slot, double *pos, double *vel, double *force,
+                    double *energy, double *virial);
+
+/* Steps completed by the replica in a slot. */
+int ljmd_batch_slot_steps(ljmd_batch *b, int32_t slot, int64_t *steps);
+
+/* Free a slot (its memory returns to the budget). */
+int ljmd_batch_release(ljmd_batch *b, int32_t slot);
+
+void ljmd_batch_destroy(ljmd_batch *b);
+
 /* Thread-local message for the last non-zero status returned on this thread. */
 const char *ljmd_last_error(void);
 

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libljmd.so")
-SOURCES = ["ljmd_kernels.hip", "ljmd_system.hip", "ljmd_batch.hip"]
+SOURCES = ["ljmd_kernels.hip", "ljmd_host.hip", "ljmd_system.hip", "ljmd_batch.hip"]
 
 # -ffp-contract=off: the distance arithmetic must not be fused (explicit fma elsewhere).
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.

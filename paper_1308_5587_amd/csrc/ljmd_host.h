@@ -1,0 +1,77 @@
+// Host-side helpers shared by the single-system and batch entry points of libljmd:
+// error reporting, device allocation through the configured allocator, and the per-replica
+// tables (pair coefficients, cell grid, bricks and halos) that the kernels read.
+#pragma once
+
+#include "ljmd_internal.h"
+#include "../../include/ljmd.h"
+
+#include <cstdint>
+#include <string>
+#include <utility>
+#include <vector>
+
+namespace ljmd {
+
+// Thread-local message returned by ljmd_last_error; set_err formats it and returns code.
+extern thread_local std::string g_last_error;
+int set_err(int code, const char *fmt, ...);
+
+#define HIPCHK(expr)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::ljmd::set_err(LJMD_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));  \
+    } while (0)
+
+#define CHK(expr)                     \
+    do {                              \
+        int r_ = (expr);              \
+        if (r_ != LJMD_OK) return r_; \
+    } while (0)
+
+// Device memory through the user's allocator (or hipMalloc), with a record for freeing.
+struct DeviceArena {
+    ljmd_alloc_fn alloc = nullptr;
+    ljmd_free_fn free = nullptr;
+    void *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    std::vector<std::pair<void *, size_t>> blocks;
+    int64_t bytes = 0;
+
+    int get(void **p, size_t n);
+    void put(void *p);
+    void release_all();
+    template <class T>
+    int get_t(T **p, size_t count) {
+        return get(reinterpret_cast<void **>(p), count * sizeof(T));
+    }
+};
+
+// Pair coefficients of one replica: ntypes x ntypes rows (row-major), list radii squared,
+// and the largest list radius. Pairs with r_cut == 0 are disabled.
+struct PairTable {
+    std::vector<PairCoef> coef;
+    std::vector<double> rl2;
+    double rl_max = 0.0;
+};
+void make_pair_table(int ntypes, const double *eps, const double *sig, const double *rc,
+                     double skin, PairTable *out);
+
+// Cell grid, bricks and halos of one replica, with replica-local cell indices.
+struct ReplicaGrid {
+    int nc[3] = {0, 0, 0};
+    bool canonical = false;          // fewer than 3 cells on some axis
+    int ncell = 0, nbrick = 0, max_halo = 0;
+    std::vector<int> rank;           // local linear cell index -> local cell index
+    std::vector<int> xyz;            // local cell index -> packed (cx | cy << 10 | cz << 20)
+    std::vector<BrickInfo> bricks;   // first_cell local, rep unset
+    std::vector<HaloCell> halo;      // HALO_MAX per brick, ranks local
+};
+// Returns LJMD_E_BOX when r_L,max exceeds half a box edge.
+int make_grid(const double L[3], double rl_max, ReplicaGrid *g);
+
+// Tile capacity (atoms staged in LDS) for a mean occupancy of atoms_per_cell.
+int choose_tile_cap(double atoms_per_cell, int max_halo, int max_ntypes, size_t lds_limit);
+
+}  // namespace ljmd

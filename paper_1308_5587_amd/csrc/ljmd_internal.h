@@ -21,15 +21,32 @@ struct PairCoef {
     double pad;
 };
 
-// Device status block (one per system).
+// Device status block (one per system or batch). Rebuild requests live in a separate
+// per-replica array: req[2 r + b] for replica r, b the position buffer just written.
 struct DevStatus {
-    int rebuild[2];          // rebuild request, indexed by the position buffer just written
     int status;              // ST_* bits
     int max_count;           // longest list seen at a build
     unsigned long long builds;
     unsigned long long entries;  // list entries written at the last build
-    int one;                 // constant 1: "go" word of an unconditional rebuild
     int pad;
+};
+
+// Parameters of one replica (a single system is a batch of one). Replica r owns particles
+// [poff, poff + n), cells [coff, coff + ncell] (ncell + 1 entries of cell_start), bricks
+// [boff, boff + nbrick) and the pair table rows [pair_off, pair_off + ntypes^2).
+struct RepParams {
+    double L[3], invL[3], inv_w[3];
+    double dt, half_dt, lim2;
+    double single_rl2;       // (r_cut + skin)^2 of pair (0,0)
+    double pad0;
+    int nc[3];
+    int poff, n;
+    int coff, ncell;
+    int boff, nbrick;
+    int canonical;           // some axis has fewer than 3 cells
+    int ntypes, pair_off;
+    int active;              // 0 for a free slot
+    int pad1;
 };
 
 enum { ST_OVERFLOW = 1, ST_NONFINITE = 2, ST_TILE = 4 };
@@ -39,11 +56,13 @@ enum { ST_OVERFLOW = 1, ST_NONFINITE = 2, ST_TILE = 4 };
 // the atoms of the halo, concatenated in halo order, form the brick's tile, and list
 // entries are 16-bit indices into that tile.
 struct BrickInfo {
-    int first_cell;  // rank of the brick's first cell (its (0,0,0) corner)
+    int first_cell;  // global index of the brick's first cell (its (0,0,0) corner)
     int ncell;       // cells in the brick (1..8)
     int nhalo;       // halo cells (<= HALO_MAX)
     int dims;        // halo extents hx | hy << 4 | hz << 8, brick extents ex << 12 | ey << 16 | ez << 20,
                      // bit 24 + a: axis a needs no minimum image (see MI_FREE)
+    int rep;         // replica, -1 for an unused brick
+    int pad[3];
 };
 // Bit 24 + a of BrickInfo::dims is set when, on axis a, the brick's halo lies in cells
 // 1 .. n_cell - 2 and n_cell >= 10. Between builds no particle moves more than skin/2 <
@@ -95,8 +114,10 @@ __host__ __device__ inline size_t nlist_lds_bytes(int tile_cap, int ntypes) {
     return b;
 }
 
-// Arguments of the force kernel family (by value).
+// Arguments of the force kernel family (by value). The grid covers bricks [0, nbrick);
+// each brick reads its replica's parameters.
 struct ForceArgs {
+    const RepParams *reps;
     const double4 *pos_in;   // x, y, z, type (as double); sorted order
     double4 *pos_out;        // MODE_FUSED: positions after the drift
     double4 *vel;            // vx, vy, vz, 1/m
@@ -106,82 +127,83 @@ struct ForceArgs {
     const int *nl_count;
     const uint16_t *nlist;   // 16-bit tile indices
     const BrickInfo *bricks;
-    const HaloCell *halo;    // HALO_MAX per brick
     const int *cell_start;
     const int *tile_tab;     // TILE_TAB ints per brick, written by the build
     double *u_out;           // per-particle energy half-sums (ENERGY)
     double *w_out;           // per-particle virial half-sums, 6 per particle (ENERGY)
     double *ke_out;          // per-particle kinetic energy at the full step (ENERGY, FUSED)
-    const PairCoef *pair;    // ntypes x ntypes
-    int *rebuild_set;        // FUSED: raised when a particle moved >= skin/2
-    int *rebuild_clear;      // FUSED: the other buffer's request, cleared by workgroup 0
+    const PairCoef *pair;    // pair rows of all replicas
+    int *req;                // rebuild requests, 2 per replica
+    int *rem;                // MODE_FUSED with step limits: steps left, 2 per replica (or null)
+    const int *only;         // replica mask (null: all replicas)
     int *status;
-    PairCoef single;         // pair (0,0) when ntypes == 1
-    double L[3], invL[3];
-    double dt, half_dt, lim2;
-    int n, npad, cap, lshift, ntypes;
-    int nbrick, tile_cap;
+    int *rep_status;         // per-replica status bits (or null)
+    int cur;                 // position buffer read (0/1): req/rem parity
+    int npad, cap, lshift, nbrick, tile_cap, max_ntypes;
 };
 
 struct KickDriftArgs {
+    const RepParams *reps;
+    const int *prep;         // replica of each particle (null: replica 0)
     const double4 *pos_in;
     double4 *pos_out;
     double4 *vel;
     int4 *img;
     const double4 *xb;
     const double4 *force;
-    int *rebuild_set;
-    int *rebuild_clear;
-    double L[3], invL[3];
-    double dt, half_dt, lim2;
-    int n;
+    int *req;
+    const int *only;         // replica mask (null: all)
+    int cur;
+    int n;                   // particle slots [0, n)
 };
 
 struct RebuildArgs {
-    const int *go;           // the rebuild runs only if *go != 0
-    const double *rl2_table; // ntypes x ntypes list radii squared
+    const RepParams *reps;
+    const int *prep;         // replica of each particle (null: replica 0)
+    const int *crep;         // replica of each cell (null: replica 0)
+    const int *go;           // replica r rebuilds only if go[r * go_stride] != 0
+    int go_stride;
+    const double *rl2_table; // pair rows of all replicas: list radii squared
     double4 *pos;            // current positions (sorted order); rewritten in new order
     double4 *pos_scr;
     double4 *vel, *vel_scr;
     int4 *img, *img_scr;
     double4 *xb;
     int *key, *slot, *perm;
-    int *cell_count;         // ncell, zero between builds
-    int *cell_start;         // ncell + 1
-    const int *cell_rank;    // linear cell index -> Morton rank
-    const int *cell_xyz;     // Morton rank -> packed (cx | cy << 10 | cz << 20)
+    int *cell_count;         // zero between builds
+    int *cell_start;         // ncell + 1 entries per replica
+    const int *cell_rank;    // per replica: local linear cell index -> global cell index
+    const int *cell_xyz;     // global cell -> packed local (cx | cy << 10 | cz << 20)
     int *nl_count;
     uint16_t *nlist;
     const BrickInfo *bricks;
     const HaloCell *halo;
     int *tile_tab;
-    const PairCoef *pair;
     DevStatus *st;
-    double L[3], invL[3], inv_w[3];
-    double single_rl2;
-    int nc[3];
-    int ncell, n, npad, cap, lshift, ntypes;
-    int canonical_mi;        // 1 when some axis has fewer than 3 cells
-    int nbrick, tile_cap;
+    int *rep_status;         // per-replica status bits (or null)
+    int n, ncell, nbrick, nrep;   // slot counts of the arrays
+    int npad, cap, lshift, tile_cap, max_ntypes;
 };
 
 // ---------------------------------------------------------------- launchers
 hipError_t launch_upload(hipStream_t s, const double *pos, const double *vel, const int *type,
                          const double *mass, double4 *pos4, double4 *vel4, int4 *img, int n,
-                         const double L[3], int set_vel, int set_img, const int *img_in);
+                         const double L[3], int set_vel, int set_img, const int *img_in,
+                         int poff);
 hipError_t launch_kick_drift(hipStream_t s, const KickDriftArgs &a);
 hipError_t launch_force(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
                         bool energy, int block);
 hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a);
 hipError_t launch_reduce(hipStream_t s, const double *u, const double *w, const double *ke,
-                         const double4 *vel, int n, double *partials, int nblocks_max,
+                         const double4 *vel, int poff, int n, double *partials, int nblocks_max,
                          double *out);
-hipError_t launch_unsort_vec(hipStream_t s, const double4 *src, const int4 *img, int n,
-                             double *dst);
-hipError_t launch_unsort_img(hipStream_t s, const int4 *img, int n, int *dst);
+hipError_t launch_unsort_vec(hipStream_t s, const double4 *src, const int4 *img, int poff,
+                             int n, double *dst);
+hipError_t launch_unsort_img(hipStream_t s, const int4 *img, int poff, int n, int *dst);
 hipError_t launch_unsort_scalar(hipStream_t s, const double *src, int width, const int4 *img,
-                                int n, double *dst);
+                                int poff, int n, double *dst);
 hipError_t launch_fill_status(hipStream_t s, DevStatus *st);
+hipError_t launch_fill_int(hipStream_t s, int *p, int n, int value);
 hipError_t launch_decode_list(hipStream_t s, const RebuildArgs &a, int *out);
 
 }  // namespace ljmd

@@ -191,12 +191,13 @@ __device__ __forceinline__ void tile_save(const TileSmem &t, int *tab) {
 
 // ---------------------------------------------------------------- upload (create / set_state)
 
-// Host arrays (tag order) -> device SoA in tag order, positions wrapped into [0, L):
-// k = floor(x / L) whole boxes are removed, then one-box rounding fix-ups.
+// Host arrays (tag order) -> device SoA in tag order at slots poff + q, positions wrapped
+// into [0, L): k = floor(x / L) whole boxes are removed, then one-box rounding fix-ups.
 __global__ void k_upload(const double *__restrict__ pos, const double *__restrict__ vel,
                          const int *__restrict__ type, const double *__restrict__ mass,
                          double4 *pos4, double4 *vel4, int4 *img, int n, double L0, double L1,
-                         double L2, int set_vel, int set_img, const int *__restrict__ img_in) {
+                         double L2, int set_vel, int set_img, const int *__restrict__ img_in,
+                         int poff) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
     double Ls[3] = {L0, L1, L2};
@@ -214,60 +215,64 @@ __global__ void k_upload(const double *__restrict__ pos, const double *__restric
         x[a] = v;
         im[a] = m + (img_in ? img_in[3 * q + a] : 0);
     }
-    int tag = q;
-    int t = type[q];
-    pos4[q] = make_double4(x[0], x[1], x[2], (double)t);
+    const int t = type ? type[q] : 0;
+    pos4[poff + q] = make_double4(x[0], x[1], x[2], (double)t);
     if (set_vel) {
         double m = mass ? mass[q] : 1.0;
-        vel4[q] = make_double4(vel[3 * q], vel[3 * q + 1], vel[3 * q + 2], 1.0 / m);
+        vel4[poff + q] = make_double4(vel[3 * q], vel[3 * q + 1], vel[3 * q + 2], 1.0 / m);
     }
-    if (set_img) img[q] = make_int4(im[0], im[1], im[2], tag);
+    if (set_img) img[poff + q] = make_int4(im[0], im[1], im[2], q);
 }
 
 hipError_t launch_upload(hipStream_t s, const double *pos, const double *vel, const int *type,
                          const double *mass, double4 *pos4, double4 *vel4, int4 *img, int n,
-                         const double L[3], int set_vel, int set_img, const int *img_in) {
+                         const double L[3], int set_vel, int set_img, const int *img_in,
+                         int poff) {
     int b = 256;
     hipLaunchKernelGGL(k_upload, dim3((n + b - 1) / b), dim3(b), 0, s, pos, vel, type, mass,
-                       pos4, vel4, img, n, L[0], L[1], L[2], set_vel, set_img, img_in);
+                       pos4, vel4, img, n, L[0], L[1], L[2], set_vel, set_img, img_in, poff);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- kick + drift
 
 // First half of a velocity-Verlet step from stored forces: v += dt/(2m) F, x += dt v,
-// wrap, then raise the rebuild request if |x - x_build| (min image) >= skin/2.
+// wrap, then raise the replica's rebuild request if |x - x_build| (min image) >= skin/2.
 __global__ void __launch_bounds__(256) k_kick_drift(const KickDriftArgs a) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild_clear = 0;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     bool exceed = false;
+    int rep = -1;
     if (q < a.n) {
-        double4 x = a.pos_in[q];
-        double4 v = a.vel[q];
-        double4 f = a.force[q];
-        double hm = a.half_dt * v.w;
-        v.x = __builtin_fma(hm, f.x, v.x);
-        v.y = __builtin_fma(hm, f.y, v.y);
-        v.z = __builtin_fma(hm, f.z, v.z);
-        int4 im = a.img[q];
-        int4 im0 = im;
-        x.x = __builtin_fma(a.dt, v.x, x.x);
-        x.y = __builtin_fma(a.dt, v.y, x.y);
-        x.z = __builtin_fma(a.dt, v.z, x.z);
-        wrap_coord(x.x, im.x, a.L[0]);
-        wrap_coord(x.y, im.y, a.L[1]);
-        wrap_coord(x.z, im.z, a.L[2]);
-        a.pos_out[q] = x;
-        a.vel[q] = v;
-        if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
-        double4 b = a.xb[q];
-        double dx = mi_rint(x.x - b.x, a.L[0], a.invL[0]);
-        double dy = mi_rint(x.y - b.y, a.L[1], a.invL[1]);
-        double dz = mi_rint(x.z - b.z, a.L[2], a.invL[2]);
-        exceed = r2_canon(dx, dy, dz) >= a.lim2;
+        rep = a.prep ? a.prep[q] : 0;
+        if (rep >= 0 && a.reps[rep].active && !(a.only && !a.only[rep])) {
+            const RepParams &P = a.reps[rep];
+            if (q == P.poff) a.req[2 * rep + a.cur] = 0;  // the other buffer's request
+            double4 x = a.pos_in[q];
+            double4 v = a.vel[q];
+            const double4 f = a.force[q];
+            const double hm = P.half_dt * v.w;
+            v.x = __builtin_fma(hm, f.x, v.x);
+            v.y = __builtin_fma(hm, f.y, v.y);
+            v.z = __builtin_fma(hm, f.z, v.z);
+            int4 im = a.img[q];
+            const int4 im0 = im;
+            x.x = __builtin_fma(P.dt, v.x, x.x);
+            x.y = __builtin_fma(P.dt, v.y, x.y);
+            x.z = __builtin_fma(P.dt, v.z, x.z);
+            wrap_coord(x.x, im.x, P.L[0]);
+            wrap_coord(x.y, im.y, P.L[1]);
+            wrap_coord(x.z, im.z, P.L[2]);
+            a.pos_out[q] = x;
+            a.vel[q] = v;
+            if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
+            const double4 b = a.xb[q];
+            const double dx = mi_rint(x.x - b.x, P.L[0], P.invL[0]);
+            const double dy = mi_rint(x.y - b.y, P.L[1], P.invL[1]);
+            const double dz = mi_rint(x.z - b.z, P.L[2], P.invL[2]);
+            exceed = r2_canon(dx, dy, dz) >= P.lim2;
+        }
     }
-    const unsigned long long vote = __ballot(exceed);
-    if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1) atomicOr(a.rebuild_set, 1);
+    if (exceed) atomicOr(&a.req[2 * rep + (a.cur ^ 1)], 1);
 }
 
 hipError_t launch_kick_drift(hipStream_t s, const KickDriftArgs &a) {
@@ -363,12 +368,14 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                                              const double *__restrict__ sy,
                                              const double *__restrict__ sz,
                                              const int *__restrict__ sty,
-                                             const PairCoef *s_pair, int first, int natoms) {
+                                             const PairCoef *s_pair, const PairCoef &single,
+                                             const RepParams &P, int rep, bool last, int first,
+                                             int natoms) {
     const int per_pass = blockDim.x / TPP;
     const int g = threadIdx.x / TPP;
     const int lane = threadIdx.x & (TPP - 1);
-    const double L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
-    const double iL0 = a.invL[0], iL1 = a.invL[1], iL2 = a.invL[2];
+    const double L0 = P.L[0], L1 = P.L[1], L2 = P.L[2];
+    const double iL0 = P.invL[0], iL1 = P.invL[1], iL2 = P.invL[2];
     typedef int v4i __attribute__((ext_vector_type(4)));
     const size_t cstride = (size_t)a.npad << a.lshift;  // 16-byte chunks between rounds
 
@@ -437,7 +444,7 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                     const double dy = NO_MI ? py[v] - xi.y : mi_rint(py[v] - xi.y, L1, iL1);
                     const double dz = NO_MI ? pz[v] - xi.z : mi_rint(pz[v] - xi.z, L2, iL2);
                     const double r2 = r2_canon(dx, dy, dz);
-                    const PairCoef &c = MULTI ? s_pair[ti * a.ntypes + pt[v]] : a.single;
+                    const PairCoef &c = MULTI ? s_pair[ti * P.ntypes + pt[v]] : single;
                     if (pv[v] && r2 < c.rc2)
                         pair_term<PREC, ENERGY>(c, dx, dy, dz, r2, acc, ue, w0, w1, w2, w3, w4, w5);
                 }
@@ -467,7 +474,10 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
         if (active && lane == 0) {
             const bool finite =
                 __builtin_isfinite(fx) && __builtin_isfinite(fy) && __builtin_isfinite(fz);
-            if (!finite) atomicOr(a.status, ST_NONFINITE);
+            if (!finite) {
+                atomicOr(a.status, ST_NONFINITE);
+                if (a.rep_status) atomicOr(&a.rep_status[rep], ST_NONFINITE);
+            }
             if (ENERGY) {
                 a.u_out[q] = ue;
                 double *w = a.w_out + 6 * (size_t)q;
@@ -477,14 +487,16 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                 a.force[q] = make_double4(fx, fy, fz, 0.0);
             } else {
                 double4 v = v_pre;
-                const double hm = a.half_dt * v.w;
+                const double hm = P.half_dt * v.w;
                 // second half kick of the current step: full-step velocity
                 v.x = __builtin_fma(hm, fx, v.x);
                 v.y = __builtin_fma(hm, fy, v.y);
                 v.z = __builtin_fma(hm, fz, v.z);
-                if (MODE == MODE_FINAL) {
+                if (MODE == MODE_FINAL || last) {
+                    // the replica's last step: no drift; the position stays in place
                     a.vel[q] = v;
                     a.force[q] = make_double4(fx, fy, fz, 0.0);
+                    if (MODE == MODE_FUSED) a.pos_out[q] = xi;
                 } else {
                     if (ENERGY) {
                         const double m = 1.0 / v.w;
@@ -495,9 +507,9 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                     v.y = __builtin_fma(hm, fy, v.y);
                     v.z = __builtin_fma(hm, fz, v.z);
                     double4 x = xi;
-                    x.x = __builtin_fma(a.dt, v.x, x.x);
-                    x.y = __builtin_fma(a.dt, v.y, x.y);
-                    x.z = __builtin_fma(a.dt, v.z, x.z);
+                    x.x = __builtin_fma(P.dt, v.x, x.x);
+                    x.y = __builtin_fma(P.dt, v.y, x.y);
+                    x.z = __builtin_fma(P.dt, v.z, x.z);
                     int4 im = im_pre;
                     const int4 im0 = im;
                     wrap_coord(x.x, im.x, L0);
@@ -509,14 +521,15 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                     const double ex = mi_rint(x.x - b_pre.x, L0, iL0);
                     const double ey = mi_rint(x.y - b_pre.y, L1, iL1);
                     const double ez = mi_rint(x.z - b_pre.z, L2, iL2);
-                    exceed = r2_canon(ex, ey, ez) >= a.lim2;
+                    exceed = r2_canon(ex, ey, ez) >= P.lim2;
                 }
             }
         }
         if (MODE == MODE_FUSED) {
+            // all particles of the workgroup belong to one replica: one atomic per wavefront
             const unsigned long long vote = __ballot(exceed);
             if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1)
-                atomicOr(a.rebuild_set, 1);
+                atomicOr(&a.req[2 * rep + (a.cur ^ 1)], 1);
         }
     }
 }
@@ -531,38 +544,57 @@ template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI>
 __global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
     extern __shared__ double dyn_smem[];
     __shared__ TileSmem t;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const BrickInfo bi = a.bricks[b];
+    const int rep = bi.rep;
+    if (rep < 0) return;
+    const RepParams &P = a.reps[rep];
+    if (!P.active || (a.only && !a.only[rep])) return;
+    // steps left for this replica: >= 2 full step, 1 last step, 0 finished (positions kept)
+    int r_in = 2;
+    if (MODE == MODE_FUSED) {
+        if (a.rem) r_in = a.rem[2 * rep + a.cur];
+        if (b == P.boff && threadIdx.x == 0) {
+            if (a.rem) a.rem[2 * rep + (a.cur ^ 1)] = r_in > 0 ? r_in - 1 : 0;
+            a.req[2 * rep + a.cur] = 0;  // the request for this buffer was served
+        }
+    }
+    const int first = a.cell_start[bi.first_cell];
+    const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
+    if (MODE == MODE_FUSED && r_in <= 0) {
+        for (int k = threadIdx.x; k < natoms; k += blockDim.x)
+            a.pos_out[first + k] = a.pos_in[first + k];
+        return;
+    }
     double *sx = dyn_smem;
     double *sy = sx + a.tile_cap;
     double *sz = sy + a.tile_cap;
     int *sty = reinterpret_cast<int *>(sz + a.tile_cap);
     PairCoef *s_pair = reinterpret_cast<PairCoef *>(sz + a.tile_cap + (a.tile_cap + 1) / 2);
     if (MULTI)
-        for (int k = threadIdx.x; k < a.ntypes * a.ntypes; k += blockDim.x) s_pair[k] = a.pair[k];
-    if (MODE == MODE_FUSED && blockIdx.x == 0 && threadIdx.x == 0) *a.rebuild_clear = 0;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const BrickInfo bi = a.bricks[b];
+        for (int k = threadIdx.x; k < P.ntypes * P.ntypes; k += blockDim.x)
+            s_pair[k] = a.pair[P.pair_off + k];
+    const PairCoef single = a.pair[P.pair_off];
     tile_load(a.tile_tab + (size_t)b * TILE_TAB, t);
     const bool staged = t.total <= a.tile_cap;
     if (staged) tile_stage<MULTI>(t, a.pos_in, sx, sy, sz, sty);
-
-    const int first = a.cell_start[bi.first_cell];
-    const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
+    const bool last = MODE == MODE_FUSED && r_in == 1;
     const int mif = (bi.dims >> MI_FREE_SHIFT) & 7;
     if (staged && mif == 7)
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, true>(a, t, sx, sy, sz, sty, s_pair,
-                                                                 first, natoms);
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, true>(
+            a, t, sx, sy, sz, sty, s_pair, single, P, rep, last, first, natoms);
     else if (staged)
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, false>(a, t, sx, sy, sz, sty, s_pair,
-                                                                  first, natoms);
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, false>(
+            a, t, sx, sy, sz, sty, s_pair, single, P, rep, last, first, natoms);
     else
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, false, false>(a, t, sx, sy, sz, sty, s_pair,
-                                                                   first, natoms);
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, false, false>(
+            a, t, sx, sy, sz, sty, s_pair, single, P, rep, last, first, natoms);
 }
 
 template <int PREC, int TPP, int MODE, bool ENERGY>
 static hipError_t launch_force_t(hipStream_t s, const ForceArgs &a, int block) {
-    const size_t smem = force_lds_bytes(a.tile_cap, a.ntypes);
-    if (a.ntypes > 1)
+    const size_t smem = force_lds_bytes(a.tile_cap, a.max_ntypes);
+    if (a.max_ntypes > 1)
         hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, true>), dim3(a.nbrick), dim3(block),
                            smem, s, a);
     else
@@ -614,21 +646,29 @@ __device__ __forceinline__ int cell_coord(double f, int nc) {
     return f > 0.0 ? (int)fmin(f, (double)(nc - 1)) : 0;
 }
 
+// Replica of particle q / cell c and whether it takes part in this rebuild.
+__device__ __forceinline__ bool rebuilds(const RebuildArgs &a, int rep) {
+    return rep >= 0 && a.reps[rep].active && a.go[rep * a.go_stride] != 0;
+}
+
 // Cell of each particle; the slot inside its cell comes from an integer atomic counter
 // (the order is made deterministic afterwards by k_cell_gather). Particles are still in the
 // previous build's cell order, so equal cells come in runs along a wavefront: each run
 // takes its slots with one atomic add by its first lane.
 __global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
-    if (*a.go == 0) return;
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int wl = threadIdx.x & 63;
     int r = -1;
     if (q < a.n) {
-        const double4 x = a.pos[q];
-        const int cx = cell_coord(x.x * a.inv_w[0], a.nc[0]);
-        const int cy = cell_coord(x.y * a.inv_w[1], a.nc[1]);
-        const int cz = cell_coord(x.z * a.inv_w[2], a.nc[2]);
-        r = a.cell_rank[(cx * a.nc[1] + cy) * a.nc[2] + cz];
+        const int rep = a.prep ? a.prep[q] : 0;
+        if (rebuilds(a, rep)) {
+            const RepParams &P = a.reps[rep];
+            const double4 x = a.pos[q];
+            const int cx = cell_coord(x.x * P.inv_w[0], P.nc[0]);
+            const int cy = cell_coord(x.y * P.inv_w[1], P.nc[1]);
+            const int cz = cell_coord(x.z * P.inv_w[2], P.nc[2]);
+            r = a.cell_rank[P.coff + (cx * P.nc[1] + cy) * P.nc[2] + cz];
+        }
     }
     const int prev = __shfl_up(r, 1);
     const bool head = (wl == 0) || (r != prev);
@@ -646,11 +686,14 @@ __global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
     }
 }
 
-// Exclusive scan of the cell counts into cell_start[0..ncell], one workgroup of 1024
-// threads, in tiles of SCAN_TILE counts staged through LDS with coalesced loads; the counts
-// are zeroed for the next build.
+// Exclusive scan of a replica's cell counts into cell_start[coff .. coff + ncell], starting
+// at its first particle slot. One workgroup of 1024 threads per replica, in tiles of
+// SCAN_TILE counts staged through LDS with coalesced loads; the counts are zeroed for the
+// next build.
 __global__ void __launch_bounds__(1024) k_scan(const RebuildArgs a) {
-    if (*a.go == 0) return;
+    const int rep = blockIdx.x;
+    if (!rebuilds(a, rep)) return;
+    const RepParams &P = a.reps[rep];
     __shared__ int s_val[SCAN_TILE];
     __shared__ int s_sum[1024];
     __shared__ int s_carry;
@@ -658,16 +701,18 @@ __global__ void __launch_bounds__(1024) k_scan(const RebuildArgs a) {
     const int t = threadIdx.x;
     constexpr int PER = SCAN_TILE / 1024;
     if (t == 0) {
-        s_carry = 0;
-        a.st->entries = 0ull;
+        s_carry = P.poff;
+        if (rep == 0) a.st->entries = 0ull;
     }
-    for (int base = 0; base < a.ncell; base += SCAN_TILE) {
-        const int len = min(SCAN_TILE, a.ncell - base);
+    int *cs = a.cell_start + P.coff;
+    int *cc = a.cell_count + P.coff;
+    for (int base = 0; base < P.ncell; base += SCAN_TILE) {
+        const int len = min(SCAN_TILE, P.ncell - base);
         for (int u = t; u < SCAN_TILE; u += T) {
             int v = 0;
             if (u < len) {
-                v = a.cell_count[base + u];
-                a.cell_count[base + u] = 0;
+                v = cc[base + u];
+                cc[base + u] = 0;
             }
             s_val[u] = v;
         }
@@ -689,18 +734,18 @@ __global__ void __launch_bounds__(1024) k_scan(const RebuildArgs a) {
             run += k;
         }
         __syncthreads();
-        for (int u = t; u < len; u += T) a.cell_start[base + u] = s_val[u];
+        for (int u = t; u < len; u += T) cs[base + u] = s_val[u];
         __syncthreads();
         if (t == T - 1) s_carry += s_sum[T - 1];
         __syncthreads();
     }
-    if (t == 0) a.cell_start[a.ncell] = s_carry;
+    if (t == 0) cs[P.ncell] = s_carry;
 }
 
 __global__ void __launch_bounds__(256) k_scatter(const RebuildArgs a) {
-    if (*a.go == 0) return;
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.n) return;
+    if (!rebuilds(a, a.prep ? a.prep[q] : 0)) return;
     a.perm[a.cell_start[a.key[q]] + a.slot[q]] = q;
 }
 
@@ -714,9 +759,9 @@ __device__ __forceinline__ void gather_member(const RebuildArgs &a, int dst, int
 }
 
 __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
-    if (*a.go == 0) return;
     __shared__ int s_in[SORT_LDS];
     for (int c = blockIdx.x; c < a.ncell; c += gridDim.x) {
+        if (!rebuilds(a, a.crep ? a.crep[c] : 0)) continue;  // uniform per workgroup
         const int beg = a.cell_start[c];
         const int m = a.cell_start[c + 1] - beg;
         __syncthreads();  // s_in of the previous cell is no longer read
@@ -760,13 +805,14 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                                             const double *__restrict__ sy,
                                             const double *__restrict__ sz,
                                             const int *__restrict__ sty, const double *s_rl2,
-                                            int &my_max, unsigned long long &my_entries) {
+                                            const RepParams &P, int &my_max,
+                                            unsigned long long &my_entries) {
     const int hy = (bi.dims >> 4) & 15, hz = (bi.dims >> 8) & 15;
     const int fpk = a.cell_xyz[bi.first_cell];
     const int wl = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nwave = blockDim.x >> 6;
-    const int nst = a.canonical_mi ? t.nhalo : 27;
+    const int nst = P.canonical ? t.nhalo : 27;
     for (int ci = wave; ci < bi.ncell; ci += nwave) {
         const int rank = bi.first_cell + ci;
         const int pk = a.cell_xyz[rank];
@@ -791,17 +837,17 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
             const int ti = MULTI ? (int)xi.w : 0;
             int count = 0;
             for (int s = 0; s < nst; ++s) {
-                const int h = a.canonical_mi
+                const int h = P.canonical
                                   ? s
                                   : ((lx + s / 9) * hy + (ly + (s / 3) % 3)) * hz + (lz + s % 3);
                 const int o = t.off[h];
                 const int m = t.off[h + 1] - o;
                 const int jst = t.start[h];
                 const int code = t.shift[h];
-                const bool shifted = !a.canonical_mi && code != 21;  // 21: no shift on any axis
-                const double shx = (double)((code & 3) - 1) * a.L[0];
-                const double shy = (double)(((code >> 2) & 3) - 1) * a.L[1];
-                const double shz = (double)(((code >> 4) & 3) - 1) * a.L[2];
+                const bool shifted = !P.canonical && code != 21;  // 21: no shift on any axis
+                const double shx = (double)((code & 3) - 1) * P.L[0];
+                const double shy = (double)(((code >> 2) & 3) - 1) * P.L[1];
+                const double shz = (double)(((code >> 4) & 3) - 1) * P.L[2];
                 for (int t0 = 0; t0 < m; t0 += Ln) {
                     const int tt = t0 + lane;
                     const bool valid = active && tt < m;
@@ -821,17 +867,17 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                         tj = (int)pj.w;
                     }
                     double dx = xjx - xi.x, dy = xjy - xi.y, dz = xjz - xi.z;
-                    if (a.canonical_mi) {
-                        dx = mi_branch(dx, a.L[0]);
-                        dy = mi_branch(dy, a.L[1]);
-                        dz = mi_branch(dz, a.L[2]);
+                    if (P.canonical) {
+                        dx = mi_branch(dx, P.L[0]);
+                        dy = mi_branch(dy, P.L[1]);
+                        dz = mi_branch(dz, P.L[2]);
                     } else if (shifted) {
                         dx = dx + shx;  // adding 0.0 is exact
                         dy = dy + shy;
                         dz = dz + shz;
                     }
                     const double r2 = r2_canon(dx, dy, dz);
-                    const double rl2 = MULTI ? s_rl2[ti * a.ntypes + tj] : a.single_rl2;
+                    const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.single_rl2;
                     const bool hit = valid && (jst + tt) != q && r2 < rl2;
                     const unsigned long long bal = __ballot(hit) & gmask;
                     if (hit) {
@@ -847,7 +893,10 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
             }
             if (active && lane == 0) {
                 a.nl_count[q] = count;
-                if (count > a.cap) atomicOr(&a.st->status, ST_OVERFLOW);
+                if (count > a.cap) {
+                    atomicOr(&a.st->status, ST_OVERFLOW);
+                    if (a.rep_status) atomicOr(&a.rep_status[bi.rep], ST_OVERFLOW);
+                }
                 my_max = count > my_max ? count : my_max;
                 my_entries += (unsigned long long)(count < a.cap ? count : a.cap);
             }
@@ -872,7 +921,10 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
 // With fewer than 3 cells on some axis the branch form is applied directly.
 template <bool MULTI>
 __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
-    if (*a.go == 0) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const BrickInfo bi = a.bricks[b];
+    if (!rebuilds(a, bi.rep)) return;
+    const RepParams &P = a.reps[bi.rep];
     extern __shared__ double dyn_smem[];
     __shared__ TileSmem t;
     double *sx = dyn_smem;
@@ -881,10 +933,9 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
     int *sty = reinterpret_cast<int *>(sz + a.tile_cap);
     double *s_rl2 = sz + a.tile_cap + (a.tile_cap + 1) / 2;
     if (MULTI)
-        for (int k = threadIdx.x; k < a.ntypes * a.ntypes; k += blockDim.x) s_rl2[k] = a.rl2_table[k];
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.st->builds, 1ull);
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const BrickInfo bi = a.bricks[b];
+        for (int k = threadIdx.x; k < P.ntypes * P.ntypes; k += blockDim.x)
+            s_rl2[k] = a.rl2_table[P.pair_off + k];
+    if (b == P.boff && threadIdx.x == 0) atomicAdd(&a.st->builds, 1ull);
     tile_setup(bi, a.halo + (size_t)b * HALO_MAX, a.cell_start, t);
     tile_save(t, a.tile_tab + (size_t)b * TILE_TAB);
     // the permuted state of the brick's particles becomes the main state and the new build
@@ -902,7 +953,10 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
         if (t.total > TILE_INDEX_MAX) {
             // 16-bit tile indices cannot address this tile: no list for the brick
             for (int q = first + (int)threadIdx.x; q < last; q += blockDim.x) a.nl_count[q] = 0;
-            if (threadIdx.x == 0) atomicOr(&a.st->status, ST_TILE);
+            if (threadIdx.x == 0) {
+                atomicOr(&a.st->status, ST_TILE);
+                if (a.rep_status) atomicOr(&a.rep_status[bi.rep], ST_TILE);
+            }
             return;
         }
     }
@@ -913,9 +967,9 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
     int my_max = 0;
     unsigned long long my_entries = 0ull;
     if (staged)
-        nlist_cells<MULTI, true>(a, t, bi, sx, sy, sz, sty, s_rl2, my_max, my_entries);
+        nlist_cells<MULTI, true>(a, t, bi, sx, sy, sz, sty, s_rl2, P, my_max, my_entries);
     else
-        nlist_cells<MULTI, false>(a, t, bi, sx, sy, sz, sty, s_rl2, my_max, my_entries);
+        nlist_cells<MULTI, false>(a, t, bi, sx, sy, sz, sty, s_rl2, P, my_max, my_entries);
 
     // wavefront reductions of the build statistics, one atomic each per wavefront
     for (int o = 32; o > 0; o >>= 1) {
@@ -933,6 +987,7 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
 __global__ void __launch_bounds__(256) k_decode_list(const RebuildArgs a, int *out) {
     __shared__ TileSmem t;
     const BrickInfo bi = a.bricks[blockIdx.x];
+    if (bi.rep < 0 || !a.reps[bi.rep].active) return;
     tile_setup(bi, a.halo + (size_t)blockIdx.x * HALO_MAX, a.cell_start, t);
     const int first = a.cell_start[bi.first_cell];
     const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
@@ -954,11 +1009,11 @@ hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
     const int b = 256;
     const int g = (a.n + b - 1) / b;
     hipLaunchKernelGGL(k_bin, dim3(g), dim3(b), 0, s, a);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_scan, dim3(a.nrep), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(b), 0, s, a);
     hipLaunchKernelGGL(k_cell_gather, dim3(a.ncell < 8192 ? a.ncell : 8192), dim3(64), 0, s, a);
-    const size_t smem = nlist_lds_bytes(a.tile_cap, a.ntypes);
-    if (a.ntypes > 1)
+    const size_t smem = nlist_lds_bytes(a.tile_cap, a.max_ntypes);
+    if (a.max_ntypes > 1)
         hipLaunchKernelGGL(k_nlist<true>, dim3(a.nbrick), dim3(512), smem, s, a);
     else
         hipLaunchKernelGGL(k_nlist<false>, dim3(a.nbrick), dim3(512), smem, s, a);
@@ -967,20 +1022,22 @@ hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
 
 // ---------------------------------------------------------------- reductions
 
-// Deterministic FP64 sums of U, W[6] and K: each workgroup adds a fixed strided subset in
-// a fixed order and tree-reduces it in LDS; one workgroup then reduces the partials the
-// same way. K is taken from ke[] when given, else from the stored velocities.
+// Deterministic FP64 sums of U, W[6] and K over particles [poff, poff + n): each workgroup
+// adds a fixed strided subset in a fixed order and tree-reduces it in LDS; one workgroup
+// then reduces the partials the same way. K is taken from ke[] when given, else from the
+// stored velocities.
 __global__ void __launch_bounds__(RED_BLOCK) k_reduce_partials(const double *u, const double *w,
                                                                 const double *ke,
-                                                                const double4 *vel, int n,
-                                                                double *partials) {
+                                                                const double4 *vel, int poff,
+                                                                int n, double *partials) {
     __shared__ double s[RED_QUANT][RED_BLOCK];
     double acc[RED_QUANT];
     for (int c = 0; c < RED_QUANT; ++c) acc[c] = 0.0;
     const int stride = gridDim.x * blockDim.x;
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const size_t q = (size_t)poff + k;
         acc[0] += u[q];
-        for (int c = 0; c < 6; ++c) acc[1 + c] += w[6 * (size_t)q + c];
+        for (int c = 0; c < 6; ++c) acc[1 + c] += w[6 * q + c];
         if (ke) {
             acc[7] += ke[q];
         } else {
@@ -1019,12 +1076,12 @@ __global__ void __launch_bounds__(RED_BLOCK) k_reduce_final(const double *partia
 }
 
 hipError_t launch_reduce(hipStream_t s, const double *u, const double *w, const double *ke,
-                         const double4 *vel, int n, double *partials, int nblocks_max,
+                         const double4 *vel, int poff, int n, double *partials, int nblocks_max,
                          double *out) {
     int g = (n + RED_BLOCK - 1) / RED_BLOCK;
     if (g > nblocks_max) g = nblocks_max;
     if (g < 1) g = 1;
-    hipLaunchKernelGGL(k_reduce_partials, dim3(g), dim3(RED_BLOCK), 0, s, u, w, ke, vel, n,
+    hipLaunchKernelGGL(k_reduce_partials, dim3(g), dim3(RED_BLOCK), 0, s, u, w, ke, vel, poff, n,
                        partials);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_BLOCK), 0, s, partials, g, out);
     return hipGetLastError();
@@ -1032,66 +1089,77 @@ hipError_t launch_reduce(hipStream_t s, const double *u, const double *w, const 
 
 // ---------------------------------------------------------------- outputs in tag order
 
-__global__ void k_unsort_vec(const double4 *src, const int4 *img, int n, double *dst) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const double4 v = src[q];
-    const int t = img[q].w;
+// Particles [poff, poff + n) hold tags 0 .. n-1 (in img.w); outputs are written by tag.
+__global__ void k_unsort_vec(const double4 *src, const int4 *img, int poff, int n, double *dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double4 v = src[poff + k];
+    const int t = img[poff + k].w;
     dst[3 * (size_t)t] = v.x;
     dst[3 * (size_t)t + 1] = v.y;
     dst[3 * (size_t)t + 2] = v.z;
 }
 
-__global__ void k_unsort_img(const int4 *img, int n, int *dst) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const int4 v = img[q];
+__global__ void k_unsort_img(const int4 *img, int poff, int n, int *dst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int4 v = img[poff + k];
     dst[3 * (size_t)v.w] = v.x;
     dst[3 * (size_t)v.w + 1] = v.y;
     dst[3 * (size_t)v.w + 2] = v.z;
 }
 
-__global__ void k_unsort_scalar(const double *src, int width, const int4 *img, int n,
+__global__ void k_unsort_scalar(const double *src, int width, const int4 *img, int poff, int n,
                                 double *dst) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
-    const int t = img[q].w;
-    for (int c = 0; c < width; ++c) dst[(size_t)width * t + c] = src[(size_t)width * q + c];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int t = img[poff + k].w;
+    for (int c = 0; c < width; ++c)
+        dst[(size_t)width * t + c] = src[(size_t)width * (poff + k) + c];
 }
 
-hipError_t launch_unsort_vec(hipStream_t s, const double4 *src, const int4 *img, int n,
+hipError_t launch_unsort_vec(hipStream_t s, const double4 *src, const int4 *img, int poff, int n,
                              double *dst) {
-    hipLaunchKernelGGL(k_unsort_vec, dim3((n + 255) / 256), dim3(256), 0, s, src, img, n, dst);
+    hipLaunchKernelGGL(k_unsort_vec, dim3((n + 255) / 256), dim3(256), 0, s, src, img, poff, n,
+                       dst);
     return hipGetLastError();
 }
 
-hipError_t launch_unsort_img(hipStream_t s, const int4 *img, int n, int *dst) {
-    hipLaunchKernelGGL(k_unsort_img, dim3((n + 255) / 256), dim3(256), 0, s, img, n, dst);
+hipError_t launch_unsort_img(hipStream_t s, const int4 *img, int poff, int n, int *dst) {
+    hipLaunchKernelGGL(k_unsort_img, dim3((n + 255) / 256), dim3(256), 0, s, img, poff, n, dst);
     return hipGetLastError();
 }
 
 hipError_t launch_unsort_scalar(hipStream_t s, const double *src, int width, const int4 *img,
-                                int n, double *dst) {
-    hipLaunchKernelGGL(k_unsort_scalar, dim3((n + 255) / 256), dim3(256), 0, s, src, width,
-                       img, n, dst);
+                                int poff, int n, double *dst) {
+    hipLaunchKernelGGL(k_unsort_scalar, dim3((n + 255) / 256), dim3(256), 0, s, src, width, img,
+                       poff, n, dst);
     return hipGetLastError();
 }
 
 __global__ void k_fill_status(DevStatus *st) {
     if (threadIdx.x == 0) {
-        st->rebuild[0] = 0;
-        st->rebuild[1] = 0;
         st->status = 0;
         st->max_count = 0;
         st->builds = 0ull;
         st->entries = 0ull;
-        st->one = 1;
         st->pad = 0;
     }
 }
 
 hipError_t launch_fill_status(hipStream_t s, DevStatus *st) {
     hipLaunchKernelGGL(k_fill_status, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_int(int *p, int n, int value) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = value;
+}
+
+hipError_t launch_fill_int(hipStream_t s, int *p, int n, int value) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, s, p, n, value);
     return hipGetLastError();
 }
 

@@ -1,9 +1,10 @@
-// Host side of libljmd: the C ABI of include/ljmd.h for one system.
+// Host side of libljmd: the single-system C ABI of include/ljmd.h. For the kernels a
+// system is a batch of one replica (a parameter table of one entry, all offsets 0).
 //
 // Step structure (velocity Verlet, NVE). With x(t), v(t) and F(t) on the device:
 //   kick-drift kernel        v += dt/2m F(t); x(t+1) = x + dt v, wrapped, written into the
 //                            other position buffer; raises the rebuild request if needed.
-//   gated rebuild kernels    bin -> scan -> scatter -> in-cell sort -> permute -> Verlet
+//   gated rebuild kernels    bin -> scan -> scatter -> in-cell sort and gather -> Verlet
 //                            build; every kernel returns at once unless the request is set.
 //   n-1 times: fused kernel  F(t+1) at x(t+1); v += dt/2m F (full step); v += dt/2m F;
 //                            x(t+2) into the other buffer; rebuild request; gated rebuild.
@@ -12,54 +13,20 @@
 // into a HIP graph of `graph_steps` units. Host and device meet once per call, at the end,
 // to read the status word: on list overflow the call restores its starting state, grows
 // the list and runs again; on a non-finite force it restores and returns an error.
-#include "ljmd_internal.h"
-#include "../../include/ljmd.h"
+#include "ljmd_host.h"
 
 #include <algorithm>
 #include <cmath>
-#include <cstdarg>
-#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
-#include <string>
+#include <new>
 #include <tuple>
 #include <vector>
 
 using namespace ljmd;
 
 namespace {
-
-thread_local std::string g_err;
-
-int set_err(int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return code;
-}
-
-#define HIPCHK(expr)                                                                        \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return set_err(LJMD_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));          \
-    } while (0)
-
-#define CHK(expr)                   \
-    do {                            \
-        int r_ = (expr);            \
-        if (r_ != LJMD_OK) return r_; \
-    } while (0)
-
-uint64_t spread3(uint64_t v) {  // 10-bit value -> every third bit
-    uint64_t r = 0;
-    for (int b = 0; b < 10; ++b) r |= ((v >> b) & 1ull) << (3 * b);
-    return r;
-}
 
 struct TuneKey {
     int prec, multi, nbucket;
@@ -77,8 +44,10 @@ struct ljmd_system {
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;
+    DeviceArena mem;
+    size_t lds_limit = 64 * 1024;
     int n = 0, npad = 0;
-    double L[3]{}, invL[3]{};
+    double L[3]{};
     int ntypes = 1;
     std::vector<double> eps, sig, rc;
     std::vector<char> is_set;
@@ -86,16 +55,20 @@ struct ljmd_system {
     std::vector<double> h_mass;
     bool table_dirty = true;
     double rl_max = 0.0;
-    PairCoef single{};
+    RepParams rep{};  // host copy of the replica parameters
     // device memory
-    std::vector<std::pair<void *, size_t>> allocs;
-    int64_t bytes = 0;
+    RepParams *d_rep = nullptr;
     PairCoef *d_pair = nullptr;
     double *d_rl2 = nullptr;
-    int nc[3]{0, 0, 0};
+    int *d_req = nullptr;  // rebuild requests, one per position buffer
+    int *d_one = nullptr;  // constant 1: the go word of an unconditional rebuild
     int ncell = 0, ncell_alloc = 0;
     int *d_cell_rank = nullptr, *d_cell_xyz = nullptr, *d_cell_count = nullptr,
         *d_cell_start = nullptr;
+    BrickInfo *d_bricks = nullptr;
+    HaloCell *d_halo = nullptr;
+    int *d_tile_tab = nullptr;
+    int nbrick = 0, nbrick_alloc = 0, tile_cap = 0;
     double4 *d_pos[2]{}, *d_pos_scr = nullptr, *d_vel = nullptr, *d_vel_scr = nullptr,
             *d_force = nullptr, *d_xb = nullptr;
     int4 *d_img = nullptr, *d_img_scr = nullptr;
@@ -103,12 +76,6 @@ struct ljmd_system {
     int *d_count = nullptr;
     uint16_t *d_nlist = nullptr;
     int cap = 0;
-    BrickInfo *d_bricks = nullptr;
-    HaloCell *d_halo = nullptr;
-    int *d_tile_tab = nullptr;
-    int nbrick = 0, nbrick_alloc = 0, tile_cap = 0;
-    bool canonical = false;
-    size_t lds_limit = 64 * 1024;
     size_t nlist_alloc = 0;
     double *d_u = nullptr, *d_w = nullptr, *d_ke = nullptr, *d_partials = nullptr,
            *d_red = nullptr;
@@ -132,42 +99,12 @@ struct ljmd_system {
 
 namespace {
 
-int dalloc(ljmd_system *s, void **p, size_t bytes) {
-    *p = nullptr;
-    if (bytes == 0) bytes = 256;
-    if (s->cfg.alloc) {
-        *p = s->cfg.alloc(bytes, s->stream, s->cfg.alloc_ctx);
-        if (!*p) return set_err(LJMD_E_NOMEM, "allocator returned NULL for %zu bytes", bytes);
-    } else {
-        hipError_t e = hipMalloc(p, bytes);
-        if (e != hipSuccess || !*p)
-            return set_err(LJMD_E_NOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
-    }
-    s->allocs.emplace_back(*p, bytes);
-    s->bytes += (int64_t)bytes;
-    return LJMD_OK;
-}
-
-void dfree(ljmd_system *s, void *p) {
-    if (!p) return;
-    for (size_t k = 0; k < s->allocs.size(); ++k) {
-        if (s->allocs[k].first == p) {
-            size_t b = s->allocs[k].second;
-            if (s->cfg.free)
-                s->cfg.free(p, b, s->stream, s->cfg.alloc_ctx);
-            else
-                (void)hipFree(p);
-            s->bytes -= (int64_t)b;
-            s->allocs.erase(s->allocs.begin() + (long)k);
-            return;
-        }
-    }
-}
-
 template <class T>
 int dalloc_t(ljmd_system *s, T **p, size_t count) {
-    return dalloc(s, (void **)p, count * sizeof(T));
+    return s->mem.get_t(p, count);
 }
+
+void dfree(ljmd_system *s, void *p) { s->mem.put(p); }
 
 void drop_graphs(ljmd_system *s) {
     for (int c = 0; c < 2; ++c)
@@ -184,8 +121,15 @@ int sync_status(ljmd_system *s, DevStatus *out) {
 }
 
 int clear_status_bits(ljmd_system *s) {
-    // status and max_count words only; requests and counters stay
+    // status and max_count words only; the counters stay
     HIPCHK(hipMemsetAsync(&s->d_st->status, 0, 2 * sizeof(int), s->stream));
+    return LJMD_OK;
+}
+
+int precision(ljmd_system *s) { return s->cfg.precision == LJMD_MIXED ? PREC_MIXED : PREC_FP64; }
+
+int launch_chk(hipError_t e, const char *what) {
+    if (e != hipSuccess) return set_err(LJMD_E_DEVICE, "launch of %s: %s", what, hipGetErrorString(e));
     return LJMD_OK;
 }
 
@@ -196,183 +140,79 @@ int setup_table(ljmd_system *s) {
     for (int k = 0; k < nt * nt; ++k)
         if (!s->is_set[k])
             return set_err(LJMD_E_STATE, "pair (%d,%d) has not been set", k / nt, k % nt);
-    std::vector<PairCoef> tab(nt * nt);
-    std::vector<double> rl2(nt * nt);
-    double rl_max = 0.0;
-    for (int k = 0; k < nt * nt; ++k) {
-        PairCoef c{};
-        const double e = s->eps[k], sg = s->sig[k], r = s->rc[k];
-        if (r > 0.0) {
-            const double rl = r + s->cfg.skin;
-            c.rc2 = r * r;
-            c.rl2 = rl * rl;
-            rl_max = std::max(rl_max, rl);
-            const double s6 = sg * sg * sg * sg * sg * sg;
-            const double s12 = s6 * s6;
-            c.lj1 = 48.0 * e * s12;
-            c.lj2 = 24.0 * e * s6;
-            c.lj3 = 4.0 * e * s12;
-            c.lj4 = 4.0 * e * s6;
-            const double q2 = (sg * sg) / c.rc2;
-            const double q6 = q2 * q2 * q2;
-            c.shift = 4.0 * e * (q6 * q6 - q6);
-        }
-        tab[k] = c;
-        rl2[k] = c.rl2;
-    }
-    for (int a = 0; a < 3; ++a)
-        if (rl_max > 0.5 * s->L[a])
-            return set_err(LJMD_E_BOX, "r_cut + skin = %g exceeds half the box edge %g", rl_max,
-                           s->L[a]);
-    s->rl_max = rl_max;
-    s->single = tab[0];
-    HIPCHK(hipMemcpyAsync(s->d_pair, tab.data(), sizeof(PairCoef) * nt * nt,
-                          hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(s->d_rl2, rl2.data(), sizeof(double) * nt * nt, hipMemcpyHostToDevice,
-                          s->stream));
-    // cell grid: width >= the largest list radius (a relative margin keeps it strictly
-    // larger, so rounding in the binning can never hide a pair)
-    int nc[3];
-    for (int a = 0; a < 3; ++a) {
-        double r = rl_max > 0.0 ? rl_max * (1.0 + 1e-12) : s->L[a] / 3.0;
-        long v = (long)std::floor(s->L[a] / r);
-        if (v < 1) v = 1;
-        if (v > 1023) v = 1023;
-        nc[a] = (int)v;
-    }
-    const int ncell = nc[0] * nc[1] * nc[2];
-    if (ncell > s->ncell_alloc) {
+    PairTable pt;
+    make_pair_table(nt, s->eps.data(), s->sig.data(), s->rc.data(), s->cfg.skin, &pt);
+    ReplicaGrid g;
+    CHK(make_grid(s->L, pt.rl_max, &g));
+    const int ncell = g.ncell;
+    if (ncell + 1 > s->ncell_alloc) {
         dfree(s, s->d_cell_rank);
         dfree(s, s->d_cell_xyz);
         dfree(s, s->d_cell_count);
         dfree(s, s->d_cell_start);
-        CHK(dalloc_t(s, &s->d_cell_rank, ncell));
-        CHK(dalloc_t(s, &s->d_cell_xyz, ncell));
-        CHK(dalloc_t(s, &s->d_cell_count, ncell));
+        s->d_cell_rank = s->d_cell_xyz = s->d_cell_count = s->d_cell_start = nullptr;
+        s->ncell_alloc = 0;
+        CHK(dalloc_t(s, &s->d_cell_rank, ncell + 1));
+        CHK(dalloc_t(s, &s->d_cell_xyz, ncell + 1));
+        CHK(dalloc_t(s, &s->d_cell_count, ncell + 1));
         CHK(dalloc_t(s, &s->d_cell_start, ncell + 1));
-        s->ncell_alloc = ncell;
+        s->ncell_alloc = ncell + 1;
     }
-    // Bricks of up to 2 x 2 x 2 cells (one cell wide on an axis with fewer than 4 cells,
-    // single cells when some axis has fewer than 3), bricks in Morton order, cells in
-    // Morton order inside their brick: every brick is a contiguous range of cell ranks.
-    const bool canonical = nc[0] < 3 || nc[1] < 3 || nc[2] < 3;
-    int ext[3], nb[3];
-    for (int a = 0; a < 3; ++a) {
-        ext[a] = (!canonical && nc[a] >= 4) ? 2 : 1;
-        nb[a] = (nc[a] + ext[a] - 1) / ext[a];
-    }
-    const int nbrick = nb[0] * nb[1] * nb[2];
-    std::vector<std::pair<uint64_t, int>> bmort(nbrick);
-    for (int x = 0; x < nb[0]; ++x)
-        for (int y = 0; y < nb[1]; ++y)
-            for (int z = 0; z < nb[2]; ++z) {
-                const int lin = (x * nb[1] + y) * nb[2] + z;
-                bmort[lin] = {spread3(x) | (spread3(y) << 1) | (spread3(z) << 2), lin};
-            }
-    std::sort(bmort.begin(), bmort.end());
-    std::vector<int> rank(ncell), xyz(ncell);
-    std::vector<BrickInfo> bricks(nbrick);
-    std::vector<int> brick_lo(3 * nbrick), brick_n(3 * nbrick);
-    int next = 0;
-    for (int bo = 0; bo < nbrick; ++bo) {
-        const int lin = bmort[bo].second;
-        const int bz = lin % nb[2], by = (lin / nb[2]) % nb[1], bx = lin / (nb[1] * nb[2]);
-        const int lo[3] = {bx * ext[0], by * ext[1], bz * ext[2]};
-        int cn[3];
-        for (int a = 0; a < 3; ++a) cn[a] = std::min(ext[a], nc[a] - lo[a]);
-        BrickInfo &bi = bricks[bo];
-        bi.first_cell = next;
-        bi.ncell = 0;
-        for (int c = 0; c < 8; ++c) {
-            const int l[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
-            if (l[0] >= cn[0] || l[1] >= cn[1] || l[2] >= cn[2]) continue;
-            const int x = lo[0] + l[0], y = lo[1] + l[1], z = lo[2] + l[2];
-            rank[(x * nc[1] + y) * nc[2] + z] = next;
-            xyz[next] = x | (y << 10) | (z << 20);
-            ++next;
-            ++bi.ncell;
-        }
-        for (int a = 0; a < 3; ++a) {
-            brick_lo[3 * bo + a] = lo[a];
-            brick_n[3 * bo + a] = cn[a];
-        }
-    }
-    // halo of each brick: cells lo-1 .. lo+n per axis, seen in the periodic image given by
-    // the wrap; duplicates (fewer than 3 cells on an axis) keep their first occurrence
-    std::vector<HaloCell> halo((size_t)nbrick * HALO_MAX);
-    int max_halo = 0;
-    for (int bo = 0; bo < nbrick; ++bo) {
-        BrickInfo &bi = bricks[bo];
-        int hd[3];
-        for (int a = 0; a < 3; ++a) hd[a] = brick_n[3 * bo + a] + 2;
-        bi.dims = hd[0] | (hd[1] << 4) | (hd[2] << 8) | (brick_n[3 * bo] << 12) |
-                  (brick_n[3 * bo + 1] << 16) | (brick_n[3 * bo + 2] << 20);
-        for (int a = 0; a < 3; ++a) {
-            const int lo = brick_lo[3 * bo + a], hi = lo + brick_n[3 * bo + a];
-            if (!canonical && nc[a] >= 10 && lo - 1 >= 1 && hi <= nc[a] - 2)
-                bi.dims |= 1 << (MI_FREE_SHIFT + a);
-        }
-        int nh = 0;
-        for (int hx = 0; hx < hd[0]; ++hx)
-            for (int hy = 0; hy < hd[1]; ++hy)
-                for (int hz = 0; hz < hd[2]; ++hz) {
-                    const int hc[3] = {hx, hy, hz};
-                    int e[3], code = 0;
-                    for (int a = 0; a < 3; ++a) {
-                        int v = brick_lo[3 * bo + a] + hc[a] - 1;
-                        int sh = 0;
-                        if (v < 0) { v += nc[a]; sh = -1; }
-                        else if (v >= nc[a]) { v -= nc[a]; sh = 1; }
-                        e[a] = v;
-                        code |= (sh + 1) << (2 * a);
-                    }
-                    const int r = rank[(e[0] * nc[1] + e[1]) * nc[2] + e[2]];
-                    bool dup = false;
-                    if (canonical)
-                        for (int u = 0; u < nh; ++u) dup |= halo[(size_t)bo * HALO_MAX + u].rank == r;
-                    if (dup) continue;
-                    halo[(size_t)bo * HALO_MAX + nh] = HaloCell{r, code};
-                    ++nh;
-                }
-        bi.nhalo = nh;
-        max_halo = std::max(max_halo, nh);
-    }
-    if (nbrick > s->nbrick_alloc) {
+    if (g.nbrick > s->nbrick_alloc) {
         dfree(s, s->d_bricks);
         dfree(s, s->d_halo);
         dfree(s, s->d_tile_tab);
-        CHK(dalloc_t(s, &s->d_bricks, nbrick));
-        CHK(dalloc_t(s, &s->d_halo, (size_t)nbrick * HALO_MAX));
-        CHK(dalloc_t(s, &s->d_tile_tab, (size_t)nbrick * TILE_TAB));
-        s->nbrick_alloc = nbrick;
+        s->d_bricks = nullptr;
+        s->d_halo = nullptr;
+        s->d_tile_tab = nullptr;
+        s->nbrick_alloc = 0;
+        CHK(dalloc_t(s, &s->d_bricks, g.nbrick));
+        CHK(dalloc_t(s, &s->d_halo, (size_t)g.nbrick * HALO_MAX));
+        CHK(dalloc_t(s, &s->d_tile_tab, (size_t)g.nbrick * TILE_TAB));
+        s->nbrick_alloc = g.nbrick;
     }
-    HIPCHK(hipMemcpyAsync(s->d_bricks, bricks.data(), sizeof(BrickInfo) * nbrick,
-                          hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(s->d_halo, halo.data(), sizeof(HaloCell) * (size_t)nbrick * HALO_MAX,
-                          hipMemcpyHostToDevice, s->stream));
-    s->nbrick = nbrick;
-    s->canonical = canonical;
-    // LDS tile capacity: the expected halo occupancy with headroom, within the LDS a
-    // workgroup may use (larger tiles are read from global memory instead)
-    {
-        const double per_cell = (double)s->n / ncell;
-        const double expect = max_halo * per_cell;
-        int cap = (int)std::ceil(1.35 * expect + 128.0);
-        cap = (cap + 63) & ~63;
-        cap = std::min(cap, TILE_MAX);
-        const size_t limit = std::min<size_t>(s->lds_limit, 64 * 1024) - 4096;
-        while (cap > 64 && std::max(force_lds_bytes(cap, s->ntypes), nlist_lds_bytes(cap, s->ntypes)) > limit)
-            cap -= 64;
-        s->tile_cap = cap;
+    RepParams &P = s->rep;
+    P = RepParams{};
+    for (int a = 0; a < 3; ++a) {
+        P.L[a] = s->L[a];
+        P.invL[a] = 1.0 / s->L[a];
+        P.inv_w[a] = (double)g.nc[a] / s->L[a];
+        P.nc[a] = g.nc[a];
     }
-    HIPCHK(hipMemcpyAsync(s->d_cell_rank, rank.data(), sizeof(int) * ncell,
+    P.dt = s->cfg.dt;
+    P.half_dt = 0.5 * s->cfg.dt;
+    const double lim = 0.5 * s->cfg.skin;
+    P.lim2 = lim * lim;
+    P.single_rl2 = pt.coef[0].rl2;
+    P.poff = 0;
+    P.n = s->n;
+    P.coff = 0;
+    P.ncell = ncell;
+    P.boff = 0;
+    P.nbrick = g.nbrick;
+    P.canonical = g.canonical ? 1 : 0;
+    P.ntypes = nt;
+    P.pair_off = 0;
+    P.active = 1;
+    HIPCHK(hipMemcpyAsync(s->d_rep, &P, sizeof(RepParams), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_pair, pt.coef.data(), sizeof(PairCoef) * nt * nt,
                           hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(s->d_cell_xyz, xyz.data(), sizeof(int) * ncell, hipMemcpyHostToDevice,
+    HIPCHK(hipMemcpyAsync(s->d_rl2, pt.rl2.data(), sizeof(double) * nt * nt, hipMemcpyHostToDevice,
                           s->stream));
-    HIPCHK(hipMemsetAsync(s->d_cell_count, 0, sizeof(int) * ncell, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_cell_rank, g.rank.data(), sizeof(int) * ncell, hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_cell_xyz, g.xyz.data(), sizeof(int) * ncell, hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipMemsetAsync(s->d_cell_count, 0, sizeof(int) * (ncell + 1), s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_bricks, g.bricks.data(), sizeof(BrickInfo) * g.nbrick,
+                          hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_halo, g.halo.data(), sizeof(HaloCell) * (size_t)g.nbrick * HALO_MAX,
+                          hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));  // host vectors go out of scope
-    for (int a = 0; a < 3; ++a) s->nc[a] = nc[a];
+    s->rl_max = pt.rl_max;
     s->ncell = ncell;
+    s->nbrick = g.nbrick;
+    s->tile_cap = choose_tile_cap((double)s->n / ncell, g.max_halo, nt, s->lds_limit);
     s->table_dirty = false;
     s->list_valid = false;
     s->force_valid = false;
@@ -402,9 +242,14 @@ int round_cap(double v) { return std::max(8, (int)std::ceil(v)); }
 
 // ------------------------------------------------------------ argument blocks
 
+// go[0] is the rebuild's gate: a request word, or d_one for an unconditional rebuild
 RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
     RebuildArgs a{};
+    a.reps = s->d_rep;
+    a.prep = nullptr;  // every particle, cell and brick belongs to replica 0
+    a.crep = nullptr;
     a.go = go;
+    a.go_stride = 0;
     a.rl2_table = s->d_rl2;
     a.pos = s->d_pos[cur];
     a.pos_scr = s->d_pos_scr;
@@ -422,32 +267,25 @@ RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
     a.cell_xyz = s->d_cell_xyz;
     a.nl_count = s->d_count;
     a.nlist = s->d_nlist;
-    a.pair = s->d_pair;
-    a.st = s->d_st;
-    for (int d = 0; d < 3; ++d) {
-        a.L[d] = s->L[d];
-        a.invL[d] = s->invL[d];
-        a.inv_w[d] = (double)s->nc[d] / s->L[d];
-        a.nc[d] = s->nc[d];
-    }
-    a.single_rl2 = s->single.rl2;
-    a.ncell = s->ncell;
-    a.n = s->n;
-    a.npad = s->npad;
-    a.cap = s->cap;
-    a.lshift = s->lshift;
-    a.ntypes = s->ntypes;
-    a.canonical_mi = s->canonical ? 1 : 0;
     a.bricks = s->d_bricks;
     a.halo = s->d_halo;
     a.tile_tab = s->d_tile_tab;
+    a.st = s->d_st;
+    a.n = s->n;
+    a.ncell = s->ncell;
     a.nbrick = s->nbrick;
+    a.nrep = 1;
+    a.npad = s->npad;
+    a.cap = s->cap;
+    a.lshift = s->lshift;
     a.tile_cap = s->tile_cap;
+    a.max_ntypes = s->ntypes;
     return a;
 }
 
 ForceArgs force_args(ljmd_system *s, int cur) {
     ForceArgs a{};
+    a.reps = s->d_rep;
     a.pos_in = s->d_pos[cur];
     a.pos_out = s->d_pos[cur ^ 1];
     a.vel = s->d_vel;
@@ -457,69 +295,48 @@ ForceArgs force_args(ljmd_system *s, int cur) {
     a.nl_count = s->d_count;
     a.nlist = s->d_nlist;
     a.bricks = s->d_bricks;
-    a.halo = s->d_halo;
     a.cell_start = s->d_cell_start;
     a.tile_tab = s->d_tile_tab;
-    a.nbrick = s->nbrick;
-    a.tile_cap = s->tile_cap;
     a.u_out = s->d_u;
     a.w_out = s->d_w;
     a.ke_out = s->d_ke;
     a.pair = s->d_pair;
-    a.rebuild_set = &s->d_st->rebuild[cur ^ 1];
-    a.rebuild_clear = &s->d_st->rebuild[cur];
+    a.req = s->d_req;
+    a.rem = nullptr;  // no step budget: every fused step is a full step
+    a.only = nullptr;
     a.status = &s->d_st->status;
-    a.single = s->single;
-    for (int d = 0; d < 3; ++d) {
-        a.L[d] = s->L[d];
-        a.invL[d] = s->invL[d];
-    }
-    a.dt = s->cfg.dt;
-    a.half_dt = 0.5 * s->cfg.dt;
-    const double lim = 0.5 * s->cfg.skin;
-    a.lim2 = lim * lim;
-    a.n = s->n;
+    a.cur = cur;
     a.npad = s->npad;
     a.cap = s->cap;
     a.lshift = s->lshift;
-    a.ntypes = s->ntypes;
+    a.nbrick = s->nbrick;
+    a.tile_cap = s->tile_cap;
+    a.max_ntypes = s->ntypes;
     return a;
 }
 
 KickDriftArgs kick_drift_args(ljmd_system *s, int cur) {
     KickDriftArgs a{};
+    a.reps = s->d_rep;
+    a.prep = nullptr;
     a.pos_in = s->d_pos[cur];
     a.pos_out = s->d_pos[cur ^ 1];
     a.vel = s->d_vel;
     a.img = s->d_img;
     a.xb = s->d_xb;
     a.force = s->d_force;
-    a.rebuild_set = &s->d_st->rebuild[cur ^ 1];
-    a.rebuild_clear = &s->d_st->rebuild[cur];
-    for (int d = 0; d < 3; ++d) {
-        a.L[d] = s->L[d];
-        a.invL[d] = s->invL[d];
-    }
-    a.dt = s->cfg.dt;
-    a.half_dt = 0.5 * s->cfg.dt;
-    const double lim = 0.5 * s->cfg.skin;
-    a.lim2 = lim * lim;
+    a.req = s->d_req;
+    a.only = nullptr;
+    a.cur = cur;
     a.n = s->n;
     return a;
 }
 
-int launch_chk(hipError_t e, const char *what) {
-    if (e != hipSuccess) return set_err(LJMD_E_DEVICE, "launch of %s: %s", what, hipGetErrorString(e));
-    return LJMD_OK;
-}
-
 // unconditional rebuild at the current positions
 int enqueue_forced_rebuild(ljmd_system *s) {
-    RebuildArgs a = rebuild_args(s, &s->d_st->one, s->cur);
+    RebuildArgs a = rebuild_args(s, s->d_one, s->cur);
     return launch_chk(launch_rebuild(s->stream, a), "rebuild");
 }
-
-int precision(ljmd_system *s) { return s->cfg.precision == LJMD_MIXED ? PREC_MIXED : PREC_FP64; }
 
 int enqueue_eval(ljmd_system *s, bool energy) {
     ForceArgs a = force_args(s, s->cur);
@@ -545,7 +362,7 @@ int build_list(ljmd_system *s) {
     for (int attempt = 0; attempt < 8; ++attempt) {
         CHK(clear_status_bits(s));
         // a fresh list makes any pending rebuild request moot
-        HIPCHK(hipMemsetAsync(s->d_st->rebuild, 0, 2 * sizeof(int), s->stream));
+        HIPCHK(hipMemsetAsync(s->d_req, 0, 2 * sizeof(int), s->stream));
         CHK(enqueue_forced_rebuild(s));
         DevStatus st{};
         CHK(sync_status(s, &st));
@@ -592,9 +409,10 @@ double time_evals(ljmd_system *s, int reps) {
         return 1e30;
     }
     double best = 1e30;
-    if (enqueue_eval(s, false) == LJMD_OK) {  // warm
+    bool ok = true;
+    for (int r = 0; r < 3 && ok; ++r) ok = enqueue_eval(s, false) == LJMD_OK;  // clocks up
+    if (ok) {
         (void)hipEventRecord(e0, s->stream);
-        bool ok = true;
         for (int r = 0; r < reps && ok; ++r) ok = enqueue_eval(s, false) == LJMD_OK;
         (void)hipEventRecord(e1, s->stream);
         (void)hipEventSynchronize(e1);
@@ -670,7 +488,7 @@ int enqueue_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_ind
     CHK(launch_chk(launch_force(st, fa, precision(s), s->tpp, MODE_FUSED, false, s->block),
                    "fused step"));
     if (timed) HIPCHK(hipEventRecord(s->ev[2 * ev_index + 1], st));
-    RebuildArgs ra = rebuild_args(s, &s->d_st->rebuild[cur ^ 1], cur ^ 1);
+    RebuildArgs ra = rebuild_args(s, s->d_req + (cur ^ 1), cur ^ 1);
     return launch_chk(launch_rebuild(st, ra), "rebuild");
 }
 
@@ -732,7 +550,8 @@ int restore(ljmd_system *s, int cur0) {
     return LJMD_OK;
 }
 
-// One attempt at nsteps >= 1 steps from a ready state. Returns OK, or sets *overflow.
+// One attempt at nsteps >= 1 steps from a ready state; reports overflow and non-finite
+// forces through the flags.
 int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
     *overflow = false;
     *nonfinite = false;
@@ -742,10 +561,10 @@ int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
         KickDriftArgs ka = kick_drift_args(s, s->cur);
         CHK(launch_chk(launch_kick_drift(s->stream, ka), "kick-drift"));
         s->cur ^= 1;
-        RebuildArgs ra = rebuild_args(s, &s->d_st->rebuild[s->cur], s->cur);
+        RebuildArgs ra = rebuild_args(s, s->d_req + s->cur, s->cur);
         CHK(launch_chk(launch_rebuild(s->stream, ra), "rebuild"));
     }
-    int64_t units = nsteps - 1;
+    const int64_t units = nsteps - 1;
     const bool use_graph = s->graph_steps > 0 && !s->timing;
     if (s->timing) CHK(ensure_events(s, units));
     int64_t done = 0;
@@ -784,15 +603,34 @@ bool finite_array(const double *p, size_t k) {
     return true;
 }
 
+int fetch_vec(ljmd_system *s, const double4 *src, double *out) {
+    CHK(launch_chk(launch_unsort_vec(s->stream, src, s->d_img, 0, s->n, s->d_stage), "unsort"));
+    HIPCHK(hipMemcpyAsync(out, s->d_stage, 3 * (size_t)s->n * sizeof(double), hipMemcpyDeviceToHost,
+                          s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LJMD_OK;
+}
+
+int eval_thermo(ljmd_system *s, double red[RED_QUANT]) {
+    CHK(ensure_ready(s));
+    CHK(enqueue_eval(s, true));
+    CHK(launch_chk(launch_reduce(s->stream, s->d_u, s->d_w, nullptr, s->d_vel, 0, s->n,
+                                 s->d_partials, s->red_blocks, s->d_red),
+                   "reduce"));
+    HIPCHK(hipMemcpyAsync(red, s->d_red, RED_QUANT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LJMD_OK;
+}
+
 }  // namespace
 
 // ================================================================ C ABI
 
 extern "C" {
 
-const char *ljmd_last_error(void) { return g_err.c_str(); }
+const char *ljmd_last_error(void) { return ljmd::g_last_error.c_str(); }
 
-const char *ljmd_version(void) { return "ljmd 0.1 (gfx950)"; }
+const char *ljmd_version(void) { return "ljmd 0.2 (gfx950)"; }
 
 int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, const double *vel,
                        const int32_t *type, const double *mass, ljmd_system **out) {
@@ -843,12 +681,13 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
             s->lds_limit = (size_t)v;
     }
     s->stream = (hipStream_t)cfg->stream;
+    s->mem.alloc = cfg->alloc;
+    s->mem.free = cfg->free;
+    s->mem.ctx = cfg->alloc_ctx;
+    s->mem.stream = s->stream;
     s->n = (int)n;
     s->npad = (int)((n + 63) & ~63LL);
-    for (int a = 0; a < 3; ++a) {
-        s->L[a] = cfg->box[a];
-        s->invL[a] = 1.0 / cfg->box[a];
-    }
+    for (int a = 0; a < 3; ++a) s->L[a] = cfg->box[a];
     s->ntypes = cfg->ntypes;
     const int nt2 = s->ntypes * s->ntypes;
     s->eps.assign(nt2, 0.0);
@@ -864,8 +703,11 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
 
     const size_t N = (size_t)n;
     int rc = LJMD_OK;
+    rc = rc ? rc : dalloc_t(s, &s->d_rep, 1);
     rc = rc ? rc : dalloc_t(s, &s->d_pair, nt2);
     rc = rc ? rc : dalloc_t(s, &s->d_rl2, nt2);
+    rc = rc ? rc : dalloc_t(s, &s->d_req, 2);
+    rc = rc ? rc : dalloc_t(s, &s->d_one, 1);
     rc = rc ? rc : dalloc_t(s, &s->d_pos[0], N);
     rc = rc ? rc : dalloc_t(s, &s->d_pos[1], N);
     rc = rc ? rc : dalloc_t(s, &s->d_pos_scr, N);
@@ -900,13 +742,16 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
         ljmd_system_destroy(s);
         return code;
     };
+    static const int one = 1;
     if (hipMemcpyAsync(st_pos, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(st_vel, vel, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(st_type, type, N * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_one, &one, sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemsetAsync(s->d_req, 0, 2 * sizeof(int), s->stream) != hipSuccess ||
         (mass && hipMemcpyAsync(st_mass, mass, N * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess))
         return fail(set_err(LJMD_E_DEVICE, "host-to-device copy failed"));
     if (launch_upload(s->stream, st_pos, st_vel, st_type, mass ? st_mass : nullptr, s->d_pos[0],
-                      s->d_vel, s->d_img, s->n, s->L, 1, 1, nullptr) != hipSuccess ||
+                      s->d_vel, s->d_img, s->n, s->L, 1, 1, nullptr, 0) != hipSuccess ||
         launch_fill_status(s->stream, s->d_st) != hipSuccess)
         return fail(set_err(LJMD_E_DEVICE, "upload kernel failed"));
     if (hipStreamSynchronize(s->stream) != hipSuccess)
@@ -922,7 +767,7 @@ void ljmd_system_destroy(ljmd_system *s) {
     drop_graphs(s);
     for (hipEvent_t e : s->ev) (void)hipEventDestroy(e);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
-    while (!s->allocs.empty()) dfree(s, s->allocs.back().first);
+    s->mem.release_all();
     delete s;
 }
 
@@ -981,29 +826,10 @@ int ljmd_step(ljmd_system *s, int64_t nsteps) {
     return LJMD_OK;
 }
 
-static int fetch_vec(ljmd_system *s, const double4 *src, double *out) {
-    CHK(launch_chk(launch_unsort_vec(s->stream, src, s->d_img, s->n, s->d_stage), "unsort"));
-    HIPCHK(hipMemcpyAsync(out, s->d_stage, 3 * (size_t)s->n * sizeof(double), hipMemcpyDeviceToHost,
-                          s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    return LJMD_OK;
-}
-
 int ljmd_get_forces(ljmd_system *s, double *out) {
     if (!s || !out) return set_err(LJMD_E_INVAL, "null argument");
     CHK(ensure_ready(s));
     return fetch_vec(s, s->d_force, out);
-}
-
-static int eval_thermo(ljmd_system *s, double red[RED_QUANT]) {
-    CHK(ensure_ready(s));
-    CHK(enqueue_eval(s, true));
-    CHK(launch_chk(launch_reduce(s->stream, s->d_u, s->d_w, nullptr, s->d_vel, s->n, s->d_partials,
-                                 s->red_blocks, s->d_red),
-                   "reduce"));
-    HIPCHK(hipMemcpyAsync(red, s->d_red, RED_QUANT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(hipStreamSynchronize(s->stream));
-    return LJMD_OK;
 }
 
 int ljmd_get_energy(ljmd_system *s, double *potential, double *kinetic) {
@@ -1029,12 +855,12 @@ int ljmd_get_per_particle(ljmd_system *s, double *u, double *w) {
     CHK(enqueue_eval(s, true));
     const size_t N = (size_t)s->n;
     if (u) {
-        CHK(launch_chk(launch_unsort_scalar(s->stream, s->d_u, 1, s->d_img, s->n, s->d_stage), "unsort"));
+        CHK(launch_chk(launch_unsort_scalar(s->stream, s->d_u, 1, s->d_img, 0, s->n, s->d_stage), "unsort"));
         HIPCHK(hipMemcpyAsync(u, s->d_stage, N * sizeof(double), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
     if (w) {
-        CHK(launch_chk(launch_unsort_scalar(s->stream, s->d_w, 6, s->d_img, s->n, s->d_stage), "unsort"));
+        CHK(launch_chk(launch_unsort_scalar(s->stream, s->d_w, 6, s->d_img, 0, s->n, s->d_stage), "unsort"));
         HIPCHK(hipMemcpyAsync(w, s->d_stage, 6 * N * sizeof(double), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
@@ -1046,7 +872,7 @@ int ljmd_get_state(ljmd_system *s, double *pos, double *vel, int32_t *img, int64
     if (pos) CHK(fetch_vec(s, s->d_pos[s->cur], pos));
     if (vel) CHK(fetch_vec(s, s->d_vel, vel));
     if (img) {
-        CHK(launch_chk(launch_unsort_img(s->stream, s->d_img, s->n, (int *)s->d_stage), "unsort"));
+        CHK(launch_chk(launch_unsort_img(s->stream, s->d_img, 0, s->n, (int *)s->d_stage), "unsort"));
         HIPCHK(hipMemcpyAsync(img, s->d_stage, 3 * (size_t)s->n * sizeof(int), hipMemcpyDeviceToHost,
                               s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
@@ -1072,7 +898,7 @@ int ljmd_set_state(ljmd_system *s, const double *pos, const double *vel, const i
     if (img) HIPCHK(hipMemcpyAsync(st_img, img, 3 * N * sizeof(int), hipMemcpyHostToDevice, s->stream));
     s->cur = 0;
     CHK(launch_chk(launch_upload(s->stream, st_pos, st_vel, st_type, s->h_mass.empty() ? nullptr : st_mass,
-                                 s->d_pos[0], s->d_vel, s->d_img, s->n, s->L, 1, 1, img ? st_img : nullptr),
+                                 s->d_pos[0], s->d_vel, s->d_img, s->n, s->L, 1, 1, img ? st_img : nullptr, 0),
                    "upload"));
     HIPCHK(hipStreamSynchronize(s->stream));
     if (step) s->steps = *step;
@@ -1088,7 +914,7 @@ int ljmd_get_neighbor_pairs(ljmd_system *s, int64_t *count, int32_t *pairs, doub
     // global index of every entry, row q at q * cap, decoded on the device
     int *d_out = nullptr;
     CHK(dalloc_t(s, &d_out, N * (size_t)s->cap));
-    RebuildArgs ra = rebuild_args(s, &s->d_st->one, s->cur);
+    RebuildArgs ra = rebuild_args(s, s->d_one, s->cur);
     int rc = launch_chk(launch_decode_list(s->stream, ra, d_out), "decode list");
     std::vector<int> cnt(N), ent(N * (size_t)s->cap);
     std::vector<int4> img(N);
@@ -1132,9 +958,9 @@ int ljmd_get_stats(ljmd_system *s, ljmd_stats *out) {
     out->overflow_retries = s->overflow_retries;
     out->threads_per_particle = s->tpp;
     out->block_size = s->block;
-    for (int a = 0; a < 3; ++a) out->ncell[a] = s->nc[a];
+    for (int a = 0; a < 3; ++a) out->ncell[a] = s->rep.nc[a];
     out->graph_steps = s->graph_steps;
-    out->device_bytes = s->bytes;
+    out->device_bytes = s->mem.bytes;
     out->list_entries = (int64_t)st.entries;
     return LJMD_OK;
 }

@@ -53,6 +53,22 @@ class LjmdStats(C.Structure):
                 ("device_bytes", C.c_int64), ("list_entries", C.c_int64)]
 
 
+class LjmdBatchConfig(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("precision", C.c_int32),
+                ("dt", C.c_double), ("skin", C.c_double), ("block_steps", C.c_int32),
+                ("threads_per_particle", C.c_int32), ("block_size", C.c_int32),
+                ("nlist_capacity", C.c_int32), ("stream", C.c_void_p), ("alloc", ALLOC_FN),
+                ("free", FREE_FN), ("alloc_ctx", C.c_void_p)]
+
+
+class LjmdReplicaSpec(C.Structure):
+    _fields_ = [("box", C.c_double * 3), ("n", C.c_int64), ("pos", C.POINTER(C.c_double)),
+                ("vel", C.POINTER(C.c_double)), ("type", C.POINTER(C.c_int32)),
+                ("ntypes", C.c_int32), ("eps", C.POINTER(C.c_double)),
+                ("sigma", C.POINTER(C.c_double)), ("r_cut", C.POINTER(C.c_double)),
+                ("nsteps", C.c_int64)]
+
+
 class LjmdError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"LJMD_E_{_ERRNAMES.get(code, code)} ({code}): {msg}")
@@ -66,6 +82,9 @@ EXPORTED = [
     "ljmd_get_forces", "ljmd_get_energy", "ljmd_get_virial", "ljmd_get_per_particle",
     "ljmd_get_state", "ljmd_set_state", "ljmd_get_neighbor_pairs", "ljmd_get_stats",
     "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_last_error", "ljmd_version",
+    "ljmd_batch_create", "ljmd_batch_destroy", "ljmd_batch_footprint", "ljmd_batch_admit",
+    "ljmd_batch_run_block", "ljmd_batch_poll", "ljmd_batch_read", "ljmd_batch_slot_steps",
+    "ljmd_batch_release",
 ]
 
 
@@ -95,6 +114,15 @@ def load(path: str = LIB_PATH):
         "ljmd_kernel_time": ([vp, lp, dp], C.c_int),
         "ljmd_last_error": ([], C.c_char_p),
         "ljmd_version": ([], C.c_char_p),
+        "ljmd_batch_create": ([C.POINTER(LjmdBatchConfig), C.POINTER(vp)], C.c_int),
+        "ljmd_batch_destroy": ([vp], None),
+        "ljmd_batch_footprint": ([vp, C.POINTER(LjmdReplicaSpec), lp], C.c_int),
+        "ljmd_batch_admit": ([vp, C.POINTER(LjmdReplicaSpec), ip], C.c_int),
+        "ljmd_batch_run_block": ([vp], C.c_int),
+        "ljmd_batch_poll": ([vp, ip, ip], C.c_int),
+        "ljmd_batch_read": ([vp, C.c_int32, dp, dp, dp, dp, dp], C.c_int),
+        "ljmd_batch_slot_steps": ([vp, C.c_int32, lp], C.c_int),
+        "ljmd_batch_release": ([vp, C.c_int32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -282,6 +310,140 @@ class System:
         ms = C.c_double(0.0)
         _check(self._lib.ljmd_kernel_time(self._h, C.byref(n), C.byref(ms)))
         return int(n.value), float(ms.value)
+
+
+def pair_tables(ntypes, pairs):
+    """(eps, sigma, r_cut) as symmetric ntypes x ntypes float64 tables from a list of
+    (a, b, epsilon, sigma, r_cut); unlisted pairs get r_cut = 0 (no interaction)."""
+    eps = np.zeros((ntypes, ntypes))
+    sig = np.ones((ntypes, ntypes))
+    rc = np.zeros((ntypes, ntypes))
+    for (a, b, e, sg, r) in pairs:
+        for (i, j) in ((a, b), (b, a)):
+            eps[i, j], sig[i, j], rc[i, j] = e, sg, r
+    return eps, sig, rc
+
+
+class _ReplicaRequest:
+    """A replica spec in C layout; owns the arrays it points to."""
+
+    def __init__(self, spec, nsteps):
+        self.pos = np.ascontiguousarray(spec.pos, dtype=np.float64).reshape(-1, 3)
+        self.vel = np.ascontiguousarray(spec.vel, dtype=np.float64).reshape(-1, 3)
+        self.typ = np.ascontiguousarray(spec.type, dtype=np.int32).reshape(-1)
+        self.eps, self.sig, self.rc = (np.ascontiguousarray(t) for t in
+                                       pair_tables(int(spec.ntypes), spec.pairs))
+        c = LjmdReplicaSpec()
+        for a in range(3):
+            c.box[a] = float(np.asarray(spec.box, dtype=np.float64).reshape(3)[a])
+        c.n = self.pos.shape[0]
+        c.pos = _dp(self.pos)
+        c.vel = _dp(self.vel)
+        c.type = _ip(self.typ)
+        c.ntypes = int(spec.ntypes)
+        c.eps = _dp(self.eps)
+        c.sigma = _dp(self.sig)
+        c.r_cut = _dp(self.rc)
+        c.nsteps = int(nsteps)
+        self.c = c
+
+
+class Batch:
+    """Many independent LJ replicas on the GPU (ljmd_batch): admit, run blocks, poll, read,
+    release. Arrays in and out are numpy, tag order."""
+
+    def __init__(self, budget_bytes, max_slots, precision="mixed", dt=0.005, skin=0.4,
+                 block_steps=100, threads_per_particle=0, block_size=0, nlist_capacity=0,
+                 stream=None, torch_memory=True):
+        lib = load()
+        self._lib = lib
+        cfg = LjmdBatchConfig()
+        cfg.budget_bytes = int(budget_bytes)
+        cfg.max_slots = int(max_slots)
+        cfg.precision = {"fp64": LJMD_FP64, "mixed": LJMD_MIXED}[precision]
+        cfg.dt = float(dt)
+        cfg.skin = float(skin)
+        cfg.block_steps = int(block_steps)
+        cfg.threads_per_particle = int(threads_per_particle)
+        cfg.block_size = int(block_size)
+        cfg.nlist_capacity = int(nlist_capacity)
+        self._alloc = None
+        torch = _torch_cuda()
+        if torch is not None:
+            dev = torch.cuda.current_device()
+            if stream is None:
+                stream = torch.cuda.current_stream(dev).cuda_stream
+            if torch_memory:
+                self._alloc = _TorchAllocator(torch, dev)
+                cfg.alloc = self._alloc.alloc
+                cfg.free = self._alloc.free
+        cfg.stream = stream if stream else None
+        self._cfg = cfg
+        self.max_slots = int(max_slots)
+        self.block_steps = int(block_steps) if block_steps else 100
+        self._n = {}
+        h = C.c_void_p()
+        _check(lib.ljmd_batch_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.ljmd_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def footprint(self, spec, nsteps=1):
+        req = _ReplicaRequest(spec, nsteps)
+        out = C.c_int64(0)
+        _check(self._lib.ljmd_batch_footprint(self._h, C.byref(req.c), C.byref(out)))
+        return int(out.value)
+
+    def admit(self, spec, nsteps):
+        """Admit a replica for nsteps steps; returns its slot. Raises LjmdError (code
+        LJMD_E_CAPACITY when no slot or budget is free)."""
+        req = _ReplicaRequest(spec, nsteps)
+        slot = C.c_int32(-1)
+        _check(self._lib.ljmd_batch_admit(self._h, C.byref(req.c), C.byref(slot)))
+        self._n[int(slot.value)] = req.pos.shape[0]
+        return int(slot.value)
+
+    def run_block(self):
+        _check(self._lib.ljmd_batch_run_block(self._h))
+
+    def poll(self):
+        out = np.empty(self.max_slots, dtype=np.int32)
+        k = C.c_int32(0)
+        _check(self._lib.ljmd_batch_poll(self._h, _ip(out), C.byref(k)))
+        return [int(v) for v in out[:k.value]]
+
+    def slot_steps(self, slot):
+        out = C.c_int64(0)
+        _check(self._lib.ljmd_batch_slot_steps(self._h, int(slot), C.byref(out)))
+        return int(out.value)
+
+    def read(self, slot, energy=True):
+        n = self._n[int(slot)]
+        pos = np.empty((n, 3))
+        vel = np.empty((n, 3))
+        f = np.empty((n, 3))
+        e = np.zeros(2)
+        w = np.zeros(6)
+        _check(self._lib.ljmd_batch_read(self._h, int(slot), _dp(pos), _dp(vel), _dp(f),
+                                         _dp(e) if energy else None, _dp(w) if energy else None))
+        out = {"pos": pos, "vel": vel, "forces": f}
+        if energy:
+            out.update(potential=float(e[0]), kinetic=float(e[1]), virial=w)
+        return out
+
+    def release(self, slot):
+        _check(self._lib.ljmd_batch_release(self._h, int(slot)))
+        self._n.pop(int(slot), None)
 
 
 def version():

@@ -118,16 +118,20 @@ def test_no_device_reports_device_error(lib):
     assert e.value.code == ljmd.LJMD_E_DEVICE
 
 
-def test_struct_layout_matches_header(lib, tmp_path):
-    """The ctypes mirrors of ljmd_config and ljmd_stats have the C compiler's layout."""
+STRUCTS = [("ljmd_config", "LjmdConfig"), ("ljmd_stats", "LjmdStats"),
+           ("ljmd_batch_config", "LjmdBatchConfig"), ("ljmd_replica_spec", "LjmdReplicaSpec")]
+
+
+@pytest.mark.parametrize("cname,pyname", STRUCTS)
+def test_struct_layout_matches_header(lib, tmp_path, cname, pyname):
+    """The ctypes mirrors of the C structs have the C compiler's size and offsets."""
     import subprocess
 
-    fields_cfg = [f for f, _ in ljmd.LjmdConfig._fields_]
-    fields_st = [f for f, _ in ljmd.LjmdStats._fields_]
+    cls = getattr(ljmd, pyname)
+    fields = [f for f, _ in cls._fields_]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ljmd.h"', "int main(void){",
-             'printf("%zu %zu\\n", sizeof(ljmd_config), sizeof(ljmd_stats));']
-    lines += [f'printf("%zu\\n", offsetof(ljmd_config, {f}));' for f in fields_cfg]
-    lines += [f'printf("%zu\\n", offsetof(ljmd_stats, {f}));' for f in fields_st]
+             f'printf("%zu\\n", sizeof({cname}));']
+    lines += [f'printf("%zu\\n", offsetof({cname}, {f}));' for f in fields]
     lines += ["return 0;}"]
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines))
@@ -136,9 +140,49 @@ def test_struct_layout_matches_header(lib, tmp_path):
                    check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
     vals = [int(v) for v in out]
-    assert vals[0] == C.sizeof(ljmd.LjmdConfig) and vals[1] == C.sizeof(ljmd.LjmdStats)
-    offs = vals[2:]
-    for k, f in enumerate(fields_cfg):
-        assert getattr(ljmd.LjmdConfig, f).offset == offs[k], f
-    for k, f in enumerate(fields_st):
-        assert getattr(ljmd.LjmdStats, f).offset == offs[len(fields_cfg) + k], f
+    assert vals[0] == C.sizeof(cls)
+    for k, f in enumerate(fields):
+        assert getattr(cls, f).offset == vals[1 + k], f
+
+
+def _bcfg(**kw):
+    cfg = ljmd.LjmdBatchConfig()
+    cfg.budget_bytes = kw.get("budget", 64 << 20)
+    cfg.max_slots = kw.get("slots", 4)
+    cfg.precision = kw.get("precision", 1)
+    cfg.dt = kw.get("dt", 0.005)
+    cfg.skin = kw.get("skin", 0.4)
+    cfg.block_steps = kw.get("steps", 0)
+    cfg.threads_per_particle = kw.get("tpp", 0)
+    cfg.block_size = kw.get("block", 0)
+    return cfg
+
+
+@pytest.mark.parametrize("kw", [
+    dict(slots=0), dict(precision=7), dict(dt=0.0), dict(skin=-1.0), dict(steps=3),
+    dict(steps=-2), dict(tpp=5), dict(block=96), dict(budget=1000),
+])
+def test_invalid_batch_config_rejected_before_device(lib, kw):
+    h = C.c_void_p()
+    rc = lib.ljmd_batch_create(C.byref(_bcfg(**kw)), C.byref(h))
+    assert rc == ljmd.LJMD_E_INVAL
+    assert not h.value
+    assert lib.ljmd_last_error().decode()
+
+
+def test_batch_null_handles(lib):
+    assert lib.ljmd_batch_run_block(None) == ljmd.LJMD_E_INVAL
+    assert lib.ljmd_batch_release(None, 0) == ljmd.LJMD_E_INVAL
+    k = C.c_int32(0)
+    assert lib.ljmd_batch_poll(None, None, C.byref(k)) == ljmd.LJMD_E_INVAL
+    lib.ljmd_batch_destroy(None)
+
+
+def test_batch_no_device(lib):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible; this checks the no-device path")
+    h = C.c_void_p()
+    assert lib.ljmd_batch_create(C.byref(_bcfg()), C.byref(h)) == ljmd.LJMD_E_DEVICE
+    assert not h.value
