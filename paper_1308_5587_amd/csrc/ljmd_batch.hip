@@ -437,7 +437,7 @@ void set_tpp(ljmd_batch *b, int t) {
 int tune(ljmd_batch *b, int s) {
     const int want_tpp = b->cfg.threads_per_particle, want_block = b->cfg.block_size;
     const int tpps[] = {1, 2, 4, 8};
-    const int blocks[] = {128, 256, 512};
+    const int blocks[] = {128, 192, 256, 320, 384, 448, 512};
     double best = 1e30;
     int bt = want_tpp ? want_tpp : 4, bb = want_block ? want_block : 256;
     if (want_tpp && want_block) {

@@ -96,21 +96,19 @@ constexpr int RED_QUANT = 8;         // U, W[6], K
 constexpr int SORT_LDS = 1024;       // in-cell sort capacity per workgroup
 constexpr int SCAN_TILE = 8192;      // counts per LDS tile of the scan (multiple of 1024)
 
-// Dynamic LDS of the force kernel: tile x, y, z (FP64), then types and the pair table
-// when there are several types.
+// Dynamic LDS of the force kernel: the tile as double4 records (x, y, z, type), then the
+// pair table when there are several types.
 __host__ __device__ inline size_t force_lds_bytes(int tile_cap, int ntypes) {
-    size_t b = (size_t)tile_cap * 3 * sizeof(double);
-    if (ntypes > 1)
-        b += (size_t)((tile_cap + 1) / 2) * sizeof(double) +
-             (size_t)ntypes * ntypes * sizeof(PairCoef);
+    size_t b = (size_t)tile_cap * 4 * sizeof(double);
+    if (ntypes > 1) b += (size_t)ntypes * ntypes * sizeof(PairCoef);
     return b;
 }
 
-// Dynamic LDS of the list build: tile x, y, z (FP64), then types and the list radii.
+// Dynamic LDS of the list build: the tile as double4 records, then the list radii squared
+// when there are several types.
 __host__ __device__ inline size_t nlist_lds_bytes(int tile_cap, int ntypes) {
-    size_t b = (size_t)tile_cap * 3 * sizeof(double);
-    if (ntypes > 1)
-        b += (size_t)((tile_cap + 1) / 2) * sizeof(double) + (size_t)ntypes * ntypes * sizeof(double);
+    size_t b = (size_t)tile_cap * 4 * sizeof(double);
+    if (ntypes > 1) b += (size_t)ntypes * ntypes * sizeof(double);
     return b;
 }
 

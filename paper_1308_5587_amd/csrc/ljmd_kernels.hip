@@ -80,10 +80,12 @@ __device__ __forceinline__ void wrap_coord(double &x, int &im, double L) {
 // List slot of entry k of particle q with 2^ls lanes per particle: lanes own chunks of 8
 // consecutive 16-bit entries, lane l holds chunks l, l + 2^ls, ...; for chunk index c the
 // lanes of consecutive particles are adjacent, so a wavefront reads 64 x 16 contiguous bytes.
+// In closed form: slot = (k >> (3 + ls)) * (npad << (3 + ls)) + (q << (3 + ls))
+//                        + (k & (2^(3 + ls) - 1)).
 __device__ __forceinline__ size_t nl_slot(int q, int k, int npad, int ls) {
-    const size_t c = (size_t)(k >> (3 + ls));
-    const size_t l = (size_t)((k >> 3) & ((1 << ls) - 1));
-    return ((((c * (size_t)npad + (size_t)q) << ls) + l) << 3) | (size_t)(k & 7);
+    const int sh = 3 + ls;
+    return (size_t)((unsigned)k >> sh) * ((size_t)npad << sh) + ((size_t)q << sh) +
+           (size_t)(k & ((1 << sh) - 1));
 }
 
 // ---------------------------------------------------------------- brick tiles
@@ -143,23 +145,27 @@ __device__ __forceinline__ int tile_global(const TileSmem &t, int k) {
     return t.start[h] + (k - t.off[h]);
 }
 
-// Copy the tile's positions (and types) into LDS, structure of arrays: blockDim / 64
+// Copy the tile's atoms (x, y, z, type) into LDS as double4 records: blockDim / 64
 // consecutive threads copy one halo cell's atoms (consecutive in memory).
-template <bool MULTI>
-__device__ __forceinline__ void tile_stage(const TileSmem &t, const double4 *pos, double *sx,
-                                           double *sy, double *sz, int *sty) {
+__device__ __forceinline__ void tile_stage(const TileSmem &t, const double4 *pos, double4 *st) {
     const int per = blockDim.x >= 64 ? (int)blockDim.x / 64 : 1;
     const int sub = threadIdx.x % per;
     for (int h = threadIdx.x / per; h < t.nhalo; h += (int)blockDim.x / per) {
         const int o = t.off[h];
         const int m = t.off[h + 1] - o;
         const double4 *src = pos + t.start[h];
-        for (int k = sub; k < m; k += per) {
-            const double4 p = src[k];
-            sx[o + k] = p.x;
-            sy[o + k] = p.y;
-            sz[o + k] = p.z;
-            if (MULTI) sty[o + k] = (int)p.w;
+        // four loads in flight per thread before the LDS stores (an index past the cell
+        // reads its first atom, k0 < m, and is not stored)
+        for (int k0 = sub; k0 < m; k0 += 4 * per) {
+            const int k1 = k0 + per, k2 = k0 + 2 * per, k3 = k0 + 3 * per;
+            const double4 p0 = src[k0];
+            const double4 p1 = src[k1 < m ? k1 : k0];
+            const double4 p2 = src[k2 < m ? k2 : k0];
+            const double4 p3 = src[k3 < m ? k3 : k0];
+            st[o + k0] = p0;
+            if (k1 < m) st[o + k1] = p1;
+            if (k2 < m) st[o + k2] = p2;
+            if (k3 < m) st[o + k3] = p3;
         }
     }
     __syncthreads();
@@ -364,10 +370,7 @@ __device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double d
 // (plain LDS reads) or, for a tile larger than the LDS allocation, from global memory.
 template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI, bool STAGED, bool NO_MI>
 __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem &t,
-                                             const double *__restrict__ sx,
-                                             const double *__restrict__ sy,
-                                             const double *__restrict__ sz,
-                                             const int *__restrict__ sty,
+                                             const double4 *__restrict__ st,
                                              const PairCoef *s_pair, const PairCoef &single,
                                              const RepParams &P, int rep, bool last, int first,
                                              int natoms) {
@@ -426,10 +429,11 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                     const int idx = pv[v] ? e[u] : 0;
                     pt[v] = 0;
                     if (STAGED) {
-                        px[v] = sx[idx];
-                        py[v] = sy[idx];
-                        pz[v] = sz[idx];
-                        if (MULTI) pt[v] = sty[idx];
+                        const double4 pj = st[idx];
+                        px[v] = pj.x;
+                        py[v] = pj.y;
+                        pz[v] = pj.z;
+                        if (MULTI) pt[v] = (int)pj.w;
                     } else {
                         const double4 pj = a.pos_in[tile_global(t, idx)];
                         px[v] = pj.x;
@@ -542,7 +546,7 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
 // allocation, the positions are read from global memory through the tile offsets instead.
 template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI>
 __global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
-    extern __shared__ double dyn_smem[];
+    extern __shared__ double4 dyn_tile[];
     __shared__ TileSmem t;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BrickInfo bi = a.bricks[b];
@@ -566,29 +570,26 @@ __global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
             a.pos_out[first + k] = a.pos_in[first + k];
         return;
     }
-    double *sx = dyn_smem;
-    double *sy = sx + a.tile_cap;
-    double *sz = sy + a.tile_cap;
-    int *sty = reinterpret_cast<int *>(sz + a.tile_cap);
-    PairCoef *s_pair = reinterpret_cast<PairCoef *>(sz + a.tile_cap + (a.tile_cap + 1) / 2);
+    double4 *st = dyn_tile;
+    PairCoef *s_pair = reinterpret_cast<PairCoef *>(st + a.tile_cap);
     if (MULTI)
         for (int k = threadIdx.x; k < P.ntypes * P.ntypes; k += blockDim.x)
             s_pair[k] = a.pair[P.pair_off + k];
     const PairCoef single = a.pair[P.pair_off];
     tile_load(a.tile_tab + (size_t)b * TILE_TAB, t);
     const bool staged = t.total <= a.tile_cap;
-    if (staged) tile_stage<MULTI>(t, a.pos_in, sx, sy, sz, sty);
+    if (staged) tile_stage(t, a.pos_in, st);
     const bool last = MODE == MODE_FUSED && r_in == 1;
     const int mif = (bi.dims >> MI_FREE_SHIFT) & 7;
     if (staged && mif == 7)
         force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, true>(
-            a, t, sx, sy, sz, sty, s_pair, single, P, rep, last, first, natoms);
+            a, t, st, s_pair, single, P, rep, last, first, natoms);
     else if (staged)
         force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, false>(
-            a, t, sx, sy, sz, sty, s_pair, single, P, rep, last, first, natoms);
+            a, t, st, s_pair, single, P, rep, last, first, natoms);
     else
         force_passes<PREC, TPP, MODE, ENERGY, MULTI, false, false>(
-            a, t, sx, sy, sz, sty, s_pair, single, P, rep, last, first, natoms);
+            a, t, st, s_pair, single, P, rep, last, first, natoms);
 }
 
 template <int PREC, int TPP, int MODE, bool ENERGY>
@@ -796,17 +797,79 @@ __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
 
 // ---------------------------------------------------------------- rebuild: Verlet list
 
+// Candidates of one stencil cell for the particles of a wavefront's groups: each group of
+// Ln lanes takes Ln atoms of the cell at a time and appends the hits of its particle in
+// lane order. MIK selects the minimum-image form, fixed per cell: 0 none (the halo cell is
+// in the primary image), 1 a constant shift of the halo cell's periodic image, 2 the branch
+// form (fewer than 3 cells on some axis).
+template <bool MULTI, bool STAGED, int MIK>
+__device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
+                                                const double4 *__restrict__ st,
+                                                const double *s_rl2, const RepParams &P, int o,
+                                                int m, int jst, double shx, double shy,
+                                                double shz, const double4 &xi, int ti, int q,
+                                                bool active, int Ln, int lane,
+                                                unsigned long long gmask, int &count) {
+    // list slots (nl_slot in closed form with the particle's part precomputed)
+    const int sh = 3 + a.lshift;
+    const size_t rstride = (size_t)a.npad << sh;
+    const size_t qbase = (size_t)q << sh;
+    for (int t0 = 0; t0 < m; t0 += Ln) {
+        const int tt = t0 + lane;
+        const bool valid = active && tt < m;
+        const int tv = valid ? tt : 0;
+        double xjx, xjy, xjz;
+        int tj = 0;
+        if (STAGED) {
+            const double4 pj = st[o + tv];
+            xjx = pj.x;
+            xjy = pj.y;
+            xjz = pj.z;
+            if (MULTI) tj = (int)pj.w;
+        } else {
+            const double4 pj = a.pos_scr[jst + tv];
+            xjx = pj.x;
+            xjy = pj.y;
+            xjz = pj.z;
+            tj = (int)pj.w;
+        }
+        double dx = xjx - xi.x, dy = xjy - xi.y, dz = xjz - xi.z;
+        if (MIK == 2) {
+            dx = mi_branch(dx, P.L[0]);
+            dy = mi_branch(dy, P.L[1]);
+            dz = mi_branch(dz, P.L[2]);
+        } else if (MIK == 1) {
+            dx = dx + shx;  // adding 0.0 on an unshifted axis is exact
+            dy = dy + shy;
+            dz = dz + shz;
+        }
+        const double r2 = r2_canon(dx, dy, dz);
+        const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.single_rl2;
+        const bool hit = valid && (jst + tt) != q && r2 < rl2;
+        const unsigned long long bal = __ballot(hit) & gmask;
+        if (hit) {
+            // hits of lower lanes of the group: mbcnt counts the set bits of bal below
+            // this lane
+            const int k = count + (int)__builtin_amdgcn_mbcnt_hi(
+                                      (unsigned)(bal >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            if (k < a.cap) {
+                const size_t slot = (size_t)((unsigned)k >> sh) * rstride + qbase +
+                                    (size_t)(k & ((1 << sh) - 1));
+                a.nlist[slot] = (uint16_t)(o + tt);
+            }
+        }
+        count += __popcll(bal);
+    }
+}
+
 // The cells of one brick, one wavefront per cell; STAGED selects candidate positions from
-// the LDS tile (plain LDS reads) or, for a tile larger than the LDS allocation, from global
-// memory.
+// the LDS tile or, for a tile larger than the LDS allocation, from global memory.
 template <bool MULTI, bool STAGED>
 __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem &t,
-                                            const BrickInfo &bi, const double *__restrict__ sx,
-                                            const double *__restrict__ sy,
-                                            const double *__restrict__ sz,
-                                            const int *__restrict__ sty, const double *s_rl2,
-                                            const RepParams &P, int &my_max,
-                                            unsigned long long &my_entries) {
+                                            const BrickInfo &bi, const double4 *__restrict__ st,
+                                            const double *s_rl2, const RepParams &P,
+                                            int &my_max, unsigned long long &my_entries) {
     const int hy = (bi.dims >> 4) & 15, hz = (bi.dims >> 8) & 15;
     const int fpk = a.cell_xyz[bi.first_cell];
     const int wl = threadIdx.x & 63;
@@ -844,51 +907,18 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                 const int m = t.off[h + 1] - o;
                 const int jst = t.start[h];
                 const int code = t.shift[h];
-                const bool shifted = !P.canonical && code != 21;  // 21: no shift on any axis
-                const double shx = (double)((code & 3) - 1) * P.L[0];
-                const double shy = (double)(((code >> 2) & 3) - 1) * P.L[1];
-                const double shz = (double)(((code >> 4) & 3) - 1) * P.L[2];
-                for (int t0 = 0; t0 < m; t0 += Ln) {
-                    const int tt = t0 + lane;
-                    const bool valid = active && tt < m;
-                    const int tv = valid ? tt : 0;
-                    double xjx, xjy, xjz;
-                    int tj = 0;
-                    if (STAGED) {
-                        xjx = sx[o + tv];
-                        xjy = sy[o + tv];
-                        xjz = sz[o + tv];
-                        if (MULTI) tj = sty[o + tv];
-                    } else {
-                        const double4 pj = a.pos_scr[jst + tv];
-                        xjx = pj.x;
-                        xjy = pj.y;
-                        xjz = pj.z;
-                        tj = (int)pj.w;
-                    }
-                    double dx = xjx - xi.x, dy = xjy - xi.y, dz = xjz - xi.z;
-                    if (P.canonical) {
-                        dx = mi_branch(dx, P.L[0]);
-                        dy = mi_branch(dy, P.L[1]);
-                        dz = mi_branch(dz, P.L[2]);
-                    } else if (shifted) {
-                        dx = dx + shx;  // adding 0.0 is exact
-                        dy = dy + shy;
-                        dz = dz + shz;
-                    }
-                    const double r2 = r2_canon(dx, dy, dz);
-                    const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.single_rl2;
-                    const bool hit = valid && (jst + tt) != q && r2 < rl2;
-                    const unsigned long long bal = __ballot(hit) & gmask;
-                    if (hit) {
-                        // hits of lower lanes of the group: mbcnt counts the set bits of
-                        // bal below this lane
-                        const int k = count + (int)__builtin_amdgcn_mbcnt_hi(
-                                                  (unsigned)(bal >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                        if (k < a.cap) a.nlist[nl_slot(q, k, a.npad, a.lshift)] = (uint16_t)(o + tt);
-                    }
-                    count += __popcll(bal);
+                if (P.canonical) {
+                    nlist_scan_cell<MULTI, STAGED, 2>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0,
+                                                      xi, ti, q, active, Ln, lane, gmask, count);
+                } else if (code != 21) {  // 21: no shift on any axis
+                    const double shx = (double)((code & 3) - 1) * P.L[0];
+                    const double shy = (double)(((code >> 2) & 3) - 1) * P.L[1];
+                    const double shz = (double)(((code >> 4) & 3) - 1) * P.L[2];
+                    nlist_scan_cell<MULTI, STAGED, 1>(a, st, s_rl2, P, o, m, jst, shx, shy, shz,
+                                                      xi, ti, q, active, Ln, lane, gmask, count);
+                } else {
+                    nlist_scan_cell<MULTI, STAGED, 0>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0,
+                                                      xi, ti, q, active, Ln, lane, gmask, count);
                 }
             }
             if (active && lane == 0) {
@@ -925,13 +955,10 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
     const BrickInfo bi = a.bricks[b];
     if (!rebuilds(a, bi.rep)) return;
     const RepParams &P = a.reps[bi.rep];
-    extern __shared__ double dyn_smem[];
+    extern __shared__ double4 dyn_tile[];
     __shared__ TileSmem t;
-    double *sx = dyn_smem;
-    double *sy = sx + a.tile_cap;
-    double *sz = sy + a.tile_cap;
-    int *sty = reinterpret_cast<int *>(sz + a.tile_cap);
-    double *s_rl2 = sz + a.tile_cap + (a.tile_cap + 1) / 2;
+    double4 *st = dyn_tile;
+    double *s_rl2 = reinterpret_cast<double *>(st + a.tile_cap);
     if (MULTI)
         for (int k = threadIdx.x; k < P.ntypes * P.ntypes; k += blockDim.x)
             s_rl2[k] = a.rl2_table[P.pair_off + k];
@@ -961,15 +988,15 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
         }
     }
     const bool staged = t.total <= a.tile_cap;
-    if (staged) tile_stage<MULTI>(t, a.pos_scr, sx, sy, sz, sty);
+    if (staged) tile_stage(t, a.pos_scr, st);
 
     const int wl = threadIdx.x & 63;
     int my_max = 0;
     unsigned long long my_entries = 0ull;
     if (staged)
-        nlist_cells<MULTI, true>(a, t, bi, sx, sy, sz, sty, s_rl2, P, my_max, my_entries);
+        nlist_cells<MULTI, true>(a, t, bi, st, s_rl2, P, my_max, my_entries);
     else
-        nlist_cells<MULTI, false>(a, t, bi, sx, sy, sz, sty, s_rl2, P, my_max, my_entries);
+        nlist_cells<MULTI, false>(a, t, bi, st, s_rl2, P, my_max, my_entries);
 
     // wavefront reductions of the build statistics, one atomic each per wavefront
     for (int o = 32; o > 0; o >>= 1) {

@@ -446,7 +446,7 @@ int tune(ljmd_system *s) {
         }
     }
     const int tpps[] = {1, 2, 4, 8};
-    const int blocks[] = {128, 256, 512};
+    const int blocks[] = {128, 192, 256, 320, 384, 448, 512};
     double best = 1e30;
     int bt = 4, bb = 128;
     for (int t : tpps) {

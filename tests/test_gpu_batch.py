@@ -199,3 +199,20 @@ def test_slots_budget_and_errors(ljmd_mod):
         small.admit(spec, 5)
     assert e.value.code == E.LJMD_E_CAPACITY
     small.close()
+
+
+def test_served_stream_results_equal_alone(ljmd_mod):
+    print_case("served request stream: each result equals its alone run")
+    from paper_1308_5587_amd import serve
+
+    arrivals = gen.make_arrivals(6, rate=40.0, seed=7, n_lo=512, n_hi=3000, steps_lo=20,
+                                 steps_hi=90)
+    mk = lambda p: gen.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed)  # noqa: E731
+    reqs = serve.requests_from_arrivals(arrivals, mk)
+    b = ljmd_mod.Batch(128 << 20, 3, precision="mixed", block_steps=10,
+                       threads_per_particle=TPP, block_size=BLOCK)
+    rep = serve.serve(b, reqs, keep_results=True)
+    b.close()
+    assert len(rep.requests) == 6 and rep.peak_resident >= 2
+    for r in rep.requests:
+        _same(r.result, _alone(ljmd_mod, r.spec, r.nsteps, "mixed"))
