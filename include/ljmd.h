@@ -245,6 +245,24 @@ int ljmd_batch_release(ljmd_batch *b, int32_t slot);
 
 void ljmd_batch_destroy(ljmd_batch *b);
 
+/* Counters of a batch. */
+typedef struct ljmd_batch_stats {
+    int32_t resident;          /* occupied slots (running or finished, not yet released) */
+    int32_t running;           /* resident replicas with steps left */
+    int64_t blocks;            /* ljmd_batch_run_block calls that ran a block */
+    int64_t overflow_reruns;   /* replicas whose block ran again after a list overflow */
+    int64_t rebuilds;          /* list builds over all replicas (one per replica build) */
+    int32_t nlist_capacity;    /* list entries per particle (all replicas) */
+    int32_t threads_per_particle;
+    int32_t block_size;
+    int32_t tile_capacity;     /* atoms of a brick tile held in LDS */
+    int64_t device_bytes;      /* device memory held by the batch */
+    int64_t used_bytes;        /* footprints of the resident replicas */
+    int64_t budget_bytes;
+} ljmd_batch_stats;
+
+int ljmd_batch_get_stats(ljmd_batch *b, ljmd_batch_stats *out);
+
 /* Thread-local message for the last non-zero status returned on this thread. */
 const char *ljmd_last_error(void);
 

@@ -162,6 +162,7 @@ struct ljmd_batch {
     hipGraphExec_t graph = nullptr;
     GraphKey gkey{};
     int red_blocks = 1024;
+    int64_t blocks = 0, overflow_reruns = 0;
 };
 
 namespace {
@@ -934,6 +935,7 @@ int ljmd_batch_run_block(ljmd_batch *b) {
     CHK(ensure_graph(b));
     HIPCHK(hipGraphLaunch(b->graph, b->stream));
     CHK(read_status(b));
+    b->blocks += 1;
     std::vector<int> overflowed;
     for (int s : running) {
         Slot &sl = b->slots[s];
@@ -961,6 +963,7 @@ int ljmd_batch_run_block(ljmd_batch *b) {
             CHK(copy_range(b, b->slots[s], false));
             b->h_mask[s] = 1;
         }
+        b->overflow_reruns += (int64_t)overflowed.size();
         CHK(upload_mask(b, b->d_go, b->h_mask));
         CHK(upload_mask(b, b->d_only, b->h_mask));
         CHK(forced_rebuild(b, overflowed));
@@ -1064,6 +1067,29 @@ int ljmd_batch_read(ljmd_batch *b, int32_t s, double *pos, double *vel, double *
         if (virial)
             for (int c = 0; c < 6; ++c) virial[c] = red[1 + c];
     }
+    return LJMD_OK;
+}
+
+int ljmd_batch_get_stats(ljmd_batch *b, ljmd_batch_stats *out) {
+    if (!b || !out) return set_err(LJMD_E_INVAL, "null argument");
+    DevStatus st{};
+    HIPCHK(hipMemcpyAsync(&st, b->d_st, sizeof st, hipMemcpyDeviceToHost, b->stream));
+    CHK(sync(b));
+    std::memset(out, 0, sizeof *out);
+    for (const Slot &sl : b->slots) {
+        out->resident += sl.used ? 1 : 0;
+        out->running += (sl.used && !sl.done) ? 1 : 0;
+    }
+    out->blocks = b->blocks;
+    out->overflow_reruns = b->overflow_reruns;
+    out->rebuilds = (int64_t)st.builds;
+    out->nlist_capacity = b->cap;
+    out->threads_per_particle = b->tpp;
+    out->block_size = b->block;
+    out->tile_capacity = b->tile_cap;
+    out->device_bytes = b->mem.bytes;
+    out->used_bytes = b->used_bytes;
+    out->budget_bytes = b->cfg.budget_bytes;
     return LJMD_OK;
 }
 

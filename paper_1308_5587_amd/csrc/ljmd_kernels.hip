@@ -368,7 +368,9 @@ __device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double d
 
 // The particle passes of one brick; STAGED selects neighbour positions from the LDS tile
 // (plain LDS reads) or, for a tile larger than the LDS allocation, from global memory.
-template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI, bool STAGED, bool NO_MI>
+// MIF: bit a set when no pair of the brick can wrap on axis a (the minimum image is skipped
+// there; subtracting 0 x L would give the same bits).
+template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI, bool STAGED, int MIF>
 __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem &t,
                                              const double4 *__restrict__ st,
                                              const PairCoef *s_pair, const PairCoef &single,
@@ -444,9 +446,9 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                 }
 #pragma unroll
                 for (int v = 0; v < FORCE_BATCH; ++v) {
-                    const double dx = NO_MI ? px[v] - xi.x : mi_rint(px[v] - xi.x, L0, iL0);
-                    const double dy = NO_MI ? py[v] - xi.y : mi_rint(py[v] - xi.y, L1, iL1);
-                    const double dz = NO_MI ? pz[v] - xi.z : mi_rint(pz[v] - xi.z, L2, iL2);
+                    const double dx = (MIF & 1) ? px[v] - xi.x : mi_rint(px[v] - xi.x, L0, iL0);
+                    const double dy = (MIF & 2) ? py[v] - xi.y : mi_rint(py[v] - xi.y, L1, iL1);
+                    const double dz = (MIF & 4) ? pz[v] - xi.z : mi_rint(pz[v] - xi.z, L2, iL2);
                     const double r2 = r2_canon(dx, dy, dz);
                     const PairCoef &c = MULTI ? s_pair[ti * P.ntypes + pt[v]] : single;
                     if (pv[v] && r2 < c.rc2)
@@ -581,15 +583,29 @@ __global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
     if (staged) tile_stage(t, a.pos_in, st);
     const bool last = MODE == MODE_FUSED && r_in == 1;
     const int mif = (bi.dims >> MI_FREE_SHIFT) & 7;
-    if (staged && mif == 7)
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, true>(
+#define LJMD_PASSES(M) \
+    force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, M>(a, t, st, s_pair, single, P, rep, last, first, natoms)
+    if (!staged) {
+        force_passes<PREC, TPP, MODE, ENERGY, MULTI, false, 0>(
             a, t, st, s_pair, single, P, rep, last, first, natoms);
-    else if (staged)
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, false>(
-            a, t, st, s_pair, single, P, rep, last, first, natoms);
-    else
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, false, false>(
-            a, t, st, s_pair, single, P, rep, last, first, natoms);
+    } else if (MODE == MODE_FUSED) {
+        // the step kernel: a variant per set of wrap-free axes
+        switch (mif) {
+            case 7: LJMD_PASSES(7); break;
+            case 6: LJMD_PASSES(6); break;
+            case 5: LJMD_PASSES(5); break;
+            case 3: LJMD_PASSES(3); break;
+            case 4: LJMD_PASSES(4); break;
+            case 2: LJMD_PASSES(2); break;
+            case 1: LJMD_PASSES(1); break;
+            default: LJMD_PASSES(0); break;
+        }
+    } else if (mif == 7) {
+        LJMD_PASSES(7);
+    } else {
+        LJMD_PASSES(0);
+    }
+#undef LJMD_PASSES
 }
 
 template <int PREC, int TPP, int MODE, bool ENERGY>

@@ -69,6 +69,15 @@ class LjmdReplicaSpec(C.Structure):
                 ("nsteps", C.c_int64)]
 
 
+class LjmdBatchStats(C.Structure):
+    _fields_ = [("resident", C.c_int32), ("running", C.c_int32), ("blocks", C.c_int64),
+                ("overflow_reruns", C.c_int64), ("rebuilds", C.c_int64),
+                ("nlist_capacity", C.c_int32), ("threads_per_particle", C.c_int32),
+                ("block_size", C.c_int32), ("tile_capacity", C.c_int32),
+                ("device_bytes", C.c_int64), ("used_bytes", C.c_int64),
+                ("budget_bytes", C.c_int64)]
+
+
 class LjmdError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"LJMD_E_{_ERRNAMES.get(code, code)} ({code}): {msg}")
@@ -84,7 +93,7 @@ EXPORTED = [
     "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_last_error", "ljmd_version",
     "ljmd_batch_create", "ljmd_batch_destroy", "ljmd_batch_footprint", "ljmd_batch_admit",
     "ljmd_batch_run_block", "ljmd_batch_poll", "ljmd_batch_read", "ljmd_batch_slot_steps",
-    "ljmd_batch_release",
+    "ljmd_batch_release", "ljmd_batch_get_stats",
 ]
 
 
@@ -123,6 +132,7 @@ def load(path: str = LIB_PATH):
         "ljmd_batch_read": ([vp, C.c_int32, dp, dp, dp, dp, dp], C.c_int),
         "ljmd_batch_slot_steps": ([vp, C.c_int32, lp], C.c_int),
         "ljmd_batch_release": ([vp, C.c_int32], C.c_int),
+        "ljmd_batch_get_stats": ([vp, C.POINTER(LjmdBatchStats)], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -428,7 +438,7 @@ class Batch:
         return int(out.value)
 
     def read(self, slot, energy=True):
-        n = self._n[int(slot)]
+        n = max(1, self._n.get(int(slot), 0))  # an unknown slot gets LJMD_E_STATE below
         pos = np.empty((n, 3))
         vel = np.empty((n, 3))
         f = np.empty((n, 3))
@@ -440,6 +450,11 @@ class Batch:
         if energy:
             out.update(potential=float(e[0]), kinetic=float(e[1]), virial=w)
         return out
+
+    def stats(self):
+        st = LjmdBatchStats()
+        _check(self._lib.ljmd_batch_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in LjmdBatchStats._fields_}
 
     def release(self, slot):
         _check(self._lib.ljmd_batch_release(self._h, int(slot)))

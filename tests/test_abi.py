@@ -119,7 +119,8 @@ def test_no_device_reports_device_error(lib):
 
 
 STRUCTS = [("ljmd_config", "LjmdConfig"), ("ljmd_stats", "LjmdStats"),
-           ("ljmd_batch_config", "LjmdBatchConfig"), ("ljmd_replica_spec", "LjmdReplicaSpec")]
+           ("ljmd_batch_config", "LjmdBatchConfig"), ("ljmd_replica_spec", "LjmdReplicaSpec"),
+           ("ljmd_batch_stats", "LjmdBatchStats")]
 
 
 @pytest.mark.parametrize("cname,pyname", STRUCTS)

@@ -147,7 +147,10 @@ def test_overflow_in_block_reruns_only_that_replica(ljmd_mod, oracle_mod):
                        threads_per_particle=TPP, block_size=BLOCK)
     sc = b.admit(comp, 60)
     ss = b.admit(steady, n_steady)
+    cap0 = b.stats()["nlist_capacity"]
     _run_until_done(b, [sc, ss])
+    st = b.stats()
+    assert st["overflow_reruns"] >= 1 and st["nlist_capacity"] > cap0, (st, cap0)
     # the steady replica did not overflow: its result is untouched by the re-runs
     _same(b.read(ss), _alone(ljmd_mod, steady, n_steady, "fp64"))
     got = b.read(sc)
@@ -187,6 +190,8 @@ def test_slots_budget_and_errors(ljmd_mod):
     s2 = b.admit(spec, 4)
     assert s2 == s0
     _run_until_done(b, [s1, s2])
+    st = b.stats()
+    assert st["resident"] == 2 and st["running"] == 0 and st["used_bytes"] == 2 * fp
     # a box too small for the cutoff
     tiny = gen.make_lj_fluid(8, rho=0.8, seed=4)
     with pytest.raises(E.LjmdError) as e:
