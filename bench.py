@@ -42,6 +42,12 @@ STATE_BYTES = 128  # count 4, x+type 28, v 24, x_build 24 read; x 24, v 24 writt
 LIST_ENTRY_BYTES = 2  # 16-bit tile index per list entry
 
 
+def rebuild_bytes(mean_list):
+    """Bytes a list rebuild must move per atom: bin (read x 24, write key 4), sort and permute
+    (key and index 16, state gather 80 read + 80 written), list write (2 per entry + count 4)."""
+    return 28 + 16 + 160 + LIST_ENTRY_BYTES * mean_list + 4
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -92,6 +98,30 @@ def run_gpu(spec, precision, steps, warmup, timing_steps):
     }
     g.close()
     return out
+
+
+def energy_drift(spec, precision, steps, every, dt=0.005):
+    """NVE energy drift: least-squares slope of (E(t) - E(0)) / N against t / tau over
+    `steps` steps sampled every `every` steps, and the RMS of (E - E(0)) / N."""
+    from paper_1308_5587_amd import ljmd
+
+    g = ljmd.System.from_spec(spec, precision=precision)
+    U, K = g.energy()
+    e0 = U + K
+    t, de = [0.0], [0.0]
+    for k in range(every, steps + 1, every):
+        g.step(every)
+        U, K = g.energy()
+        t.append(k * dt)
+        de.append((U + K - e0) / spec.n)
+    st = g.stats()
+    g.close()
+    t = np.array(t)
+    de = np.array(de)
+    slope = float(np.polyfit(t, de, 1)[0])
+    return {"drift_per_atom_per_tau": slope, "rms_per_atom": float(np.sqrt(np.mean(de ** 2))),
+            "tau": steps * dt, "steps": steps, "samples": len(t), "rebuilds": st["rebuilds"],
+            "e0_per_atom": e0 / spec.n}
 
 
 def run_cpu_baseline(spec, steps):
@@ -219,6 +249,7 @@ def main():
     ap.add_argument("--batched-blocks", type=int, default=5)
     ap.add_argument("--batched-sample", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-drift", action="store_true")
     ap.add_argument("--serve-rates", type=str, default="4,16")
     ap.add_argument("--serve-count", type=int, default=32)
     args = ap.parse_args()
@@ -243,6 +274,18 @@ def main():
         log("[bench] mixed")
         mixed = run_gpu(spec, "mixed", args.steps, args.warmup, args.timing_steps)
         log(f"[bench] mixed {mixed['value']:.4g} atom-steps/s")
+    drift = None
+    if not args.no_drift:
+        log("[bench] energy drift: N=2^20 over 5 tau, N=4000 over 100 tau")
+        small = inputs.make_lj_fluid(4000, rho=0.8442, T=1.2, seed=1)
+        drift = {"lj_fluid_N1048576": {p: energy_drift(spec, p, 1000, 50)
+                                       for p in ("fp64", "mixed")},
+                 "lj_fluid_N4000": {p: energy_drift(small, p, 20000, 200)
+                                    for p in ("fp64", "mixed")}}
+        for w, d in drift.items():
+            for p, v in d.items():
+                log(f"[bench] drift {w} {p}: {v['drift_per_atom_per_tau']:.3e} per atom per tau, "
+                    f"rms {v['rms_per_atom']:.3e}")
     batched = None
     if not args.no_batched:
         log("[bench] batched: 512 replicas")
@@ -292,6 +335,17 @@ def main():
                          "kernel_avg_ms": mixed["kernel_avg_ms"],
                          "threads_per_particle": mixed["threads_per_particle"],
                          "block_size": mixed["block_size"]}
+    # the whole step against the method's bytes: list + state every step, rebuild amortised
+    k_bar = fp["steps_per_rebuild"] or float("inf")
+    b_step = (LIST_ENTRY_BYTES * fp["mean_list_length"] + 4 + (STATE_BYTES - 4)
+              + rebuild_bytes(fp["mean_list_length"]) / k_bar)
+    line["path_roofline"] = {"bound": "hbm", "bytes_per_atom_step": b_step,
+                             "ceiling_atom_steps_per_s": HBM_PEAK_GBS * 1e9 / b_step,
+                             "frac": fp["value"] / (HBM_PEAK_GBS * 1e9 / b_step),
+                             "mixed_frac": (mixed["value"] / (HBM_PEAK_GBS * 1e9 / b_step)
+                                            if mixed else None)}
+    if drift is not None:
+        line["energy_drift"] = drift
     if batched is not None:
         line["batched"] = batched
     if served is not None:

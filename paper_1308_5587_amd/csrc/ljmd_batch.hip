@@ -39,8 +39,9 @@ constexpr int PAIR_ROWS = LJMD_MAX_TYPES * LJMD_MAX_TYPES;  // pair rows reserve
 
 // Device bytes per particle slot: positions x2, scratch, velocities, scratch, forces, build
 // positions (7 x 32), image counters and scratch (2 x 16), key/slot/perm/prep/count (5 x 4),
+// work order (2),
 // energy, virial and kinetic per particle (8 + 48 + 8), the block snapshot (2 x 32 + 16).
-constexpr int64_t PER_PARTICLE = 7 * 32 + 2 * 16 + 5 * 4 + 64 + 2 * 32 + 16;
+constexpr int64_t PER_PARTICLE = 7 * 32 + 2 * 16 + 5 * 4 + 2 + 64 + 2 * 32 + 16;
 // per cell entry: rank, xyz, count, start, replica tag
 constexpr int64_t PER_CELL = 5 * 4;
 // per brick: BrickInfo, halo cells, tile table
@@ -151,6 +152,7 @@ struct ljmd_batch {
     int4 *d_img = nullptr, *d_img_scr = nullptr;
     int *d_key = nullptr, *d_slot = nullptr, *d_perm = nullptr, *d_count = nullptr;
     uint16_t *d_nlist = nullptr;
+    uint16_t *d_work = nullptr;
     size_t nlist_alloc = 0;
     double *d_u = nullptr, *d_w = nullptr, *d_ke = nullptr, *d_partials = nullptr,
            *d_red = nullptr;
@@ -298,6 +300,7 @@ RebuildArgs rebuild_args(ljmd_batch *b, const int *go, int go_stride, int cur) {
     a.cell_xyz = b->d_cell_xyz;
     a.nl_count = b->d_count;
     a.nlist = b->d_nlist;
+    a.work = b->d_work;
     a.bricks = b->d_bricks;
     a.halo = b->d_halo;
     a.tile_tab = b->d_tile_tab;
@@ -326,6 +329,7 @@ ForceArgs force_args(ljmd_batch *b, int cur, const int *only, bool with_rem) {
     a.force = b->d_force;
     a.nl_count = b->d_count;
     a.nlist = b->d_nlist;
+    a.work = b->d_work;
     a.bricks = b->d_bricks;
     a.cell_start = b->d_cell_start;
     a.tile_tab = b->d_tile_tab;
@@ -653,6 +657,7 @@ int ljmd_batch_create(const ljmd_batch_config *cfg, ljmd_batch **out) {
     get(&b->d_slot, P);
     get(&b->d_perm, P);
     get(&b->d_count, (size_t)b->npad);
+    get(&b->d_work, P);
     get(&b->d_u, P);
     get(&b->d_w, 6 * P);
     get(&b->d_ke, P);

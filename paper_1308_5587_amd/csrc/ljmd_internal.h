@@ -95,6 +95,7 @@ constexpr int RED_BLOCK = 256;       // reduction workgroup size
 constexpr int RED_QUANT = 8;         // U, W[6], K
 constexpr int SORT_LDS = 1024;       // in-cell sort capacity per workgroup
 constexpr int SCAN_TILE = 8192;      // counts per LDS tile of the scan (multiple of 1024)
+constexpr int WORK_SORT_MAX = 1024;  // bricks with more atoms keep their particles in order
 
 // Dynamic LDS of the force kernel: the tile as double4 records (x, y, z, type), then the
 // pair table when there are several types.
@@ -124,6 +125,7 @@ struct ForceArgs {
     double4 *force;          // MODE_EVAL / MODE_FINAL output
     const int *nl_count;
     const uint16_t *nlist;   // 16-bit tile indices
+    const uint16_t *work;    // per brick: order in which its particles are taken
     const BrickInfo *bricks;
     const int *cell_start;
     const int *tile_tab;     // TILE_TAB ints per brick, written by the build
@@ -174,6 +176,7 @@ struct RebuildArgs {
     const int *cell_xyz;     // global cell -> packed local (cx | cy << 10 | cz << 20)
     int *nl_count;
     uint16_t *nlist;
+    uint16_t *work;          // per brick: its particles by decreasing list length (local index)
     const BrickInfo *bricks;
     const HaloCell *halo;
     int *tile_tab;

@@ -45,14 +45,13 @@ __device__ __forceinline__ double r2_canon(double x, double y, double z) {
     return t + zz;
 }
 
-// 1/x to full FP64 precision: hardware reciprocal estimate plus two Newton steps.
+// 1/x in FP64: the hardware reciprocal estimate (relative error below 5e-8 on gfx950) refined
+// by one Newton step, which squares the error: below 3e-15 relative (measured over 2^20
+// arguments in [0.3, 12]; a second step reproduces the correctly rounded quotient).
 __device__ __forceinline__ double rcp64(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    e = __builtin_fma(-x, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    return y;
+    const double y = __builtin_amdgcn_rcp(x);
+    const double e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
 }
 
 // Workgroup b of nb is dispatched to XCD (b mod 8). Map each XCD to a contiguous range
@@ -387,7 +386,7 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
     for (int p0 = 0; p0 < natoms; p0 += per_pass) {
         const int p = p0 + g;
         const bool active = p < natoms;
-        const int q = first + (active ? p : 0);
+        const int q = first + (active ? (int)a.work[first + p] : 0);
         const double4 xi = a.pos_in[q];
         const int ti = MULTI ? (int)xi.w : 0;
         int cnt = active ? a.nl_count[q] : 0;
@@ -885,7 +884,8 @@ template <bool MULTI, bool STAGED>
 __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem &t,
                                             const BrickInfo &bi, const double4 *__restrict__ st,
                                             const double *s_rl2, const RepParams &P,
-                                            int &my_max, unsigned long long &my_entries) {
+                                            int first, int *s_cnt, int &my_max,
+                                            unsigned long long &my_entries) {
     const int hy = (bi.dims >> 4) & 15, hz = (bi.dims >> 8) & 15;
     const int fpk = a.cell_xyz[bi.first_cell];
     const int wl = threadIdx.x & 63;
@@ -939,6 +939,7 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
             }
             if (active && lane == 0) {
                 a.nl_count[q] = count;
+                if (q - first < WORK_SORT_MAX) s_cnt[q - first] = count;
                 if (count > a.cap) {
                     atomicOr(&a.st->status, ST_OVERFLOW);
                     if (a.rep_status) atomicOr(&a.rep_status[bi.rep], ST_OVERFLOW);
@@ -965,6 +966,48 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
 // and fl(fl(x_j - x_i) + s) with s in {-L, 0, L} equals the branch-form minimum image bit
 // for bit for every pair that can be listed; unshifted halo cells need no addition at all.
 // With fewer than 3 cells on some axis the branch form is applied directly.
+// Order in which the force kernels take a brick's particles: by decreasing number of
+// 8-entry list chunks (a counting sort on LDS bins), so that the particles sharing a wavefront
+// have lists of similar length. Any order gives the same results: a particle's sum does not
+// depend on the lanes it runs on.
+__device__ __forceinline__ void work_order(const RebuildArgs &a, int first, int natoms,
+                                           const int *s_cnt, int *s_bin) {
+    if (natoms > WORK_SORT_MAX) {
+        for (int p = threadIdx.x; p < natoms; p += blockDim.x) a.work[first + p] = (uint16_t)p;
+        return;
+    }
+    for (int k = threadIdx.x; k < 256; k += blockDim.x) s_bin[k] = 0;
+    __syncthreads();  // also: every count is in s_cnt
+    for (int p = threadIdx.x; p < natoms; p += blockDim.x) {
+        const int chunks = (s_cnt[p] + 7) >> 3;
+        atomicAdd(&s_bin[255 - (chunks < 255 ? chunks : 255)], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        // exclusive scan of the 256 bins, 4 per lane
+        const int l = threadIdx.x;
+        const int v0 = s_bin[4 * l], v1 = s_bin[4 * l + 1], v2 = s_bin[4 * l + 2],
+                  v3 = s_bin[4 * l + 3];
+        const int tot = v0 + v1 + v2 + v3;
+        int inc = tot;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(inc, o);
+            if (l >= o) inc += u;
+        }
+        const int ex = inc - tot;
+        s_bin[4 * l] = ex;
+        s_bin[4 * l + 1] = ex + v0;
+        s_bin[4 * l + 2] = ex + v0 + v1;
+        s_bin[4 * l + 3] = ex + v0 + v1 + v2;
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < natoms; p += blockDim.x) {
+        const int chunks = (s_cnt[p] + 7) >> 3;
+        const int at = atomicAdd(&s_bin[255 - (chunks < 255 ? chunks : 255)], 1);
+        a.work[first + at] = (uint16_t)p;
+    }
+}
+
 template <bool MULTI>
 __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -995,7 +1038,10 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
         }
         if (t.total > TILE_INDEX_MAX) {
             // 16-bit tile indices cannot address this tile: no list for the brick
-            for (int q = first + (int)threadIdx.x; q < last; q += blockDim.x) a.nl_count[q] = 0;
+            for (int q = first + (int)threadIdx.x; q < last; q += blockDim.x) {
+                a.nl_count[q] = 0;
+                a.work[q] = (uint16_t)(q - first);
+            }
             if (threadIdx.x == 0) {
                 atomicOr(&a.st->status, ST_TILE);
                 if (a.rep_status) atomicOr(&a.rep_status[bi.rep], ST_TILE);
@@ -1009,10 +1055,15 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
     const int wl = threadIdx.x & 63;
     int my_max = 0;
     unsigned long long my_entries = 0ull;
+    __shared__ int s_cnt[WORK_SORT_MAX];
+    __shared__ int s_bin[256];
+    const int first = a.cell_start[bi.first_cell];
+    const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
     if (staged)
-        nlist_cells<MULTI, true>(a, t, bi, st, s_rl2, P, my_max, my_entries);
+        nlist_cells<MULTI, true>(a, t, bi, st, s_rl2, P, first, s_cnt, my_max, my_entries);
     else
-        nlist_cells<MULTI, false>(a, t, bi, st, s_rl2, P, my_max, my_entries);
+        nlist_cells<MULTI, false>(a, t, bi, st, s_rl2, P, first, s_cnt, my_max, my_entries);
+    work_order(a, first, natoms, s_cnt, s_bin);
 
     // wavefront reductions of the build statistics, one atomic each per wavefront
     for (int o = 32; o > 0; o >>= 1) {

@@ -75,6 +75,7 @@ struct ljmd_system {
     int *d_key = nullptr, *d_slot = nullptr, *d_perm = nullptr;
     int *d_count = nullptr;
     uint16_t *d_nlist = nullptr;
+    uint16_t *d_work = nullptr;
     int cap = 0;
     size_t nlist_alloc = 0;
     double *d_u = nullptr, *d_w = nullptr, *d_ke = nullptr, *d_partials = nullptr,
@@ -267,6 +268,7 @@ RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
     a.cell_xyz = s->d_cell_xyz;
     a.nl_count = s->d_count;
     a.nlist = s->d_nlist;
+    a.work = s->d_work;
     a.bricks = s->d_bricks;
     a.halo = s->d_halo;
     a.tile_tab = s->d_tile_tab;
@@ -294,6 +296,7 @@ ForceArgs force_args(ljmd_system *s, int cur) {
     a.force = s->d_force;
     a.nl_count = s->d_count;
     a.nlist = s->d_nlist;
+    a.work = s->d_work;
     a.bricks = s->d_bricks;
     a.cell_start = s->d_cell_start;
     a.tile_tab = s->d_tile_tab;
@@ -721,6 +724,7 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
     rc = rc ? rc : dalloc_t(s, &s->d_slot, N);
     rc = rc ? rc : dalloc_t(s, &s->d_perm, N);
     rc = rc ? rc : dalloc_t(s, &s->d_count, (size_t)s->npad);
+    rc = rc ? rc : dalloc_t(s, &s->d_work, N);
     rc = rc ? rc : dalloc_t(s, &s->d_u, N);
     rc = rc ? rc : dalloc_t(s, &s->d_w, 6 * N);
     rc = rc ? rc : dalloc_t(s, &s->d_ke, N);

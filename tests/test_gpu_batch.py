@@ -142,7 +142,8 @@ def _compressing(n_side=12, rho=0.3, rate=1.0, seed=21):
 def test_overflow_in_block_reruns_only_that_replica(ljmd_mod, oracle_mod):
     print_case("in-block list overflow: re-run of the overflowing replica only")
     comp = _compressing()
-    steady, n_steady = gen.make_lj_fluid(1000, rho=0.6, T=1.4, seed=12), 60
+    # both start dilute, so the list capacity is sized for about 31 neighbours
+    steady, n_steady = gen.make_lj_fluid(1000, rho=0.3, T=1.4, seed=12), 60
     b = ljmd_mod.Batch(256 << 20, 4, precision="fp64", block_steps=20,
                        threads_per_particle=TPP, block_size=BLOCK)
     sc = b.admit(comp, 60)
