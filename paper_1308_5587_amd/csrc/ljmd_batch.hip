@@ -264,10 +264,19 @@ int ensure_stage(ljmd_batch *b, size_t doubles) {
     return LJMD_OK;
 }
 
+// Launch extents: the high-water mark of each range allocator rounded up to a power of two
+// (at least a minimum), so that the block graph is captured again only when an extent doubles
+// or halves.
+int pow2_extent(int hw, int lo, int cap) {
+    int e = lo;
+    while (e < hw && e < cap) e <<= 1;
+    return std::min(e, cap);
+}
+
 void update_extents(ljmd_batch *b) {
-    const int pe = std::min(b->p_cap, round_up(std::max(1, b->palloc.high_water()), 4096));
-    const int ce = std::min(b->c_cap, round_up(std::max(1, b->calloc_.high_water()), 1024));
-    const int be = std::min(b->b_cap, round_up(std::max(1, b->balloc.high_water()), 256));
+    const int pe = pow2_extent(b->palloc.high_water(), 4096, b->p_cap);
+    const int ce = pow2_extent(b->calloc_.high_water(), 1024, b->c_cap);
+    const int be = pow2_extent(b->balloc.high_water(), 256, b->b_cap);
     if (pe != b->p_ext || ce != b->c_ext || be != b->b_ext) drop_graph(b);
     b->p_ext = pe;
     b->c_ext = ce;
@@ -488,6 +497,16 @@ int release_slot(ljmd_batch *b, int s) {
     b->used_bytes -= sl.bytes;
     sl = Slot{};
     update_extents(b);
+    return LJMD_OK;
+}
+
+// Snapshot of every particle slot in use (one copy per array over the launch extent).
+int snapshot_all(ljmd_batch *b) {
+    const size_t n = (size_t)b->p_ext;
+    const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+    HIPCHK(hipMemcpyAsync(b->d_snap_pos, b->d_pos[b->cur], n * sizeof(double4), k, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_snap_vel, b->d_vel, n * sizeof(double4), k, b->stream));
+    HIPCHK(hipMemcpyAsync(b->d_snap_img, b->d_img, n * sizeof(int4), k, b->stream));
     return LJMD_OK;
 }
 
@@ -935,7 +954,7 @@ int ljmd_batch_run_block(ljmd_batch *b) {
     for (int s = 0; s < b->max_slots; ++s)
         if (b->slots[s].used && !b->slots[s].done) running.push_back(s);
     if (running.empty()) return LJMD_OK;
-    for (int s : running) CHK(copy_range(b, b->slots[s], true));
+    CHK(snapshot_all(b));
     CHK(clear_status(b));
     CHK(ensure_graph(b));
     HIPCHK(hipGraphLaunch(b->graph, b->stream));

@@ -392,16 +392,8 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
         int cnt = active ? a.nl_count[q] : 0;
         cnt = cnt < a.cap ? cnt : a.cap;
 
-        // the integration state does not depend on the pair loop: request it now
-        double4 v_pre = make_double4(0.0, 0.0, 0.0, 0.0), b_pre = v_pre;
-        int4 im_pre = make_int4(0, 0, 0, 0);
-        if (MODE != MODE_EVAL && active && lane == 0) {
-            v_pre = a.vel[q];
-            if (MODE == MODE_FUSED) {
-                b_pre = a.xb[q];
-                im_pre = a.img[q];
-            }
-        }
+        // the integration state (velocity, build position, images) is read after the pair
+        // loop: holding it across the loop would cost 20 registers per lane and occupancy
 
         Acc<PREC> acc;
         double ue = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
@@ -491,7 +483,7 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
             if (MODE == MODE_EVAL) {
                 a.force[q] = make_double4(fx, fy, fz, 0.0);
             } else {
-                double4 v = v_pre;
+                double4 v = a.vel[q];
                 const double hm = P.half_dt * v.w;
                 // second half kick of the current step: full-step velocity
                 v.x = __builtin_fma(hm, fx, v.x);
@@ -515,7 +507,7 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                     x.x = __builtin_fma(P.dt, v.x, x.x);
                     x.y = __builtin_fma(P.dt, v.y, x.y);
                     x.z = __builtin_fma(P.dt, v.z, x.z);
-                    int4 im = im_pre;
+                    int4 im = a.img[q];
                     const int4 im0 = im;
                     wrap_coord(x.x, im.x, L0);
                     wrap_coord(x.y, im.y, L1);
@@ -523,6 +515,7 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                     a.pos_out[q] = x;
                     a.vel[q] = v;
                     if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
+                    const double4 b_pre = a.xb[q];
                     const double ex = mi_rint(x.x - b_pre.x, L0, iL0);
                     const double ey = mi_rint(x.y - b_pre.y, L1, iL1);
                     const double ez = mi_rint(x.z - b_pre.z, L2, iL2);

@@ -211,14 +211,16 @@ def test_served_stream_results_equal_alone(ljmd_mod):
     print_case("served request stream: each result equals its alone run")
     from paper_1308_5587_amd import serve
 
-    arrivals = gen.make_arrivals(6, rate=40.0, seed=7, n_lo=512, n_hi=3000, steps_lo=20,
-                                 steps_hi=90)
+    # arrivals far faster than service, so replicas share the GPU and queue for slots
+    arrivals = gen.make_arrivals(6, rate=5000.0, seed=7, n_lo=512, n_hi=3000, steps_lo=100,
+                                 steps_hi=300)
     mk = lambda p: gen.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed)  # noqa: E731
     reqs = serve.requests_from_arrivals(arrivals, mk)
     b = ljmd_mod.Batch(128 << 20, 3, precision="mixed", block_steps=10,
                        threads_per_particle=TPP, block_size=BLOCK)
     rep = serve.serve(b, reqs, keep_results=True)
     b.close()
-    assert len(rep.requests) == 6 and rep.peak_resident >= 2
+    assert len(rep.requests) == 6
+    assert rep.peak_resident == 3, rep.peak_resident
     for r in rep.requests:
         _same(r.result, _alone(ljmd_mod, r.spec, r.nsteps, "mixed"))
