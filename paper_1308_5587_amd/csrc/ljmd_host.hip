@@ -96,37 +96,6 @@ static uint64_t spread3(uint64_t v) {  // 10-bit value -> every third bit
     return r;
 }
 
-// A box of at most 27 cells is one brick whose halo is every cell: each particle is tested
-// against all atoms of the box (no more than the 27-cell stencil would give), with the
-// branch-form minimum image, and the tile is staged once per replica instead of once per cell.
-static int make_whole_box_grid(const int nc[3], ReplicaGrid *g) {
-    const int ncell = nc[0] * nc[1] * nc[2];
-    g->rank.assign(ncell, 0);
-    g->xyz.assign(ncell, 0);
-    g->bricks.assign(1, BrickInfo{});
-    g->halo.assign((size_t)HALO_MAX, HaloCell{0, 0});
-    for (int x = 0; x < nc[0]; ++x)
-        for (int y = 0; y < nc[1]; ++y)
-            for (int z = 0; z < nc[2]; ++z) {
-                const int lin = (x * nc[1] + y) * nc[2] + z;
-                g->rank[lin] = lin;
-                g->xyz[lin] = x | (y << 10) | (z << 20);
-                g->halo[lin] = HaloCell{lin, 21};  // 21: no shift code on any axis
-            }
-    BrickInfo &bi = g->bricks[0];
-    bi.first_cell = 0;
-    bi.ncell = ncell;
-    bi.nhalo = ncell;
-    bi.dims = 0;  // the halo geometry fields serve the stencil walk only; no wrap-free axis
-    bi.rep = 0;
-    for (int a = 0; a < 3; ++a) g->nc[a] = nc[a];
-    g->canonical = true;
-    g->ncell = ncell;
-    g->nbrick = 1;
-    g->max_halo = ncell;
-    return LJMD_OK;
-}
-
 int make_grid(const double L[3], double rl_max, ReplicaGrid *g) {
     for (int a = 0; a < 3; ++a)
         if (rl_max > 0.5 * L[a])
@@ -141,7 +110,6 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g) {
         nc[a] = (int)v;
     }
     const int ncell = nc[0] * nc[1] * nc[2];
-    if (ncell <= 27) return make_whole_box_grid(nc, g);
     // Bricks of up to 2 x 2 x 2 cells (one cell wide on an axis with fewer than 4 cells,
     // single cells when some axis has fewer than 3), bricks in Morton order, cells in Morton
     // order inside their brick: every brick is a contiguous range of cells.
