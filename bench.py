@@ -52,6 +52,33 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_lj_fluid_n1048576_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1308_5587_amd", "csrc", f)
+                  for f in ("ljmd_kernels.hip", "ljmd_internal.h")]
+
+
+def measured_traffic(tpp, block):
+    """HBM bytes per launch of the fused FP64 kernel from the committed counter passes, if they
+    were taken on the current kernel sources with this launch shape; else None."""
+    import hashlib
+
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line
+                  and line.split(": ", 1)[0] in ("launch", "traffic-bytes-per-launch",
+                                                 "kernel-source-sha256"))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    if fields.get("kernel-source-sha256", "").strip() != h.hexdigest():
+        return None
+    if fields.get("launch", "").strip() != f"fp64 tpp={tpp} block={block}":
+        return None
+    return float(fields["traffic-bytes-per-launch"])
+
+
 def run_gpu(spec, precision, steps, warmup, timing_steps):
     import torch
 
@@ -322,7 +349,7 @@ def main():
                    "mean_list_length": fp["mean_list_length"]},
         "roofline": {"bound": "hbm", "achieved": fp["achieved_gbs"], "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": fp["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": measured_traffic(fp["threads_per_particle"], fp["block_size"]),
                      "kernel": "k_force<fp64, FUSED>", "kernel_avg_ms": fp["kernel_avg_ms"],
                      "bytes_per_atom": fp["bytes_per_atom"]},
         "cpu_baseline": cpu,

@@ -2,13 +2,17 @@
 
     python -m paper_1308_5587_amd.profile_run [--n N] [--steps K] [--precision fp64|mixed]
                                               [--tpp T] [--block B] [--copy-mib M]
+                                              [--replicas R --blocks K]
 
 First a plain device-to-device copy of M MiB (torch's copy kernel): under a counter pass
 its FETCH_SIZE and WRITE_SIZE give the factor between the counters and bytes actually moved.
 Then the LJ fluid (density 0.8442, T 1.2, r_cut 2.5, skin 0.4, dt 0.005) is set up with
 fixed lanes per particle and workgroup size (so no tuning launches appear in the trace) and
-advanced K steps. Every step goes through the library's HIP kernels; one line per phase is
-printed so a profiler's own output can be matched to them.
+advanced K steps. With --replicas R the batched workload runs instead: R replicas of uneven
+size (N uniform in [256, 8192], density in [0.6, 0.9], T in [0.8, 1.5], mixed precision)
+admitted into one batch and advanced K blocks of 100 steps. Every step goes through the
+library's HIP kernels; one line per phase is printed so a profiler's own output can be
+matched to them.
 """
 
 from __future__ import annotations
@@ -31,6 +35,8 @@ def main(argv=None):
     ap.add_argument("--tpp", type=int, default=2)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--replicas", type=int, default=0)
+    ap.add_argument("--blocks", type=int, default=2)
     args = ap.parse_args(argv)
 
     import torch
@@ -49,6 +55,26 @@ def main(argv=None):
     torch.cuda.synchronize()
     print(f"[profile] copy {nbytes} bytes read, {nbytes} bytes written", flush=True)
     del src, dst
+
+    if args.replicas:
+        params = inputs.make_replica_specs(args.replicas, seed=0)
+        specs = [inputs.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed) for p in params]
+        b = ljmd.Batch(8 << 30, args.replicas, precision="mixed", block_steps=100,
+                       threads_per_particle=args.tpp, block_size=args.block)
+        for sp in specs:
+            b.admit(sp, 100 * args.blocks)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.blocks):
+            b.run_block()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = b.stats()
+        print(f"[profile] batched replicas={args.replicas} atoms={sum(s.n for s in specs)} "
+              f"blocks={args.blocks} tpp={st['threads_per_particle']} "
+              f"block={st['block_size']} wall={dt:.4f}s rebuilds={st['rebuilds']}", flush=True)
+        b.close()
+        return 0
 
     spec = inputs.make_lj_fluid(args.n, rho=0.8442, T=1.2, seed=1)
     g = ljmd.System.from_spec(spec, precision=args.precision, threads_per_particle=args.tpp,
