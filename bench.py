@@ -216,6 +216,7 @@ def run_batched(count, block_steps, blocks, sample):
     assert len(b.poll()) == count
     for s in slots:
         assert b.slot_steps(s) == nsteps
+    bst = b.stats()
     b.close()
     # a sample of the same replicas, one by one on the plain FP64 path
     idx = np.random.default_rng(5).choice(count, size=min(sample, count), replace=False)
@@ -226,6 +227,8 @@ def run_batched(count, block_steps, blocks, sample):
     return {"value": value, "unit": "atom-steps/s", "replicas": count, "atoms": atoms,
             "block_steps": block_steps, "blocks": blocks, "ms_per_block": 1e3 * wall / blocks,
             "admit_s": t_admit, "dtype": "f32 pair / f64 state",
+            "threads_per_particle": bst["threads_per_particle"], "block_size": bst["block_size"],
+            "tile_capacity": bst["tile_capacity"], "rebuilds": bst["rebuilds"],
             "one_by_one_fp64": {"value": alone, "unit": "atom-steps/s", "replicas": len(idx),
                                 "steps": block_steps * blocks},
             "speedup_vs_one_by_one_fp64": value / alone}

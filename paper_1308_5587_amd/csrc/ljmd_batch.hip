@@ -211,7 +211,8 @@ int describe(const ljmd_batch *b, const ljmd_replica_spec *sp, PairTable *pt, Re
                 return set_err(LJMD_E_INVAL, "pair table is not symmetric at (%d,%d)", i, j);
         }
     make_pair_table(nt, sp->eps, sp->sigma, sp->r_cut, b->cfg.skin, pt);
-    return make_grid(sp->box, pt->rl_max, g);
+    return make_grid(sp->box, pt->rl_max, g, sp->n,
+                     choose_tile_cap(1e9, HALO_MAX, std::max(b->max_ntypes, sp->ntypes), b->lds_limit));
 }
 
 // list entries a replica is expected to need: neighbours within the largest list radius at

@@ -68,8 +68,11 @@ struct ReplicaGrid {
     std::vector<BrickInfo> bricks;   // first_cell local, rep unset
     std::vector<HaloCell> halo;      // HALO_MAX per brick, ranks local
 };
-// Returns LJMD_E_BOX when r_L,max exceeds half a box edge.
-int make_grid(const double L[3], double rl_max, ReplicaGrid *g);
+// Returns LJMD_E_BOX when r_L,max exceeds half a box edge. With n_atoms and tile_limit
+// (atoms an LDS tile can hold) given, bricks shrink to single cells when a 2 x 2 x 2 brick's
+// halo would not fit the tile at the mean density.
+int make_grid(const double L[3], double rl_max, ReplicaGrid *g, int64_t n_atoms = 0,
+              int tile_limit = 0);
 
 // Tile capacity (atoms staged in LDS) for a mean occupancy of atoms_per_cell.
 int choose_tile_cap(double atoms_per_cell, int max_halo, int max_ntypes, size_t lds_limit);

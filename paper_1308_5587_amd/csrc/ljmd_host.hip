@@ -96,7 +96,43 @@ static uint64_t spread3(uint64_t v) {  // 10-bit value -> every third bit
     return r;
 }
 
-int make_grid(const double L[3], double rl_max, ReplicaGrid *g) {
+// Boxes of at most 27 cells: every cell neighbours every other one, so each brick's halo is
+// the whole box (its distinct cells) and the list build scans all of them with the branch-form
+// minimum image. The bricks are the z-layers of cells: a few workgroups per replica, each
+// with a share of the atoms comparable to a 2 x 2 x 2 brick of a large box.
+static int make_small_box_grid(const int nc[3], ReplicaGrid *g) {
+    const int ncell = nc[0] * nc[1] * nc[2];
+    const int per = nc[0] * nc[1];
+    const int nbrick = nc[2];
+    g->rank.assign(ncell, 0);
+    g->xyz.assign(ncell, 0);
+    g->bricks.assign(nbrick, BrickInfo{});
+    g->halo.assign((size_t)nbrick * HALO_MAX, HaloCell{0, 0});
+    for (int x = 0; x < nc[0]; ++x)
+        for (int y = 0; y < nc[1]; ++y)
+            for (int z = 0; z < nc[2]; ++z) {
+                const int r = z * per + x * nc[1] + y;
+                g->rank[(x * nc[1] + y) * nc[2] + z] = r;
+                g->xyz[r] = x | (y << 10) | (z << 20);
+            }
+    for (int b = 0; b < nbrick; ++b) {
+        BrickInfo &bi = g->bricks[b];
+        bi.first_cell = b * per;
+        bi.ncell = per;
+        bi.nhalo = ncell;
+        bi.dims = 0;  // the stencil-walk fields are unused here; no wrap-free axis
+        bi.rep = 0;
+        for (int r = 0; r < ncell; ++r) g->halo[(size_t)b * HALO_MAX + r] = HaloCell{r, 21};
+    }
+    for (int a = 0; a < 3; ++a) g->nc[a] = nc[a];
+    g->canonical = true;
+    g->ncell = ncell;
+    g->nbrick = nbrick;
+    g->max_halo = ncell;
+    return LJMD_OK;
+}
+
+int make_grid(const double L[3], double rl_max, ReplicaGrid *g, int64_t n_atoms, int tile_limit) {
     for (int a = 0; a < 3; ++a)
         if (rl_max > 0.5 * L[a])
             return set_err(LJMD_E_BOX, "r_cut + skin = %g exceeds half the box edge %g", rl_max, L[a]);
@@ -110,15 +146,24 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g) {
         nc[a] = (int)v;
     }
     const int ncell = nc[0] * nc[1] * nc[2];
+    if (ncell <= 27) return make_small_box_grid(nc, g);
     // Bricks of up to 2 x 2 x 2 cells (one cell wide on an axis with fewer than 4 cells,
     // single cells when some axis has fewer than 3), bricks in Morton order, cells in Morton
     // order inside their brick: every brick is a contiguous range of cells.
     const bool canonical = nc[0] < 3 || nc[1] < 3 || nc[2] < 3;
     int ext[3], nb[3];
-    for (int a = 0; a < 3; ++a) {
-        ext[a] = (!canonical && nc[a] >= 4) ? 2 : 1;
-        nb[a] = (nc[a] + ext[a] - 1) / ext[a];
+    for (int a = 0; a < 3; ++a) ext[a] = (!canonical && nc[a] >= 4) ? 2 : 1;
+    if (n_atoms > 0 && tile_limit > 0) {
+        // while the halo would not fit the LDS tile at this density (with room for
+        // fluctuations), halve the brick along z, then y, then x: 64 halo cells, 48, 36, 27
+        const double per_cell = (double)n_atoms / ncell;
+        for (int a = 2; a >= 0; --a) {
+            const int halo = (ext[0] + 2) * (ext[1] + 2) * (ext[2] + 2);
+            if (1.2 * halo * per_cell + 64.0 <= tile_limit) break;
+            ext[a] = 1;
+        }
     }
+    for (int a = 0; a < 3; ++a) nb[a] = (nc[a] + ext[a] - 1) / ext[a];
     const int nbrick = nb[0] * nb[1] * nb[2];
     std::vector<std::pair<uint64_t, int>> bmort(nbrick);
     for (int x = 0; x < nb[0]; ++x)
@@ -207,9 +252,10 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g) {
 
 int choose_tile_cap(double atoms_per_cell, int max_halo, int max_ntypes, size_t lds_limit) {
     const double expect = max_halo * atoms_per_cell;
-    int cap = (int)std::ceil(1.35 * expect + 128.0);
-    cap = (cap + 63) & ~63;
-    cap = std::min(cap, TILE_MAX);
+    // clamp before converting: a huge request (the largest tile the LDS allows) must not
+    // overflow the integer
+    int cap = (int)std::ceil(std::min(1.1 * expect + 128.0, (double)TILE_MAX));
+    cap = std::min((cap + 63) & ~63, TILE_MAX);
     const size_t limit = std::min<size_t>(lds_limit, 64 * 1024) - 4096;
     while (cap > 64 && std::max(force_lds_bytes(cap, max_ntypes), nlist_lds_bytes(cap, max_ntypes)) > limit)
         cap -= 64;

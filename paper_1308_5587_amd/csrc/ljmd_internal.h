@@ -80,10 +80,12 @@ struct HaloCell {
     int shift;
 };
 constexpr int HALO_MAX = 64;
-constexpr int TILE_MAX = 2560;        // tile atoms staged in LDS at most (FP64 SoA: 60 KiB)
+constexpr int TILE_MAX = 2560;        // tile atoms staged in LDS at most (32 B each: 80 KiB)
+constexpr int LJMD_MAX_TYPES_DEVICE = 16;     // type count the kernels' tables allow
+constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr int TILE_INDEX_MAX = 65535; // 16-bit tile indices
 #ifndef LJMD_FORCE_BATCH
-#define LJMD_FORCE_BATCH 4
+#define LJMD_FORCE_BATCH 2
 #endif
 constexpr int FORCE_BATCH = LJMD_FORCE_BATCH;  // neighbour positions requested together (1, 2, 4, 8)
 

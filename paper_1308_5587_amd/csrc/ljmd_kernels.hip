@@ -600,9 +600,17 @@ __global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
 #undef LJMD_PASSES
 }
 
+// A tile capacity or type count outside the kernels' assumptions is refused before launch
+// (the LDS carve-up and the pair-table offset are derived from them).
+static bool lds_args_ok(int tile_cap, int max_ntypes, size_t smem) {
+    return tile_cap >= 64 && tile_cap <= TILE_MAX && max_ntypes >= 1 &&
+           max_ntypes <= LJMD_MAX_TYPES_DEVICE && smem <= LDS_MAX_BYTES;
+}
+
 template <int PREC, int TPP, int MODE, bool ENERGY>
 static hipError_t launch_force_t(hipStream_t s, const ForceArgs &a, int block) {
     const size_t smem = force_lds_bytes(a.tile_cap, a.max_ntypes);
+    if (!lds_args_ok(a.tile_cap, a.max_ntypes, smem)) return hipErrorInvalidValue;
     if (a.max_ntypes > 1)
         hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, true>), dim3(a.nbrick), dim3(block),
                            smem, s, a);
@@ -1093,6 +1101,8 @@ hipError_t launch_decode_list(hipStream_t s, const RebuildArgs &a, int *out) {
 }
 
 hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
+    if (!lds_args_ok(a.tile_cap, a.max_ntypes, nlist_lds_bytes(a.tile_cap, a.max_ntypes)))
+        return hipErrorInvalidValue;
     const int b = 256;
     const int g = (a.n + b - 1) / b;
     hipLaunchKernelGGL(k_bin, dim3(g), dim3(b), 0, s, a);

@@ -193,6 +193,9 @@ def test_slots_budget_and_errors(ljmd_mod):
     _run_until_done(b, [s1, s2])
     st = b.stats()
     assert st["resident"] == 2 and st["running"] == 0 and st["used_bytes"] == 2 * fp
+    # the whole box of 500 atoms is one staged tile (a capacity outside [64, 2560] would mean
+    # every neighbour is read from global memory)
+    assert 500 <= st["tile_capacity"] <= 2560, st
     # a box too small for the cutoff
     tiny = gen.make_lj_fluid(8, rho=0.8, seed=4)
     with pytest.raises(E.LjmdError) as e:
