@@ -254,7 +254,7 @@ int choose_tile_cap(double atoms_per_cell, int max_halo, int max_ntypes, size_t 
     const double expect = max_halo * atoms_per_cell;
     // clamp before converting: a huge request (the largest tile the LDS allows) must not
     // overflow the integer
-    int cap = (int)std::ceil(std::min(1.1 * expect + 128.0, (double)TILE_MAX));
+    int cap = (int)std::ceil(std::min(1.05 * expect + 128.0, (double)TILE_MAX));
     cap = std::min((cap + 63) & ~63, TILE_MAX);
     const size_t limit = std::min<size_t>(lds_limit, 64 * 1024) - 4096;
     while (cap > 64 && std::max(force_lds_bytes(cap, max_ntypes), nlist_lds_bytes(cap, max_ntypes)) > limit)

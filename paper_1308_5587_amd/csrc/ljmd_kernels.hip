@@ -818,7 +818,7 @@ __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
 // lane order. MIK selects the minimum-image form, fixed per cell: 0 none (the halo cell is
 // in the primary image), 1 a constant shift of the halo cell's periodic image, 2 the branch
 // form (fewer than 3 cells on some axis).
-template <bool MULTI, bool STAGED, int MIK>
+template <bool MULTI, bool STAGED, int MIK, bool SOLO>
 __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                                                 const double4 *__restrict__ st,
                                                 const double *s_rl2, const RepParams &P, int o,
@@ -862,6 +862,18 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
         const double r2 = r2_canon(dx, dy, dz);
         const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.single_rl2;
         const bool hit = valid && (jst + tt) != q && r2 < rl2;
+        if (SOLO) {
+            // one lane per particle: its hits are appended in order, no group prefix needed
+            if (hit) {
+                if (count < a.cap) {
+                    const size_t slot = (size_t)((unsigned)count >> sh) * rstride + qbase +
+                                        (size_t)(count & ((1 << sh) - 1));
+                    a.nlist[slot] = (uint16_t)(o + tt);
+                }
+                ++count;
+            }
+            continue;
+        }
         const unsigned long long bal = __ballot(hit) & gmask;
         if (hit) {
             // hits of lower lanes of the group: mbcnt counts the set bits of bal below
@@ -879,13 +891,38 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
     }
 }
 
+// The minimum-image form of a stencil cell: branch form for small boxes, else the halo cell's
+// shift code (21: no shift on any axis).
+template <bool MULTI, bool STAGED, bool SOLO>
+__device__ __forceinline__ void nlist_scan_dispatch(const RebuildArgs &a,
+                                                    const double4 *__restrict__ st,
+                                                    const double *s_rl2, const RepParams &P,
+                                                    int o, int m, int jst, int code,
+                                                    const double4 &xi, int ti, int q, bool active,
+                                                    int Ln, int lane, unsigned long long gmask,
+                                                    int &count) {
+    if (P.canonical) {
+        nlist_scan_cell<MULTI, STAGED, 2, SOLO>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0, xi, ti,
+                                                q, active, Ln, lane, gmask, count);
+    } else if (code != 21) {
+        const double shx = (double)((code & 3) - 1) * P.L[0];
+        const double shy = (double)(((code >> 2) & 3) - 1) * P.L[1];
+        const double shz = (double)(((code >> 4) & 3) - 1) * P.L[2];
+        nlist_scan_cell<MULTI, STAGED, 1, SOLO>(a, st, s_rl2, P, o, m, jst, shx, shy, shz, xi, ti,
+                                                q, active, Ln, lane, gmask, count);
+    } else {
+        nlist_scan_cell<MULTI, STAGED, 0, SOLO>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0, xi, ti,
+                                                q, active, Ln, lane, gmask, count);
+    }
+}
+
 // The cells of one brick, one wavefront per cell; STAGED selects candidate positions from
 // the LDS tile or, for a tile larger than the LDS allocation, from global memory.
 template <bool MULTI, bool STAGED>
 __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem &t,
                                             const BrickInfo &bi, const double4 *__restrict__ st,
                                             const double *s_rl2, const RepParams &P,
-                                            int first, int *s_cnt, int &my_max,
+                                            int first, uint16_t *s_cnt, int &my_max,
                                             unsigned long long &my_entries) {
     const int hy = (bi.dims >> 4) & 15, hz = (bi.dims >> 8) & 15;
     const int fpk = a.cell_xyz[bi.first_cell];
@@ -924,23 +961,16 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                 const int m = t.off[h + 1] - o;
                 const int jst = t.start[h];
                 const int code = t.shift[h];
-                if (P.canonical) {
-                    nlist_scan_cell<MULTI, STAGED, 2>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0,
-                                                      xi, ti, q, active, Ln, lane, gmask, count);
-                } else if (code != 21) {  // 21: no shift on any axis
-                    const double shx = (double)((code & 3) - 1) * P.L[0];
-                    const double shy = (double)(((code >> 2) & 3) - 1) * P.L[1];
-                    const double shz = (double)(((code >> 4) & 3) - 1) * P.L[2];
-                    nlist_scan_cell<MULTI, STAGED, 1>(a, st, s_rl2, P, o, m, jst, shx, shy, shz,
-                                                      xi, ti, q, active, Ln, lane, gmask, count);
-                } else {
-                    nlist_scan_cell<MULTI, STAGED, 0>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0,
-                                                      xi, ti, q, active, Ln, lane, gmask, count);
-                }
+                if (Ln == 1)
+                    nlist_scan_dispatch<MULTI, STAGED, true>(a, st, s_rl2, P, o, m, jst, code, xi,
+                                                             ti, q, active, Ln, lane, gmask, count);
+                else
+                    nlist_scan_dispatch<MULTI, STAGED, false>(a, st, s_rl2, P, o, m, jst, code, xi,
+                                                              ti, q, active, Ln, lane, gmask, count);
             }
             if (active && lane == 0) {
                 a.nl_count[q] = count;
-                if (q - first < WORK_SORT_MAX) s_cnt[q - first] = count;
+                if (q - first < WORK_SORT_MAX) s_cnt[q - first] = (uint16_t)(count < 65535 ? count : 65535);
                 if (count > a.cap) {
                     atomicOr(&a.st->status, ST_OVERFLOW);
                     if (a.rep_status) atomicOr(&a.rep_status[bi.rep], ST_OVERFLOW);
@@ -972,7 +1002,7 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
 // have lists of similar length. Any order gives the same results: a particle's sum does not
 // depend on the lanes it runs on.
 __device__ __forceinline__ void work_order(const RebuildArgs &a, int first, int natoms,
-                                           const int *s_cnt, int *s_bin) {
+                                           const uint16_t *s_cnt, int *s_bin) {
     if (natoms > WORK_SORT_MAX) {
         for (int p = threadIdx.x; p < natoms; p += blockDim.x) a.work[first + p] = (uint16_t)p;
         return;
@@ -1009,8 +1039,10 @@ __device__ __forceinline__ void work_order(const RebuildArgs &a, int first, int 
     }
 }
 
+// Three workgroups of 512 per CU when the tile allows it: registers capped at 80 per lane.
 template <bool MULTI>
-__global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
+k_nlist(const RebuildArgs a) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const BrickInfo bi = a.bricks[b];
     if (!rebuilds(a, bi.rep)) return;
@@ -1056,7 +1088,7 @@ __global__ void __launch_bounds__(512) k_nlist(const RebuildArgs a) {
     const int wl = threadIdx.x & 63;
     int my_max = 0;
     unsigned long long my_entries = 0ull;
-    __shared__ int s_cnt[WORK_SORT_MAX];
+    __shared__ uint16_t s_cnt[WORK_SORT_MAX];
     __shared__ int s_bin[256];
     const int first = a.cell_start[bi.first_cell];
     const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
