@@ -232,6 +232,10 @@ int64_t footprint(const ljmd_batch *b, int64_t n, int ncell, int nbrick) {
 // Capacity of the list (entries per particle), rounded to whole chunks of 8 per lane. The
 // slot of entry k does not depend on the capacity, so the old buffer's contents are kept.
 int grow_list(ljmd_batch *b, int want) {
+    // the list build addresses rounds of 8 x lanes entries with a 32-bit stride
+    if (((uint64_t)b->npad << (3 + b->lshift)) > 0xFFFFFFFFull)
+        return set_err(LJMD_E_INVAL, "%d lanes per particle is too many for %d particle slots",
+                       1 << b->lshift, b->p_cap);
     const int unit = 8 << b->lshift;
     want = std::max(unit, round_up(want, unit));
     if (want <= b->cap && b->d_nlist) return LJMD_OK;
@@ -462,6 +466,9 @@ int tune(ljmd_batch *b, int s) {
     }
     for (int t : tpps) {
         if (want_tpp && t != want_tpp) continue;
+        int ls = 0;
+        while ((1 << ls) < t) ++ls;
+        if (((uint64_t)b->npad << (3 + ls)) > 0xFFFFFFFFull) continue;
         set_tpp(b, t);
         CHK(grow_list(b, b->cap));
         CHK(forced_rebuild(b, {s}));

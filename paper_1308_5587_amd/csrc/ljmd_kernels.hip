@@ -828,8 +828,10 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                                                 unsigned long long gmask, int &count) {
     // list slots (nl_slot in closed form with the particle's part precomputed)
     const int sh = 3 + a.lshift;
-    const size_t rstride = (size_t)a.npad << sh;
-    const size_t qbase = (size_t)q << sh;
+    // the round stride npad << sh fits 32 bits (the host keeps npad x 8 x lanes < 2^32), so
+    // the slot is one 32 x 32 + 64-bit multiply-add
+    const uint32_t rstride = (uint32_t)a.npad << sh;
+    const uint64_t qbase = (uint64_t)q << sh;
     for (int t0 = 0; t0 < m; t0 += Ln) {
         const int tt = t0 + lane;
         const bool valid = active && tt < m;
@@ -866,7 +868,7 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
             // one lane per particle: its hits are appended in order, no group prefix needed
             if (hit) {
                 if (count < a.cap) {
-                    const size_t slot = (size_t)((unsigned)count >> sh) * rstride + qbase +
+                    const uint64_t slot = (uint64_t)((uint32_t)count >> sh) * rstride + qbase +
                                         (size_t)(count & ((1 << sh) - 1));
                     a.nlist[slot] = (uint16_t)(o + tt);
                 }
@@ -874,7 +876,7 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
             }
             continue;
         }
-        const unsigned long long bal = __ballot(hit) & gmask;
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit) & gmask;
         if (hit) {
             // hits of lower lanes of the group: mbcnt counts the set bits of bal below
             // this lane
@@ -882,7 +884,7 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                                       (unsigned)(bal >> 32),
                                       __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
             if (k < a.cap) {
-                const size_t slot = (size_t)((unsigned)k >> sh) * rstride + qbase +
+                const uint64_t slot = (uint64_t)((uint32_t)k >> sh) * rstride + qbase +
                                     (size_t)(k & ((1 << sh) - 1));
                 a.nlist[slot] = (uint16_t)(o + tt);
             }

@@ -221,7 +221,13 @@ int setup_table(ljmd_system *s) {
     return LJMD_OK;
 }
 
+// The list build addresses rounds of 8 x lanes entries with a 32-bit stride.
+bool lanes_fit(int npad, int lshift) { return ((uint64_t)npad << (3 + lshift)) <= 0xFFFFFFFFull; }
+
 int ensure_list_alloc(ljmd_system *s, int cap) {
+    if (!lanes_fit(s->npad, s->lshift))
+        return set_err(LJMD_E_INVAL, "%d lanes per particle is too many for %d particles",
+                       1 << s->lshift, s->n);
     // a multiple of 8 x lanes per particle (whole chunks of 8 entries per lane) keeps every
     // slot of k < cap inside cap * npad
     const int unit = 8 << s->lshift;
@@ -454,6 +460,9 @@ int tune(ljmd_system *s) {
     int bt = 4, bb = 128;
     for (int t : tpps) {
         if (want_tpp && t != want_tpp) continue;
+        int ls = 0;
+        while ((1 << ls) < t) ++ls;
+        if (!lanes_fit(s->npad, ls)) continue;
         s->tpp = t;
         for (s->lshift = 0; (1 << s->lshift) < t; ++s->lshift) {}
         s->block = 256;

@@ -71,6 +71,18 @@ def test_fp64_list_and_forces(ljmd_mod, oracle_mod, n, seed):
     _pair(o, g)
 
 
+@pytest.mark.parametrize("n,rho", [(10000, 1.0), (8000, 1.0), (16000, 1.4)])
+def test_dense_fluids_smaller_bricks(ljmd_mod, oracle_mod, n, rho):
+    # 29, 37 and 47 atoms per cell: a 2 x 2 x 2 brick's 64-cell halo would not fit the LDS
+    # tile, so bricks shrink to 2 x 2 x 1, 2 x 1 x 1 and single cells (48, 36, 27 halo cells)
+    print_case(f"fp64 dense fluid n={n} rho={rho}")
+    s = gen.make_lj_fluid(n, rho=rho, T=1.0, seed=21)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s)
+    _list_parity(o, g, s.pos)
+    _pair(o, g)
+
+
 def test_small_box_fewer_than_three_cells(ljmd_mod, oracle_mod):
     # L = 6.58 < 3 (r_cut + skin): two cells per axis, the stencil repeats cells
     print_case("fp64 small box 2 cells per axis")
