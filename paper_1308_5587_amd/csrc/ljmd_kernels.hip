@@ -938,8 +938,8 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
         const int lx = (pk & 1023) - (fpk & 1023);
         const int ly = ((pk >> 10) & 1023) - ((fpk >> 10) & 1023);
         const int lz = ((pk >> 20) & 1023) - ((fpk >> 20) & 1023);
-        const int beg = a.cell_start[rank];
-        const int cnt = a.cell_start[rank + 1] - beg;
+        const int beg = __builtin_amdgcn_readfirstlane(a.cell_start[rank]);
+        const int cnt = __builtin_amdgcn_readfirstlane(a.cell_start[rank + 1]) - beg;
         if (cnt == 0) continue;
         int Ln = 64 / cnt;
         Ln = Ln < 1 ? 1 : (Ln > 32 ? 32 : Ln);
@@ -959,10 +959,12 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                 const int h = P.canonical
                                   ? s
                                   : ((lx + s / 9) * hy + (ly + (s / 3) % 3)) * hz + (lz + s % 3);
-                const int o = t.off[h];
-                const int m = t.off[h + 1] - o;
-                const int jst = t.start[h];
-                const int code = t.shift[h];
+                // the stencil cell is the same for every lane of the wavefront: keep its
+                // bounds in scalar registers (uniform loop control, no per-lane masks)
+                const int o = __builtin_amdgcn_readfirstlane(t.off[h]);
+                const int m = __builtin_amdgcn_readfirstlane(t.off[h + 1]) - o;
+                const int jst = __builtin_amdgcn_readfirstlane(t.start[h]);
+                const int code = __builtin_amdgcn_readfirstlane(t.shift[h]);
                 if (Ln == 1)
                     nlist_scan_dispatch<MULTI, STAGED, true>(a, st, s_rl2, P, o, m, jst, code, xi,
                                                              ti, q, active, Ln, lane, gmask, count);
