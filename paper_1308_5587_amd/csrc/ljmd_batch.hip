@@ -129,7 +129,7 @@ struct ljmd_batch {
     int p_ext = 0, c_ext = 0, b_ext = 0;
     int cap = 0, cap_assumed = 128;
     int tpp = 0, lshift = 0, block = 0, tile_cap = 64, max_ntypes = 1;
-    bool layout_fixed = false;  // tpp chosen (fixed once the first replica is admitted)
+    bool layout_fixed = false;  // lanes and workgroup size final (after the first block)
     int block_steps = 100;
     int cur = 0;
     int64_t used_bytes = 0;
@@ -212,7 +212,7 @@ int describe(const ljmd_batch *b, const ljmd_replica_spec *sp, PairTable *pt, Re
         }
     make_pair_table(nt, sp->eps, sp->sigma, sp->r_cut, b->cfg.skin, pt);
     return make_grid(sp->box, pt->rl_max, g, sp->n,
-                     choose_tile_cap(1e9, HALO_MAX, std::max(b->max_ntypes, sp->ntypes), b->lds_limit));
+                     tile_limit_for(std::max(b->max_ntypes, sp->ntypes), b->lds_limit));
 }
 
 // list entries a replica is expected to need: neighbours within the largest list radius at
@@ -450,20 +450,16 @@ void set_tpp(ljmd_batch *b, int t) {
     for (b->lshift = 0; (1 << b->lshift) < t; ++b->lshift) {}
 }
 
-// Lanes per particle and workgroup size, timed on the first replica (d_go and d_only
-// select it). Rebuilding at fixed positions reproduces the same order and build
-// positions, so the trials leave no trace in the trajectory.
-int tune(ljmd_batch *b, int s) {
+// Lanes per particle and workgroup size, timed on the force evaluation of the replicas in
+// `which` (d_go and d_only select them). Each lane count needs its own list layout, so the
+// lists of those replicas are rebuilt for every trial and once more for the choice; a rebuild
+// at fixed positions is valid at any time (it only moves the next rebuild).
+int tune(ljmd_batch *b, const std::vector<int> &which) {
     const int want_tpp = b->cfg.threads_per_particle, want_block = b->cfg.block_size;
     const int tpps[] = {1, 2, 4, 8};
     const int blocks[] = {128, 192, 256, 320, 384, 448, 512};
     double best = 1e30;
-    int bt = want_tpp ? want_tpp : 4, bb = want_block ? want_block : 256;
-    if (want_tpp && want_block) {
-        set_tpp(b, bt);
-        b->block = bb;
-        return LJMD_OK;
-    }
+    int bt = want_tpp ? want_tpp : 2, bb = want_block ? want_block : 256;
     for (int t : tpps) {
         if (want_tpp && t != want_tpp) continue;
         int ls = 0;
@@ -471,7 +467,7 @@ int tune(ljmd_batch *b, int s) {
         if (((uint64_t)b->npad << (3 + ls)) > 0xFFFFFFFFull) continue;
         set_tpp(b, t);
         CHK(grow_list(b, b->cap));
-        CHK(forced_rebuild(b, {s}));
+        CHK(forced_rebuild(b, which));
         for (int k : blocks) {
             if (want_block && k != want_block) continue;
             b->block = k;
@@ -485,7 +481,10 @@ int tune(ljmd_batch *b, int s) {
     }
     set_tpp(b, bt);
     b->block = bb;
-    return grow_list(b, b->cap);
+    CHK(grow_list(b, b->cap));
+    CHK(forced_rebuild(b, which));
+    drop_graph(b);
+    return LJMD_OK;
 }
 
 int release_slot(ljmd_batch *b, int s) {
@@ -881,18 +880,12 @@ int ljmd_batch_admit(ljmd_batch *b, const ljmd_replica_spec *sp, int32_t *slot_o
     rc = set_single_mask(b, b->d_go, s);
     if (rc == LJMD_OK) rc = set_single_mask(b, b->d_only, s);
     if (rc != LJMD_OK) return undo(rc);
-    if (!b->layout_fixed) {
-        if (!b->tpp) set_tpp(b, 4);
-        if (!b->block) b->block = 256;
-        rc = grow_list(b, b->cfg.nlist_capacity > 0 ? b->cfg.nlist_capacity : expected_cap(sp, pt.rl_max));
-        if (rc == LJMD_OK) rc = forced_rebuild(b, {s});
-        if (rc == LJMD_OK && (!b->cfg.threads_per_particle || !b->cfg.block_size)) rc = tune(b, s);
-        if (rc != LJMD_OK) return undo(rc);
-        b->layout_fixed = true;
-    } else {
-        rc = grow_list(b, b->cfg.nlist_capacity > 0 ? b->cfg.nlist_capacity : expected_cap(sp, pt.rl_max));
-        if (rc != LJMD_OK) return undo(rc);
-    }
+    // until the first block tunes them, lanes and workgroup size take the given values or
+    // defaults (2, 256)
+    if (!b->tpp) set_tpp(b, 2);
+    if (!b->block) b->block = 256;
+    rc = grow_list(b, b->cfg.nlist_capacity > 0 ? b->cfg.nlist_capacity : expected_cap(sp, pt.rl_max));
+    if (rc != LJMD_OK) return undo(rc);
     rc = forced_rebuild(b, {s});
     if (rc != LJMD_OK) return undo(rc);
 
@@ -962,6 +955,18 @@ int ljmd_batch_run_block(ljmd_batch *b) {
     for (int s = 0; s < b->max_slots; ++s)
         if (b->slots[s].used && !b->slots[s].done) running.push_back(s);
     if (running.empty()) return LJMD_OK;
+    if (!b->layout_fixed) {
+        // the first block: tune lanes and workgroup size on the replicas present
+        if (!b->cfg.threads_per_particle || !b->cfg.block_size) {
+            std::fill(b->h_mask.begin(), b->h_mask.end(), 0);
+            for (int s : running) b->h_mask[s] = 1;
+            CHK(upload_mask(b, b->d_go, b->h_mask));
+            CHK(upload_mask(b, b->d_only, b->h_mask));
+            CHK(tune(b, running));
+            HIPCHK(hipMemsetAsync(b->d_req, 0, 2 * sizeof(int) * b->max_slots, b->stream));
+        }
+        b->layout_fixed = true;
+    }
     CHK(snapshot_all(b));
     CHK(clear_status(b));
     CHK(ensure_graph(b));

@@ -154,12 +154,12 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g, int64_t n_atoms,
     int ext[3], nb[3];
     for (int a = 0; a < 3; ++a) ext[a] = (!canonical && nc[a] >= 4) ? 2 : 1;
     if (n_atoms > 0 && tile_limit > 0) {
-        // while the halo would not fit the LDS tile at this density (with room for
-        // fluctuations), halve the brick along z, then y, then x: 64 halo cells, 48, 36, 27
+        // while the tile capacity this density asks for (choose_tile_cap's headroom) would
+        // exceed the limit, halve the brick along z, then y, then x: 64 halo cells, 48, 36, 27
         const double per_cell = (double)n_atoms / ncell;
         for (int a = 2; a >= 0; --a) {
             const int halo = (ext[0] + 2) * (ext[1] + 2) * (ext[2] + 2);
-            if (1.2 * halo * per_cell + 64.0 <= tile_limit) break;
+            if (1.05 * halo * per_cell + 128.0 <= tile_limit) break;
             ext[a] = 1;
         }
     }
@@ -248,6 +248,10 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g, int64_t n_atoms,
     g->nbrick = nbrick;
     g->max_halo = max_halo;
     return LJMD_OK;
+}
+
+int tile_limit_for(int max_ntypes, size_t lds_limit) {
+    return std::min(TILE_TARGET, choose_tile_cap(1e9, HALO_MAX, max_ntypes, lds_limit));
 }
 
 int choose_tile_cap(double atoms_per_cell, int max_halo, int max_ntypes, size_t lds_limit) {

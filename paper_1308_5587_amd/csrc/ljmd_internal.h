@@ -81,6 +81,9 @@ struct HaloCell {
 };
 constexpr int HALO_MAX = 64;
 constexpr int TILE_MAX = 2560;        // tile atoms staged in LDS at most (32 B each: 80 KiB)
+// Tile capacity bricks are shaped for: 1536 atoms (48 KiB) plus the build's 3.9 KiB of static
+// LDS lets three 512-thread workgroups share a CU's 160 KiB.
+constexpr int TILE_TARGET = 1536;
 constexpr int LJMD_MAX_TYPES_DEVICE = 16;     // type count the kernels' tables allow
 constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr int TILE_INDEX_MAX = 65535; // 16-bit tile indices

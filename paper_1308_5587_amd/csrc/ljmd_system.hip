@@ -144,7 +144,7 @@ int setup_table(ljmd_system *s) {
     PairTable pt;
     make_pair_table(nt, s->eps.data(), s->sig.data(), s->rc.data(), s->cfg.skin, &pt);
     ReplicaGrid g;
-    CHK(make_grid(s->L, pt.rl_max, &g, s->n, choose_tile_cap(1e9, HALO_MAX, nt, s->lds_limit)));
+    CHK(make_grid(s->L, pt.rl_max, &g, s->n, tile_limit_for(nt, s->lds_limit)));
     const int ncell = g.ncell;
     if (ncell + 1 > s->ncell_alloc) {
         dfree(s, s->d_cell_rank);
