@@ -828,7 +828,7 @@ int ljmd_batch_admit(ljmd_batch *b, const ljmd_replica_spec *sp, int32_t *slot_o
     const int old_ntypes = b->max_ntypes;
     b->max_ntypes = std::max(b->max_ntypes, nt);
     const int tc_limit = choose_tile_cap(1e9, HALO_MAX, b->max_ntypes, b->lds_limit);
-    const int tc = choose_tile_cap((double)n / g.ncell, g.max_halo, b->max_ntypes, b->lds_limit);
+    const int tc = grid_tile_cap(g, n, b->max_ntypes, b->lds_limit);
     const int new_tc = std::min(std::max(b->tile_cap, tc), tc_limit);
     if (new_tc != b->tile_cap || old_ntypes != b->max_ntypes) drop_graph(b);
     b->tile_cap = new_tc;

@@ -77,6 +77,9 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g, int64_t n_atoms 
 // Tile capacity (atoms staged in LDS) for a mean occupancy of atoms_per_cell.
 int choose_tile_cap(double atoms_per_cell, int max_halo, int max_ntypes, size_t lds_limit);
 
+// Tile capacity for a replica's grid: exact when every halo is the whole box.
+int grid_tile_cap(const ReplicaGrid &g, int64_t n_atoms, int max_ntypes, size_t lds_limit);
+
 // The tile capacity bricks are shaped for: what fits the LDS, and at most TILE_TARGET.
 int tile_limit_for(int max_ntypes, size_t lds_limit);
 

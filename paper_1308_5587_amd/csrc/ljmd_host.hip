@@ -250,6 +250,15 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g, int64_t n_atoms,
     return LJMD_OK;
 }
 
+int grid_tile_cap(const ReplicaGrid &g, int64_t n_atoms, int max_ntypes, size_t lds_limit) {
+    if (g.max_halo < g.ncell)
+        return choose_tile_cap((double)n_atoms / g.ncell, g.max_halo, max_ntypes, lds_limit);
+    // every halo is the whole box: the tile holds exactly n atoms, no headroom needed
+    const int lds_cap = choose_tile_cap(1e9, HALO_MAX, max_ntypes, lds_limit);
+    const int64_t want = std::max<int64_t>(64, (n_atoms + 63) & ~63LL);
+    return (int)std::min<int64_t>(want, lds_cap);
+}
+
 int tile_limit_for(int max_ntypes, size_t lds_limit) {
     return std::min(TILE_TARGET, choose_tile_cap(1e9, HALO_MAX, max_ntypes, lds_limit));
 }

@@ -213,7 +213,7 @@ int setup_table(ljmd_system *s) {
     s->rl_max = pt.rl_max;
     s->ncell = ncell;
     s->nbrick = g.nbrick;
-    s->tile_cap = choose_tile_cap((double)s->n / ncell, g.max_halo, nt, s->lds_limit);
+    s->tile_cap = grid_tile_cap(g, s->n, nt, s->lds_limit);
     s->table_dirty = false;
     s->list_valid = false;
     s->force_valid = false;
