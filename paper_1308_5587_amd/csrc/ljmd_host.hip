@@ -100,7 +100,7 @@ static uint64_t spread3(uint64_t v) {  // 10-bit value -> every third bit
 // the whole box (its distinct cells) and the list build scans all of them with the branch-form
 // minimum image. The bricks are the z-layers of cells: a few workgroups per replica, each
 // with a share of the atoms comparable to a 2 x 2 x 2 brick of a large box.
-static int make_small_box_grid(const int nc[3], ReplicaGrid *g) {
+static int make_small_box_grid(const int nc[3], const double L[3], ReplicaGrid *g) {
     const int ncell = nc[0] * nc[1] * nc[2];
     const int per = nc[0] * nc[1];
     const int nbrick = nc[2];
@@ -120,8 +120,11 @@ static int make_small_box_grid(const int nc[3], ReplicaGrid *g) {
         bi.first_cell = b * per;
         bi.ncell = per;
         bi.nhalo = ncell;
-        bi.dims = 0;  // the stencil-walk fields are unused here; no wrap-free axis
+        // the stencil-walk fields are unused here. x and y span the box, so only z can be
+        // centred (three or more layers); the brick is one layer thick (extent field ez)
+        bi.dims = (1 << 20) | (nc[2] >= 3 ? 1 << (CENTER_SHIFT + 2) : 0);
         bi.rep = 0;
+        bi.centre[2] = (b + 0.5) * L[2] / nc[2];
         for (int r = 0; r < ncell; ++r) g->halo[(size_t)b * HALO_MAX + r] = HaloCell{r, 21};
     }
     for (int a = 0; a < 3; ++a) g->nc[a] = nc[a];
@@ -146,7 +149,7 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g, int64_t n_atoms,
         nc[a] = (int)v;
     }
     const int ncell = nc[0] * nc[1] * nc[2];
-    if (ncell <= 27) return make_small_box_grid(nc, g);
+    if (ncell <= 27) return make_small_box_grid(nc, L, g);
     // Bricks of up to 2 x 2 x 2 cells (one cell wide on an axis with fewer than 4 cells,
     // single cells when some axis has fewer than 3), bricks in Morton order, cells in Morton
     // order inside their brick: every brick is a contiguous range of cells.
@@ -216,7 +219,10 @@ int make_grid(const double L[3], double rl_max, ReplicaGrid *g, int64_t n_atoms,
             const int lo = brick_lo[3 * bo + a], hi = lo + brick_n[3 * bo + a];
             if (!canonical && nc[a] >= 10 && lo - 1 >= 1 && hi <= nc[a] - 2)
                 bi.dims |= 1 << (MI_FREE_SHIFT + a);
+            if (nc[a] >= brick_n[3 * bo + a] + 2) bi.dims |= 1 << (CENTER_SHIFT + a);
+            bi.centre[a] = (lo + 0.5 * brick_n[3 * bo + a]) * L[a] / nc[a];
         }
+
         int nh = 0;
         for (int hx = 0; hx < hd[0]; ++hx)
             for (int hy = 0; hy < hd[1]; ++hy)

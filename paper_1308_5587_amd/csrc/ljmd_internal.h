@@ -60,9 +60,11 @@ struct BrickInfo {
     int ncell;       // cells in the brick (1..8)
     int nhalo;       // halo cells (<= HALO_MAX)
     int dims;        // halo extents hx | hy << 4 | hz << 8, brick extents ex << 12 | ey << 16 | ez << 20,
-                     // bit 24 + a: axis a needs no minimum image (see MI_FREE)
+                     // bit 24 + a: axis a needs no minimum image (see MI_FREE),
+                     // bit 27 + a: axis a is centred while staging (see CENTER)
     int rep;         // replica, -1 for an unused brick
-    int pad[3];
+    int pad;
+    double centre[3];  // the brick's centre (box units), read on the centred axes
 };
 // Bit 24 + a of BrickInfo::dims is set when, on axis a, the brick's halo lies in cells
 // 1 .. n_cell - 2 and n_cell >= 10. Between builds no particle moves more than skin/2 <
@@ -70,6 +72,15 @@ struct BrickInfo {
 // 4 cells + skin < L/2 on that axis: the plain difference x_j - x_i already is the minimum
 // image, bit for bit.
 constexpr int MI_FREE_SHIFT = 24;
+// Bit 27 + a of BrickInfo::dims is set when the axis holds at least (brick cells + 2) cells.
+// Let c be the brick's centre on that axis and w >= r_cut + skin the cell width. A brick
+// particle lies within (brick cells) w / 2 + skin / 2 of c, so a partner closer than r_cut
+// lies, in its nearest image, within (brick cells) w / 2 + w - skin / 2 < L / 2 of c. Moving
+// every staged atom and the brick's own particles to their image nearest c,
+// x - L rint((x - c) / L), therefore puts every pair that can interact at its minimum image,
+// and the pair loop takes the plain difference on that axis. Any other pair is at least
+// r_cut apart in every image and stays beyond the cutoff.
+constexpr int CENTER_SHIFT = 27;
 // Per-brick tile table written by the list build: offsets off[0..64], starts start[0..63],
 // halo count.
 constexpr int TILE_TAB = 2 * 64 + 2;

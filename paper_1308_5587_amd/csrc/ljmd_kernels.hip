@@ -54,6 +54,13 @@ __device__ __forceinline__ double rcp64(double x) {
     return __builtin_fma(y, e, y);
 }
 
+// The image of coordinate x nearest c: x - L rint((x - c) / L), rounded once; x itself when
+// it already is that image.
+__device__ __forceinline__ double near_image(double x, double c, double L, double invL) {
+    const double k = __builtin_rint((x - c) * invL);
+    return __builtin_fma(-k, L, x);
+}
+
 // Workgroup b of nb is dispatched to XCD (b mod 8). Map each XCD to a contiguous range
 // of logical tiles so that spatial neighbours share an L2.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
@@ -144,9 +151,42 @@ __device__ __forceinline__ int tile_global(const TileSmem &t, int k) {
     return t.start[h] + (k - t.off[h]);
 }
 
+// Brick centre and the axes to centre while staging (CENTER bits not already wrap-free).
+struct Centre {
+    double c[3];
+    int mask;
+};
+
+__device__ __forceinline__ Centre brick_centre(const BrickInfo &bi) {
+    Centre ce;
+    ce.mask = ((bi.dims >> CENTER_SHIFT) & 7) & ~((bi.dims >> MI_FREE_SHIFT) & 7);
+    for (int a = 0; a < 3; ++a) ce.c[a] = bi.centre[a];
+    return ce;
+}
+
+__device__ __forceinline__ double4 centred(double4 p, const Centre &ce, const RepParams &P) {
+    if (ce.mask & 1) p.x = near_image(p.x, ce.c[0], P.L[0], P.invL[0]);
+    if (ce.mask & 2) p.y = near_image(p.y, ce.c[1], P.L[1], P.invL[1]);
+    if (ce.mask & 4) p.z = near_image(p.z, ce.c[2], P.L[2], P.invL[2]);
+    return p;
+}
+
+// The same with the axes fixed at compile time (CM = the centring mask).
+template <int CM>
+__device__ __forceinline__ double4 centred_t(double4 p, const Centre &ce, const RepParams &P) {
+    if (CM & 1) p.x = near_image(p.x, ce.c[0], P.L[0], P.invL[0]);
+    if (CM & 2) p.y = near_image(p.y, ce.c[1], P.L[1], P.invL[1]);
+    if (CM & 4) p.z = near_image(p.z, ce.c[2], P.L[2], P.invL[2]);
+    return p;
+}
+
 // Copy the tile's atoms (x, y, z, type) into LDS as double4 records: blockDim / 64
-// consecutive threads copy one halo cell's atoms (consecutive in memory).
-__device__ __forceinline__ void tile_stage(const TileSmem &t, const double4 *pos, double4 *st) {
+// consecutive threads copy one halo cell's atoms (consecutive in memory). The coordinates
+// on the axes in CM are moved to their image nearest the brick centre.
+template <int CM = 0>
+__device__ __forceinline__ void tile_stage(const TileSmem &t, const double4 *pos, double4 *st,
+                                           const Centre *ce = nullptr,
+                                           const RepParams *P = nullptr) {
     const int per = blockDim.x >= 64 ? (int)blockDim.x / 64 : 1;
     const int sub = threadIdx.x % per;
     for (int h = threadIdx.x / per; h < t.nhalo; h += (int)blockDim.x / per) {
@@ -157,10 +197,16 @@ __device__ __forceinline__ void tile_stage(const TileSmem &t, const double4 *pos
         // reads its first atom, k0 < m, and is not stored)
         for (int k0 = sub; k0 < m; k0 += 4 * per) {
             const int k1 = k0 + per, k2 = k0 + 2 * per, k3 = k0 + 3 * per;
-            const double4 p0 = src[k0];
-            const double4 p1 = src[k1 < m ? k1 : k0];
-            const double4 p2 = src[k2 < m ? k2 : k0];
-            const double4 p3 = src[k3 < m ? k3 : k0];
+            double4 p0 = src[k0];
+            double4 p1 = src[k1 < m ? k1 : k0];
+            double4 p2 = src[k2 < m ? k2 : k0];
+            double4 p3 = src[k3 < m ? k3 : k0];
+            if (CM) {
+                p0 = centred_t<CM>(p0, *ce, *P);
+                p1 = centred_t<CM>(p1, *ce, *P);
+                p2 = centred_t<CM>(p2, *ce, *P);
+                p3 = centred_t<CM>(p3, *ce, *P);
+            }
             st[o + k0] = p0;
             if (k1 < m) st[o + k1] = p1;
             if (k2 < m) st[o + k2] = p2;
@@ -373,8 +419,8 @@ template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI, bool STAGED, int
 __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem &t,
                                              const double4 *__restrict__ st,
                                              const PairCoef *s_pair, const PairCoef &single,
-                                             const RepParams &P, int rep, bool last, int first,
-                                             int natoms) {
+                                             const RepParams &P, const Centre &ce, int rep,
+                                             bool last, int first, int natoms) {
     const int per_pass = blockDim.x / TPP;
     const int g = threadIdx.x / TPP;
     const int lane = threadIdx.x & (TPP - 1);
@@ -388,6 +434,8 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
         const bool active = p < natoms;
         const int q = first + (active ? (int)a.work[first + p] : 0);
         const double4 xi = a.pos_in[q];
+        // the tile is centred on the brick: so is the particle in the pair loop
+        const double4 xc = centred(xi, ce, P);
         const int ti = MULTI ? (int)xi.w : 0;
         int cnt = active ? a.nl_count[q] : 0;
         cnt = cnt < a.cap ? cnt : a.cap;
@@ -428,7 +476,8 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                         pz[v] = pj.z;
                         if (MULTI) pt[v] = (int)pj.w;
                     } else {
-                        const double4 pj = a.pos_in[tile_global(t, idx)];
+                        // centred as staging would have: the same bits as the staged path
+                        const double4 pj = centred(a.pos_in[tile_global(t, idx)], ce, P);
                         px[v] = pj.x;
                         py[v] = pj.y;
                         pz[v] = pj.z;
@@ -437,9 +486,9 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                 }
 #pragma unroll
                 for (int v = 0; v < FORCE_BATCH; ++v) {
-                    const double dx = (MIF & 1) ? px[v] - xi.x : mi_rint(px[v] - xi.x, L0, iL0);
-                    const double dy = (MIF & 2) ? py[v] - xi.y : mi_rint(py[v] - xi.y, L1, iL1);
-                    const double dz = (MIF & 4) ? pz[v] - xi.z : mi_rint(pz[v] - xi.z, L2, iL2);
+                    const double dx = (MIF & 1) ? px[v] - xc.x : mi_rint(px[v] - xc.x, L0, iL0);
+                    const double dy = (MIF & 2) ? py[v] - xc.y : mi_rint(py[v] - xc.y, L1, iL1);
+                    const double dz = (MIF & 4) ? pz[v] - xc.z : mi_rint(pz[v] - xc.z, L2, iL2);
                     const double r2 = r2_canon(dx, dy, dz);
                     const PairCoef &c = MULTI ? s_pair[ti * P.ntypes + pt[v]] : single;
                     if (pv[v] && r2 < c.rc2)
@@ -532,14 +581,20 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
     }
 }
 
-// One workgroup per brick. The brick's tile (the atoms of its halo cells, FP64 structure of
-// arrays) is staged in LDS; TPP lanes per particle of the brick stride through the
-// particle's list of 16-bit tile indices, 8 per 16-byte load, gathering neighbour
-// positions from LDS. Forces are reduced across the lanes with wavefront shuffles; lane 0
-// then finishes the particle according to MODE. If a tile is larger than the LDS
-// allocation, the positions are read from global memory through the tile offsets instead.
+// One workgroup per brick. The brick's tile (the atoms of its halo cells, double4 records,
+// moved to their image nearest the brick centre on the centred axes) is staged in LDS; TPP
+// lanes per particle of the brick stride through the particle's list of 16-bit tile
+// indices, 8 per 16-byte load, gathering neighbour positions from LDS. Forces are reduced
+// across the lanes with wavefront shuffles; lane 0 then finishes the particle according to
+// MODE. If a tile is larger than the LDS allocation, the positions are read from global
+// memory through the tile offsets instead, with the minimum image on every axis.
+// Occupancy: a 48 KiB tile lets three 512-thread workgroups share a CU, which needs at most
+// 80 VGPRs (6 waves per SIMD); the single-type variants without energy fit that without
+// spilling and are held to it, the others keep their natural register count.
 template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI>
-__global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
+__global__ void __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu((ENERGY || MULTI || TPP >= 8) ? 1 : 6)))
+k_force(const ForceArgs a) {
     extern __shared__ double4 dyn_tile[];
     __shared__ TileSmem t;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
@@ -572,14 +627,28 @@ __global__ void __launch_bounds__(512) k_force(const ForceArgs a) {
     const PairCoef single = a.pair[P.pair_off];
     tile_load(a.tile_tab + (size_t)b * TILE_TAB, t);
     const bool staged = t.total <= a.tile_cap;
-    if (staged) tile_stage(t, a.pos_in, st);
+    const Centre ce = brick_centre(bi);
+    if (staged) {
+        switch (ce.mask) {
+            case 1: tile_stage<1>(t, a.pos_in, st, &ce, &P); break;
+            case 2: tile_stage<2>(t, a.pos_in, st, &ce, &P); break;
+            case 3: tile_stage<3>(t, a.pos_in, st, &ce, &P); break;
+            case 4: tile_stage<4>(t, a.pos_in, st, &ce, &P); break;
+            case 5: tile_stage<5>(t, a.pos_in, st, &ce, &P); break;
+            case 6: tile_stage<6>(t, a.pos_in, st, &ce, &P); break;
+            case 7: tile_stage<7>(t, a.pos_in, st, &ce, &P); break;
+            default: tile_stage(t, a.pos_in, st); break;
+        }
+    }
     const bool last = MODE == MODE_FUSED && r_in == 1;
-    const int mif = (bi.dims >> MI_FREE_SHIFT) & 7;
+    // axes on which the pair loop takes the plain difference: wrap-free or centred (the
+    // variants that still take the minimum image there get k = 0 and the same bits)
+    const int mif = ((bi.dims >> MI_FREE_SHIFT) | (bi.dims >> CENTER_SHIFT)) & 7;
 #define LJMD_PASSES(M) \
-    force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, M>(a, t, st, s_pair, single, P, rep, last, first, natoms)
+    force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, M>(a, t, st, s_pair, single, P, ce, rep, last, first, natoms)
     if (!staged) {
         force_passes<PREC, TPP, MODE, ENERGY, MULTI, false, 0>(
-            a, t, st, s_pair, single, P, rep, last, first, natoms);
+            a, t, st, s_pair, single, P, ce, rep, last, first, natoms);
     } else if (MODE == MODE_FUSED) {
         // the step kernel: a variant per set of wrap-free axes
         switch (mif) {

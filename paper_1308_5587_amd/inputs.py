@@ -33,6 +33,7 @@ __all__ = [
     "ka_pair_table",
     "lj_single_pair_table",
     "make_replica_specs",
+    "make_lj_droplet",
     "make_arrivals",
     "cube_side",
 ]
@@ -134,6 +135,46 @@ def make_lj_fluid(
         pairs=lj_single_pair_table(r_cut),
         seed=seed,
         name=f"lj_fluid_N{n}_rho{rho}",
+    )
+
+
+def make_lj_droplet(
+    L: float = 24.0,
+    cube: float = 9.0,
+    a_dense: float = 0.97,
+    a_dilute: float = 1.6,
+    T: float = 1.0,
+    seed: int = 1,
+    jitter: float = 0.05,
+) -> LJSystemSpec:
+    """Inhomogeneous single-type LJ system: a dense simple-cubic block (spacing ``a_dense``)
+    filling the cube [0, cube)^3 of a periodic box of edge ``L``, and a dilute simple-cubic
+    vapour (spacing ``a_dilute``, sites at (i + 1/2) a_dilute) everywhere at least a_dilute / 2
+    outside that cube, periodically. Cells inside the block hold several times the box's
+    mean count, so their bricks' tiles exceed a tile capacity sized for the mean."""
+    rng = np.random.default_rng(seed)
+    k = int(math.floor(cube / a_dense))
+    g = (np.arange(k) + 0.5) * a_dense
+    dense = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    m = int(round(L / a_dilute))
+    h = (np.arange(m) + 0.5) * (L / m)
+    vap = np.stack(np.meshgrid(h, h, h, indexing="ij"), -1).reshape(-1, 3)
+    gap = 0.5 * a_dilute
+    inside = np.all((vap < cube + gap) | (vap >= L - gap), axis=1)
+    pos = np.concatenate([dense, vap[~inside]])
+    pos += rng.uniform(-jitter, jitter, size=pos.shape)
+    pos %= L
+    n = pos.shape[0]
+    vel = _mb_velocities(rng, n, T)
+    return LJSystemSpec(
+        box=np.array([L, L, L], dtype=np.float64),
+        pos=np.ascontiguousarray(pos),
+        vel=np.ascontiguousarray(vel),
+        type=np.zeros(n, dtype=np.int32),
+        ntypes=1,
+        pairs=lj_single_pair_table(),
+        seed=seed,
+        name=f"lj_droplet_L{L}",
     )
 
 

@@ -82,6 +82,22 @@ def test_batch_equals_alone_bitwise(ljmd_mod, precision):
     b.close()
 
 
+def test_staged_in_batch_equals_unstaged_alone(ljmd_mod):
+    # alone, the droplet's tile capacity is sized for its mean cell count and the bricks
+    # around its dense block read neighbours from global memory; beside a dense fluid the
+    # batch's capacity holds those tiles in LDS. Both paths must give the same bits.
+    print_case("droplet beside a dense fluid: staged in the batch, unstaged alone")
+    mix = [(gen.make_lj_droplet(seed=6), 30), (gen.make_lj_fluid(4000, seed=7), 30)]
+    b = ljmd_mod.Batch(256 << 20, 2, precision="fp64", block_steps=16,
+                       threads_per_particle=TPP, block_size=BLOCK)
+    slots = [b.admit(spec, n) for spec, n in mix]
+    _run_until_done(b, slots)
+    assert b.stats()["tile_capacity"] >= 1024
+    for (spec, n), s in zip(mix, slots):
+        _same(b.read(s), _alone(ljmd_mod, spec, n, "fp64"))
+    b.close()
+
+
 def test_admission_while_running(ljmd_mod):
     print_case("continuous admission: replicas join a running batch")
     mix = _mix()

@@ -83,6 +83,25 @@ def test_dense_fluids_smaller_bricks(ljmd_mod, oracle_mod, n, rho):
     _pair(o, g)
 
 
+def test_droplet_tiles_beyond_capacity(ljmd_mod, oracle_mod):
+    # a dense block in a dilute vapour: the tile capacity is sized for the mean cell count
+    # (about 7 atoms), so the bricks around the block (tiles of up to about 900 atoms) read
+    # their neighbours from global memory in the list build and in the force kernels
+    print_case("fp64 droplet: tiles beyond the LDS capacity")
+    s = gen.make_lj_droplet(seed=5)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s)
+    _list_parity(o, g, s.pos)
+    _pair(o, g)
+    o.step(40)
+    g.step(40)
+    po, vo, io, _ = o.state()
+    pg, vg, ig, _ = g.state()
+    assert np.abs(unwrapped(pg, ig, s.box) - unwrapped(po, io, s.box)).max() < 1e-9
+    assert np.abs(vg - vo).max() < 1e-9
+    assert max_norm_rel(g.forces(), o.forces()) < 1e-9
+
+
 def test_small_box_fewer_than_three_cells(ljmd_mod, oracle_mod):
     # L = 6.58 < 3 (r_cut + skin): two cells per axis, the stencil repeats cells
     print_case("fp64 small box 2 cells per axis")
@@ -165,6 +184,41 @@ def test_one_and_hundred_steps(ljmd_mod, oracle_mod):
     assert np.abs(vg - vo).max() < 1e-8
     assert max_norm_rel(g.forces(), o.forces()) < 1e-8
     assert g.stats()["rebuilds"] >= 5
+
+
+@pytest.mark.parametrize("n,rho,box", [
+    (1000, 0.75, None),                    # 3 cells per axis: z-layer bricks, whole-box halos
+    (1320, None, (9.0, 12.5, 17.25)),      # 3, 4 and 5 cells: bricks one and two cells wide
+    (1850, 0.8442, None),                  # 4 cells per axis: 2 x 1 x 1 bricks, halos span x
+])
+def test_hundred_steps_small_boxes(ljmd_mod, oracle_mod, n, rho, box):
+    # small boxes: every brick's halo touches the periodic boundary, so the force kernel moves
+    # staged atoms to their image nearest the brick centre on the axes where that is exact
+    print_case(f"fp64 100 steps n={n} rho={rho} box={box}")
+    if box is None:
+        s = gen.make_lj_fluid(n, rho=rho, T=1.2, seed=31)
+    else:
+        rng = np.random.default_rng(32)
+        b = np.array(box)
+        side = np.array([8, 11, 15])  # lattice spacing 1.13 to 1.15 on every axis
+        assert side.prod() == n
+        sites = np.stack(np.meshgrid(*[np.arange(k) for k in side], indexing="ij"),
+                         -1).reshape(-1, 3)
+        pos = (sites + 0.5) / side * b + rng.uniform(-0.05, 0.05, (n, 3))
+        s = gen.LJSystemSpec(b, pos, rng.normal(0, 1.1, (n, 3)), np.zeros(n, np.int32), 1,
+                             [(0, 0, 1.0, 1.0, 2.5)])
+    o = oracle_mod.OracleSystem.from_spec(s)
+    g = ljmd_mod.System.from_spec(s)
+    for k in (1, 99):
+        o.step(k)
+        g.step(k)
+        po, vo, io, _ = o.state()
+        pg, vg, ig, _ = g.state()
+        tol = 1e-12 if k == 1 else 1e-8
+        assert np.abs(unwrapped(pg, ig, s.box) - unwrapped(po, io, s.box)).max() < tol
+        assert np.abs(vg - vo).max() < tol
+        assert max_norm_rel(g.forces(), o.forces()) < (1e-10 if k == 1 else 1e-8)
+    assert g.stats()["rebuilds"] >= 3
 
 
 def test_mixed_steps_track_fp64(ljmd_mod, oracle_mod):
