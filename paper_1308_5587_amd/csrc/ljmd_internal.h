@@ -102,6 +102,10 @@ constexpr int TILE_INDEX_MAX = 65535; // 16-bit tile indices
 #define LJMD_FORCE_BATCH 2
 #endif
 constexpr int FORCE_BATCH = LJMD_FORCE_BATCH;  // neighbour positions requested together (1, 2, 4, 8)
+#ifndef LJMD_BUILD_BATCH
+#define LJMD_BUILD_BATCH 2
+#endif
+constexpr int BUILD_BATCH = LJMD_BUILD_BATCH;  // candidate rounds tested together in the build
 
 enum { MODE_EVAL = 0, MODE_FUSED = 1, MODE_FINAL = 2 };
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };

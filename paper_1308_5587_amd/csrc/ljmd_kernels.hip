@@ -901,64 +901,77 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
     // the slot is one 32 x 32 + 64-bit multiply-add
     const uint32_t rstride = (uint32_t)a.npad << sh;
     const uint64_t qbase = (uint64_t)q << sh;
-    for (int t0 = 0; t0 < m; t0 += Ln) {
-        const int tt = t0 + lane;
-        const bool valid = active && tt < m;
-        const int tv = valid ? tt : 0;
-        double xjx, xjy, xjz;
-        int tj = 0;
-        if (STAGED) {
-            const double4 pj = st[o + tv];
-            xjx = pj.x;
-            xjy = pj.y;
-            xjz = pj.z;
-            if (MULTI) tj = (int)pj.w;
-        } else {
-            const double4 pj = a.pos_scr[jst + tv];
-            xjx = pj.x;
-            xjy = pj.y;
-            xjz = pj.z;
-            tj = (int)pj.w;
+    // BUILD_BATCH rounds of Ln candidates per iteration: their positions are read and their
+    // distances tested before any append, so the LDS reads and FP64 chains of the rounds
+    // overlap; the appends then run round by round, in the order of a plain loop
+    for (int t0 = 0; t0 < m; t0 += Ln * BUILD_BATCH) {
+        bool hv[BUILD_BATCH];
+        int ttv[BUILD_BATCH];
+#pragma unroll
+        for (int u = 0; u < BUILD_BATCH; ++u) {
+            const int tt = t0 + u * Ln + lane;
+            const bool valid = active && tt < m;
+            const int tv = valid ? tt : 0;
+            double xjx, xjy, xjz;
+            int tj = 0;
+            if (STAGED) {
+                const double4 pj = st[o + tv];
+                xjx = pj.x;
+                xjy = pj.y;
+                xjz = pj.z;
+                if (MULTI) tj = (int)pj.w;
+            } else {
+                const double4 pj = a.pos_scr[jst + tv];
+                xjx = pj.x;
+                xjy = pj.y;
+                xjz = pj.z;
+                tj = (int)pj.w;
+            }
+            double dx = xjx - xi.x, dy = xjy - xi.y, dz = xjz - xi.z;
+            if (MIK == 2) {
+                dx = mi_branch(dx, P.L[0]);
+                dy = mi_branch(dy, P.L[1]);
+                dz = mi_branch(dz, P.L[2]);
+            } else if (MIK == 1) {
+                dx = dx + shx;  // adding 0.0 on an unshifted axis is exact
+                dy = dy + shy;
+                dz = dz + shz;
+            }
+            const double r2 = r2_canon(dx, dy, dz);
+            const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.single_rl2;
+            hv[u] = valid && (jst + tt) != q && r2 < rl2;
+            ttv[u] = tt;
         }
-        double dx = xjx - xi.x, dy = xjy - xi.y, dz = xjz - xi.z;
-        if (MIK == 2) {
-            dx = mi_branch(dx, P.L[0]);
-            dy = mi_branch(dy, P.L[1]);
-            dz = mi_branch(dz, P.L[2]);
-        } else if (MIK == 1) {
-            dx = dx + shx;  // adding 0.0 on an unshifted axis is exact
-            dy = dy + shy;
-            dz = dz + shz;
-        }
-        const double r2 = r2_canon(dx, dy, dz);
-        const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.single_rl2;
-        const bool hit = valid && (jst + tt) != q && r2 < rl2;
-        if (SOLO) {
-            // one lane per particle: its hits are appended in order, no group prefix needed
-            if (hit) {
-                if (count < a.cap) {
-                    const uint64_t slot = (uint64_t)((uint32_t)count >> sh) * rstride + qbase +
-                                        (size_t)(count & ((1 << sh) - 1));
-                    a.nlist[slot] = (uint16_t)(o + tt);
+#pragma unroll
+        for (int u = 0; u < BUILD_BATCH; ++u) {
+            const bool hit = hv[u];
+            if (SOLO) {
+                // one lane per particle: its hits are appended in order, no group prefix
+                if (hit) {
+                    if (count < a.cap) {
+                        const uint64_t slot = (uint64_t)((uint32_t)count >> sh) * rstride +
+                                              qbase + (size_t)(count & ((1 << sh) - 1));
+                        a.nlist[slot] = (uint16_t)(o + ttv[u]);
+                    }
+                    ++count;
                 }
-                ++count;
+                continue;
             }
-            continue;
-        }
-        const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit) & gmask;
-        if (hit) {
-            // hits of lower lanes of the group: mbcnt counts the set bits of bal below
-            // this lane
-            const int k = count + (int)__builtin_amdgcn_mbcnt_hi(
-                                      (unsigned)(bal >> 32),
-                                      __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-            if (k < a.cap) {
-                const uint64_t slot = (uint64_t)((uint32_t)k >> sh) * rstride + qbase +
-                                    (size_t)(k & ((1 << sh) - 1));
-                a.nlist[slot] = (uint16_t)(o + tt);
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit) & gmask;
+            if (hit) {
+                // hits of lower lanes of the group: mbcnt counts the set bits of bal below
+                // this lane
+                const int k = count + (int)__builtin_amdgcn_mbcnt_hi(
+                                          (unsigned)(bal >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+                if (k < a.cap) {
+                    const uint64_t slot = (uint64_t)((uint32_t)k >> sh) * rstride + qbase +
+                                          (size_t)(k & ((1 << sh) - 1));
+                    a.nlist[slot] = (uint16_t)(o + ttv[u]);
+                }
             }
+            count += __popcll(bal);
         }
-        count += __popcll(bal);
     }
 }
 
