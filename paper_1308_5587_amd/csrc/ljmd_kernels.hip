@@ -597,7 +597,11 @@ __attribute__((amdgpu_waves_per_eu((ENERGY || MULTI || TPP >= 8) ? 1 : 6)))
 k_force(const ForceArgs a) {
     extern __shared__ double4 dyn_tile[];
     __shared__ TileSmem t;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    // one system: XCD-contiguous brick ranges share halos in L2. A batch (the only caller
+    // with per-replica status words) launches a grid rounded up past its live bricks, so
+    // contiguous ranges would leave the XCDs of the tail idle: consecutive bricks go to
+    // different XCDs there (the dispatcher's round robin)
+    const int b = a.rep_status ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
     const BrickInfo bi = a.bricks[b];
     const int rep = bi.rep;
     if (rep < 0) return;
@@ -1129,7 +1133,11 @@ __device__ __forceinline__ void work_order(const RebuildArgs &a, int first, int 
 template <bool MULTI>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
 k_nlist(const RebuildArgs a) {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    // one system: every brick builds, and XCD-contiguous brick ranges share halos in L2. A
+    // batch: only the bricks of replicas that asked for a build do work, and each replica's
+    // bricks are contiguous, so consecutive bricks go to different XCDs instead (the
+    // dispatcher's round robin) to spread the builders of one step over the whole chip
+    const int b = a.nrep > 1 ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
     const BrickInfo bi = a.bricks[b];
     if (!rebuilds(a, bi.rep)) return;
     const RepParams &P = a.reps[bi.rep];
