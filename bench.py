@@ -20,11 +20,13 @@ Also reported on that line:
   served        Poisson request streams (N log-uniform in [512, 65536], density 0.8442,
                 T 1.2, 1000-10000 steps) through the continuous-batching loop: p50/p99
                 latency and atom-steps/s, beside the same stream served one request at a
-                time on the plain FP64 path.
+                time on the plain FP64 path. Arrival rates are fractions (--serve-loads) of
+                the capacity mu = batched atom-steps/s / E[N * steps].
   cpu_baseline  the CPU FP64 oracle on a bounded sample of the same workload, on this host.
 """
 
 import argparse
+import math
 import json
 import os
 import sys
@@ -234,18 +236,25 @@ def run_batched(count, block_steps, blocks, sample):
             "speedup_vs_one_by_one_fp64": value / alone}
 
 
-def run_served(rates, count, block_steps):
+def served_mean_work():
+    """E[N x steps] of the request stream (N log-uniform on [512, 65536], steps uniform on
+    [1000, 10000], drawn independently)."""
+    n_lo, n_hi, s_lo, s_hi = 512, 65536, 1000, 10000
+    return (n_hi - n_lo) / math.log(n_hi / n_lo) * 0.5 * (s_lo + s_hi)
+
+
+def run_served(rates, count, block_steps, loads=None):
     from paper_1308_5587_amd import inputs, ljmd, serve
 
     out = []
-    for rate in rates:
+    for k, rate in enumerate(rates):
         arrivals = inputs.make_arrivals(count, rate, seed=2)
         mk = lambda p: inputs.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed)  # noqa: E731
         reqs = serve.requests_from_arrivals(arrivals, mk)
         b = ljmd.Batch(16 << 30, 64, precision="mixed", block_steps=block_steps)
         rep = serve.serve(b, reqs).summary()
         b.close()
-        log(f"[bench] served rate={rate}/s: p50 {rep['p50_latency_s']:.3f} s, "
+        log(f"[bench] served rate={rate:.3g}/s: p50 {rep['p50_latency_s']:.3f} s, "
             f"p99 {rep['p99_latency_s']:.3f} s, {rep['atom_steps_per_s']:.4g} atom-steps/s")
 
         def alone(spec, nsteps):
@@ -255,9 +264,10 @@ def run_served(rates, count, block_steps):
 
         reqs1 = serve.requests_from_arrivals(arrivals, mk)
         base = serve.serve_one_by_one(alone, reqs1).summary()
-        log(f"[bench] one by one fp64 rate={rate}/s: p50 {base['p50_latency_s']:.3f} s, "
+        log(f"[bench] one by one fp64 rate={rate:.3g}/s: p50 {base['p50_latency_s']:.3f} s, "
             f"p99 {base['p99_latency_s']:.3f} s, {base['atom_steps_per_s']:.4g} atom-steps/s")
-        out.append({"rate_per_s": rate, "requests": count, **{k: rep[k] for k in (
+        out.append({"rate_per_s": rate, "load": loads[k] if loads else None,
+                    "requests": count, **{k: rep[k] for k in (
             "p50_latency_s", "p99_latency_s", "mean_latency_s", "atom_steps_per_s", "wall_s",
             "peak_resident")},
             "one_by_one_fp64": {k: base[k] for k in ("p50_latency_s", "p99_latency_s",
@@ -280,8 +290,11 @@ def main():
     ap.add_argument("--batched-sample", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-drift", action="store_true")
-    ap.add_argument("--serve-rates", type=str, default="4,16")
-    ap.add_argument("--serve-count", type=int, default=32)
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.9",
+                    help="arrival rates as fractions of the capacity the batched leg measured")
+    ap.add_argument("--serve-rates", type=str, default="",
+                    help="explicit arrival rates per second (instead of --serve-loads)")
+    ap.add_argument("--serve-count", type=int, default=48)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: multi-GPU runs (--gpus > 1) are not part of "
@@ -324,8 +337,18 @@ def main():
             f"(one by one fp64 {batched['one_by_one_fp64']['value']:.4g})")
     served = None
     if not args.no_serve:
-        rates = [float(r) for r in args.serve_rates.split(",") if r]
-        served = run_served(rates, args.serve_count, 100)
+        if args.serve_rates:
+            rates = [float(r) for r in args.serve_rates.split(",") if r]
+            loads = None
+        else:
+            # capacity in requests per second: the batched throughput (else the single-system
+            # one) over the mean work of a request
+            thr = batched["value"] if batched else fp["value"]
+            mu = thr / served_mean_work()
+            loads = [float(x) for x in args.serve_loads.split(",") if x]
+            rates = [x * mu for x in loads]
+            log(f"[bench] served: capacity {mu:.3g} requests/s, loads {loads}")
+        served = run_served(rates, args.serve_count, 100, loads)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu oracle, {args.cpu_steps} steps")

@@ -263,6 +263,34 @@ typedef struct ljmd_batch_stats {
 
 int ljmd_batch_get_stats(ljmd_batch *b, ljmd_batch_stats *out);
 
+/* ---------------------------------------------------------------- tuning table
+ *
+ * The autotuner of single systems (threads_per_particle or block_size 0 in ljmd_config)
+ * times the force evaluation over lanes per particle {1, 2, 4, 8} and workgroup sizes 128..512
+ * (the autotuning the paper applies to its kernels, Section "Performance") and keeps the
+ * choice, for the life of the process, per key (precision, one or several types, size bucket
+ * floor(log2 n)). These two calls read that table and preload it, so that a table saved from
+ * one run freezes the choices of the next: a system whose key is in the table takes the stored
+ * lanes and workgroup size without timing runs. Both are host-only (no device is touched) and
+ * safe to call from any thread. */
+typedef struct ljmd_tuning_entry {
+    int32_t precision;            /* LJMD_FP64 or LJMD_MIXED */
+    int32_t multi_type;           /* 0: one type, 1: several types */
+    int32_t size_bucket;          /* floor(log2 n), 0..26 */
+    int32_t threads_per_particle; /* 1, 2, 4 or 8 */
+    int32_t block_size;           /* a multiple of 64 in [128, 512] */
+} ljmd_tuning_entry;
+
+/* Copies the table, ordered by key, into out[0 .. min(capacity, count)) and stores the
+ * number of entries in *count (out may be NULL when capacity is 0: a size query).
+ * Errors: INVAL (count NULL, capacity < 0, out NULL with capacity > 0). */
+int ljmd_tuning_get(ljmd_tuning_entry *out, int32_t capacity, int32_t *count);
+
+/* Adds the n entries to the table, replacing entries of the same key. All entries are
+ * validated first; if any is out of range the call stores nothing. Systems created earlier
+ * keep their choice. Errors: INVAL. */
+int ljmd_tuning_set(const ljmd_tuning_entry *entries, int32_t n);
+
 /* Thread-local message for the last non-zero status returned on this thread. */
 const char *ljmd_last_error(void);
 

@@ -445,7 +445,11 @@ int tune(ljmd_system *s) {
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) {
+        int ls = 0;
+        if (it != g_tune.end())
+            while ((1 << ls) < (want_tpp ? want_tpp : it->second.first)) ++ls;
+        // a stored choice whose lane count this system cannot address is tuned afresh
+        if (it != g_tune.end() && lanes_fit(s->npad, ls)) {
             s->tpp = want_tpp ? want_tpp : it->second.first;
             s->block = want_block ? want_block : it->second.second;
             for (s->lshift = 0; (1 << s->lshift) < s->tpp; ++s->lshift) {}
@@ -643,6 +647,44 @@ extern "C" {
 const char *ljmd_last_error(void) { return ljmd::g_last_error.c_str(); }
 
 const char *ljmd_version(void) { return "ljmd 0.2 (gfx950)"; }
+
+int ljmd_tuning_get(ljmd_tuning_entry *out, int32_t capacity, int32_t *count) {
+    if (!count || capacity < 0 || (capacity > 0 && !out))
+        return set_err(LJMD_E_INVAL, "count must be non-null and out non-null when capacity > 0");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    int32_t k = 0;
+    for (const auto &kv : g_tune) {  // std::map: ordered by key
+        if (k < capacity)
+            out[k] = ljmd_tuning_entry{kv.first.prec == PREC_MIXED ? LJMD_MIXED : LJMD_FP64,
+                                       kv.first.multi, kv.first.nbucket, kv.second.first,
+                                       kv.second.second};
+        ++k;
+    }
+    *count = k;
+    return LJMD_OK;
+}
+
+int ljmd_tuning_set(const ljmd_tuning_entry *entries, int32_t n) {
+    if (n < 0 || (n > 0 && !entries))
+        return set_err(LJMD_E_INVAL, "entries must be non-null when n > 0");
+    for (int32_t k = 0; k < n; ++k) {
+        const ljmd_tuning_entry &e = entries[k];
+        const int t = e.threads_per_particle;
+        if ((e.precision != LJMD_FP64 && e.precision != LJMD_MIXED) ||
+            (e.multi_type != 0 && e.multi_type != 1) || e.size_bucket < 0 ||
+            e.size_bucket > 26 || !(t == 1 || t == 2 || t == 4 || t == 8) ||
+            e.block_size < 128 || e.block_size > 512 || e.block_size % 64)
+            return set_err(LJMD_E_INVAL, "tuning entry %d is out of range", (int)k);
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int32_t k = 0; k < n; ++k) {
+        const ljmd_tuning_entry &e = entries[k];
+        const int prec = e.precision == LJMD_MIXED ? PREC_MIXED : PREC_FP64;
+        g_tune[TuneKey{prec, e.multi_type, e.size_bucket}] = {e.threads_per_particle,
+                                                              e.block_size};
+    }
+    return LJMD_OK;
+}
 
 int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, const double *vel,
                        const int32_t *type, const double *mass, ljmd_system **out) {

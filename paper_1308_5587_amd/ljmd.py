@@ -9,6 +9,7 @@ this module raises instead of falling back to anything else.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 
 import numpy as np
@@ -86,6 +87,11 @@ class LjmdError(RuntimeError):
 
 _lib = None
 
+class LjmdTuningEntry(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("multi_type", C.c_int32), ("size_bucket", C.c_int32),
+                ("threads_per_particle", C.c_int32), ("block_size", C.c_int32)]
+
+
 EXPORTED = [
     "ljmd_system_create", "ljmd_system_destroy", "ljmd_pair_lj_set", "ljmd_step",
     "ljmd_get_forces", "ljmd_get_energy", "ljmd_get_virial", "ljmd_get_per_particle",
@@ -93,7 +99,7 @@ EXPORTED = [
     "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_last_error", "ljmd_version",
     "ljmd_batch_create", "ljmd_batch_destroy", "ljmd_batch_footprint", "ljmd_batch_admit",
     "ljmd_batch_run_block", "ljmd_batch_poll", "ljmd_batch_read", "ljmd_batch_slot_steps",
-    "ljmd_batch_release", "ljmd_batch_get_stats",
+    "ljmd_batch_release", "ljmd_batch_get_stats", "ljmd_tuning_get", "ljmd_tuning_set",
 ]
 
 
@@ -133,6 +139,8 @@ def load(path: str = LIB_PATH):
         "ljmd_batch_slot_steps": ([vp, C.c_int32, lp], C.c_int),
         "ljmd_batch_release": ([vp, C.c_int32], C.c_int),
         "ljmd_batch_get_stats": ([vp, C.POINTER(LjmdBatchStats)], C.c_int),
+        "ljmd_tuning_get": ([C.POINTER(LjmdTuningEntry), C.c_int32, ip], C.c_int),
+        "ljmd_tuning_set": ([C.POINTER(LjmdTuningEntry), C.c_int32], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -463,3 +471,42 @@ class Batch:
 
 def version():
     return load().ljmd_version().decode()
+
+
+_TUNING_FIELDS = ("precision", "multi_type", "size_bucket", "threads_per_particle", "block_size")
+
+
+def tuning_table():
+    """The process-wide tuning table of single systems, as a list of dicts ordered by key
+    (precision, multi_type, size_bucket) with the chosen threads_per_particle and
+    block_size."""
+    lib = load()
+    n = C.c_int32(0)
+    _check(lib.ljmd_tuning_get(None, 0, C.byref(n)))
+    buf = (LjmdTuningEntry * max(1, n.value))()
+    _check(lib.ljmd_tuning_get(buf, n.value, C.byref(n)))
+    return [{f: int(getattr(buf[k], f)) for f in _TUNING_FIELDS} for k in range(n.value)]
+
+
+def set_tuning(entries):
+    """Preload (freeze) tuning choices: systems created afterwards whose key is given take
+    the stored lanes per particle and workgroup size without timing runs."""
+    lib = load()
+    entries = list(entries)
+    buf = (LjmdTuningEntry * max(1, len(entries)))()
+    for k, e in enumerate(entries):
+        for f in _TUNING_FIELDS:
+            setattr(buf[k], f, int(e[f]))
+    _check(lib.ljmd_tuning_set(buf, len(entries)))
+
+
+def save_tuning(path):
+    """Write the tuning table to a JSON file."""
+    with open(path, "w") as f:
+        json.dump({"ljmd_tuning": tuning_table()}, f, indent=1)
+
+
+def load_tuning(path):
+    """Preload the tuning table from a JSON file written by save_tuning."""
+    with open(path) as f:
+        set_tuning(json.load(f)["ljmd_tuning"])

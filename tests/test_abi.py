@@ -120,7 +120,7 @@ def test_no_device_reports_device_error(lib):
 
 STRUCTS = [("ljmd_config", "LjmdConfig"), ("ljmd_stats", "LjmdStats"),
            ("ljmd_batch_config", "LjmdBatchConfig"), ("ljmd_replica_spec", "LjmdReplicaSpec"),
-           ("ljmd_batch_stats", "LjmdBatchStats")]
+           ("ljmd_batch_stats", "LjmdBatchStats"), ("ljmd_tuning_entry", "LjmdTuningEntry")]
 
 
 @pytest.mark.parametrize("cname,pyname", STRUCTS)
@@ -187,3 +187,36 @@ def test_batch_no_device(lib):
     h = C.c_void_p()
     assert lib.ljmd_batch_create(C.byref(_bcfg()), C.byref(h)) == ljmd.LJMD_E_DEVICE
     assert not h.value
+
+
+def test_tuning_table_round_trip(lib, tmp_path):
+    """The tuning table is host state: entries set are read back in key order, survive a
+    JSON round trip, replace entries of the same key, and an invalid entry stores nothing."""
+    mine = [dict(precision=1, multi_type=1, size_bucket=25, threads_per_particle=4, block_size=448),
+            dict(precision=0, multi_type=0, size_bucket=26, threads_per_particle=2, block_size=512)]
+    ljmd.set_tuning(mine)
+    table = ljmd.tuning_table()
+    keys = [(e["precision"], e["multi_type"], e["size_bucket"]) for e in table]
+    assert keys == sorted(keys)
+    for e in mine:
+        assert e in table
+    path = tmp_path / "tuning.json"
+    ljmd.save_tuning(path)
+    ljmd.set_tuning([dict(mine[0], threads_per_particle=8)])  # same key: replaced
+    assert dict(mine[0], threads_per_particle=8) in ljmd.tuning_table()
+    ljmd.load_tuning(path)
+    assert mine[0] in ljmd.tuning_table()
+    n = len(ljmd.tuning_table())
+    bad = [dict(mine[0], size_bucket=3), dict(mine[1], block_size=96)]
+    with pytest.raises(ljmd.LjmdError) as e:
+        ljmd.set_tuning(bad)
+    assert e.value.code == ljmd.LJMD_E_INVAL
+    assert len(ljmd.tuning_table()) == n  # the valid first entry was not stored either
+    for field, value in (("threads_per_particle", 3), ("precision", 2), ("multi_type", 2),
+                         ("size_bucket", 27), ("block_size", 64)):
+        with pytest.raises(ljmd.LjmdError):
+            ljmd.set_tuning([dict(mine[1], **{field: value})])
+    cnt = C.c_int32(-1)
+    assert lib.ljmd_tuning_get(None, 4, C.byref(cnt)) == ljmd.LJMD_E_INVAL
+    assert lib.ljmd_tuning_get(None, 0, None) == ljmd.LJMD_E_INVAL
+    assert lib.ljmd_tuning_set(None, 1) == ljmd.LJMD_E_INVAL

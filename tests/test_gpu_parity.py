@@ -150,6 +150,33 @@ def test_every_lane_count(ljmd_mod, oracle_mod, tpp):
     _pair(o, g)
 
 
+def test_frozen_tuning_table(ljmd_mod, oracle_mod, tmp_path):
+    # a tuning table saved to JSON and loaded again fixes lanes and workgroup size of systems
+    # in its key without timing runs; the tuner's own choices land in the table
+    print_case("frozen tuning table")
+    s = gen.make_lj_fluid(3000, seed=22)  # size bucket floor(log2 3000) = 11
+    path = tmp_path / "tuning.json"
+    ljmd_mod.set_tuning([dict(precision=0, multi_type=0, size_bucket=11,
+                              threads_per_particle=8, block_size=192)])
+    ljmd_mod.save_tuning(path)
+    ljmd_mod.set_tuning([dict(precision=0, multi_type=0, size_bucket=11,
+                              threads_per_particle=1, block_size=512)])
+    ljmd_mod.load_tuning(path)
+    g = ljmd_mod.System.from_spec(s, threads_per_particle=0, block_size=0)
+    g.step(0)
+    st = g.stats()
+    assert (st["threads_per_particle"], st["block_size"]) == (8, 192)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    _list_parity(o, g, s.pos)
+    _pair(o, g)
+    m = ljmd_mod.System.from_spec(gen.make_lj_fluid(5000, seed=23), precision="mixed")
+    m.step(0)  # bucket 12, mixed: tuned, then recorded
+    mst = m.stats()
+    assert dict(precision=1, multi_type=0, size_bucket=12,
+                threads_per_particle=mst["threads_per_particle"],
+                block_size=mst["block_size"]) in ljmd_mod.tuning_table()
+
+
 def test_mixed_forces(ljmd_mod, oracle_mod):
     print_case("mixed forces n=4000 and KA")
     s = gen.make_lj_fluid(4000, seed=1)
