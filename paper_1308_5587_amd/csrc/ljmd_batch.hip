@@ -816,6 +816,9 @@ int ljmd_batch_admit(ljmd_batch *b, const ljmd_replica_spec *sp, int32_t *slot_o
     P.ntypes = nt;
     P.pair_off = s * PAIR_ROWS;
     P.active = 1;
+    // the capacity the replica would have alone (its own type count): whether a brick's tile
+    // is staged is then the same alone and batched
+    P.tile_cap = grid_tile_cap(g, n, nt, b->lds_limit);
 
     // global cell and brick indices of the replica's tables
     for (auto &r : g.rank) r += coff;

@@ -46,7 +46,9 @@ struct RepParams {
     int canonical;           // some axis has fewer than 3 cells
     int ntypes, pair_off;
     int active;              // 0 for a free slot
-    int pad1;
+    int tile_cap;            // the replica's own tile capacity: a brick's tile is staged in
+                             // the force kernels only if it fits this (and the launch's LDS),
+                             // so the choice never depends on what shares a batch
 };
 
 enum { ST_OVERFLOW = 1, ST_NONFINITE = 2, ST_TILE = 4 };

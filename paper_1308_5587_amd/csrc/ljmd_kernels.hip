@@ -434,8 +434,8 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
         const bool active = p < natoms;
         const int q = first + (active ? (int)a.work[first + p] : 0);
         const double4 xi = a.pos_in[q];
-        // the tile is centred on the brick: so is the particle in the pair loop
-        const double4 xc = centred(xi, ce, P);
+        // the staged tile is centred on the brick: so is the particle in the pair loop
+        const double4 xc = STAGED ? centred(xi, ce, P) : xi;
         const int ti = MULTI ? (int)xi.w : 0;
         int cnt = active ? a.nl_count[q] : 0;
         cnt = cnt < a.cap ? cnt : a.cap;
@@ -456,15 +456,16 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
             const int e[8] = {cur.x & 0xffff, (cur.x >> 16) & 0xffff, cur.y & 0xffff,
                               (cur.y >> 16) & 0xffff, cur.z & 0xffff, (cur.z >> 16) & 0xffff,
                               cur.w & 0xffff, (cur.w >> 16) & 0xffff};
-            // entries in groups of FORCE_BATCH: all neighbour positions of the group are
-            // requested first, then the arithmetic runs on them
+            // entries in groups of FB: all neighbour positions of the group are requested
+            // first, then the arithmetic runs on them
+            constexpr int FB = FORCE_BATCH;
 #pragma unroll
-            for (int u0 = 0; u0 < 8; u0 += FORCE_BATCH) {
-                double px[FORCE_BATCH], py[FORCE_BATCH], pz[FORCE_BATCH];
-                int pt[FORCE_BATCH];
-                bool pv[FORCE_BATCH];
+            for (int u0 = 0; u0 < 8; u0 += FB) {
+                double px[FB], py[FB], pz[FB];
+                int pt[FB];
+                bool pv[FB];
 #pragma unroll
-                for (int v = 0; v < FORCE_BATCH; ++v) {
+                for (int v = 0; v < FB; ++v) {
                     const int u = u0 + v;
                     pv[v] = k0 + u < cnt && e[u] < t.total;
                     const int idx = pv[v] ? e[u] : 0;
@@ -476,8 +477,7 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                         pz[v] = pj.z;
                         if (MULTI) pt[v] = (int)pj.w;
                     } else {
-                        // centred as staging would have: the same bits as the staged path
-                        const double4 pj = centred(a.pos_in[tile_global(t, idx)], ce, P);
+                        const double4 pj = a.pos_in[tile_global(t, idx)];
                         px[v] = pj.x;
                         py[v] = pj.y;
                         pz[v] = pj.z;
@@ -485,7 +485,7 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                     }
                 }
 #pragma unroll
-                for (int v = 0; v < FORCE_BATCH; ++v) {
+                for (int v = 0; v < FB; ++v) {
                     const double dx = (MIF & 1) ? px[v] - xc.x : mi_rint(px[v] - xc.x, L0, iL0);
                     const double dy = (MIF & 2) ? py[v] - xc.y : mi_rint(py[v] - xc.y, L1, iL1);
                     const double dz = (MIF & 4) ? pz[v] - xc.z : mi_rint(pz[v] - xc.z, L2, iL2);
@@ -586,8 +586,10 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
 // lanes per particle of the brick stride through the particle's list of 16-bit tile
 // indices, 8 per 16-byte load, gathering neighbour positions from LDS. Forces are reduced
 // across the lanes with wavefront shuffles; lane 0 then finishes the particle according to
-// MODE. If a tile is larger than the LDS allocation, the positions are read from global
-// memory through the tile offsets instead, with the minimum image on every axis.
+// MODE. If a tile is larger than the replica's own tile capacity (or the LDS allocation),
+// the positions are read from global memory through the tile offsets instead, with the
+// minimum image on every axis; the capacity is the replica's, so a replica takes the same
+// path alone and in a batch.
 // Occupancy: a 48 KiB tile lets three 512-thread workgroups share a CU, which needs at most
 // 80 VGPRs (6 waves per SIMD); the single-type variants without energy fit that without
 // spilling and are held to it, the others keep their natural register count.
@@ -630,7 +632,7 @@ k_force(const ForceArgs a) {
             s_pair[k] = a.pair[P.pair_off + k];
     const PairCoef single = a.pair[P.pair_off];
     tile_load(a.tile_tab + (size_t)b * TILE_TAB, t);
-    const bool staged = t.total <= a.tile_cap;
+    const bool staged = t.total <= a.tile_cap && t.total <= P.tile_cap;
     const Centre ce = brick_centre(bi);
     if (staged) {
         switch (ce.mask) {

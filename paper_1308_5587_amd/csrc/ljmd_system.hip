@@ -195,6 +195,7 @@ int setup_table(ljmd_system *s) {
     P.ntypes = nt;
     P.pair_off = 0;
     P.active = 1;
+    P.tile_cap = grid_tile_cap(g, s->n, nt, s->lds_limit);
     HIPCHK(hipMemcpyAsync(s->d_rep, &P, sizeof(RepParams), hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->d_pair, pt.coef.data(), sizeof(PairCoef) * nt * nt,
                           hipMemcpyHostToDevice, s->stream));
@@ -213,7 +214,7 @@ int setup_table(ljmd_system *s) {
     s->rl_max = pt.rl_max;
     s->ncell = ncell;
     s->nbrick = g.nbrick;
-    s->tile_cap = grid_tile_cap(g, s->n, nt, s->lds_limit);
+    s->tile_cap = P.tile_cap;
     s->table_dirty = false;
     s->list_valid = false;
     s->force_valid = false;

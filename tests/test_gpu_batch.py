@@ -82,11 +82,12 @@ def test_batch_equals_alone_bitwise(ljmd_mod, precision):
     b.close()
 
 
-def test_staged_in_batch_equals_unstaged_alone(ljmd_mod):
+def test_tile_overflow_decided_per_replica(ljmd_mod):
     # alone, the droplet's tile capacity is sized for its mean cell count and the bricks
-    # around its dense block read neighbours from global memory; beside a dense fluid the
-    # batch's capacity holds those tiles in LDS. Both paths must give the same bits.
-    print_case("droplet beside a dense fluid: staged in the batch, unstaged alone")
+    # around its dense block read neighbours from global memory. Beside a dense fluid the
+    # batch's LDS allocation would hold those tiles, but the choice follows the replica's own
+    # capacity, so the droplet takes the same path, and gets the same bits, in both runs.
+    print_case("droplet beside a dense fluid: same force path alone and batched")
     mix = [(gen.make_lj_droplet(seed=6), 30), (gen.make_lj_fluid(4000, seed=7), 30)]
     b = ljmd_mod.Batch(256 << 20, 2, precision="fp64", block_steps=16,
                        threads_per_particle=TPP, block_size=BLOCK)
