@@ -59,10 +59,11 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1308_5587_amd", "csrc", f)
                   for f in ("ljmd_kernels.hip", "ljmd_internal.h")]
 
 
-def measured_traffic(tpp, block):
-    """HBM bytes per launch of the fused FP64 kernel from the committed counter passes, if they
-    were taken on the current kernel sources with these lanes per particle; else None. The
-    workgroup size is not matched: one workgroup per brick moves the same bytes at any size."""
+def _counter_fields(tpp):
+    """Machine-readable lines of the committed counter passes over the fused FP64 kernel, if
+    they were taken on the current kernel sources with these lanes per particle; else None.
+    The workgroup size is not matched: one workgroup per brick moves the same bytes and issues
+    the same instructions at any size."""
     import hashlib
 
     try:
@@ -71,6 +72,7 @@ def measured_traffic(tpp, block):
         return None
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line
                   and line.split(": ", 1)[0] in ("launch", "traffic-bytes-per-launch",
+                                                 "valu-wave-instructions-per-launch",
                                                  "kernel-source-sha256"))
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -79,7 +81,29 @@ def measured_traffic(tpp, block):
         return None
     if fields.get("launch", "").strip().split(" block=")[0] != f"fp64 tpp={tpp}":
         return None
-    return float(fields["traffic-bytes-per-launch"])
+    return fields
+
+
+def measured_traffic(tpp, block):
+    """HBM bytes per launch of the fused FP64 kernel (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
+    from the committed counter passes, or None (see _counter_fields)."""
+    fields = _counter_fields(tpp)
+    return float(fields["traffic-bytes-per-launch"]) if fields else None
+
+
+def valu_issue(tpp, kernel_ms):
+    """VALU issue rate of the fused FP64 kernel: the committed count of wave-level VALU
+    instructions per launch over the launch time measured here, against the issue peak of one
+    VALU instruction per CU per cycle (256 CUs x 2.4 GHz; a wave64 FP64 instruction takes four
+    cycles on a 16-lane SIMD, four SIMDs per CU). None without a matching counter pass."""
+    fields = _counter_fields(tpp)
+    if not fields or "valu-wave-instructions-per-launch" not in fields:
+        return None
+    insts = float(fields["valu-wave-instructions-per-launch"])
+    achieved = insts / (kernel_ms * 1e-3) / 1e9
+    peak = 256 * 2.4
+    return {"achieved": achieved, "peak": peak, "unit": "G wave-instructions/s",
+            "frac": achieved / peak, "instructions_per_launch": insts}
 
 
 def run_gpu(spec, precision, steps, warmup, timing_steps):
@@ -378,7 +402,8 @@ def main():
                      "unit": "GB/s", "frac": fp["achieved_gbs"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic(fp["threads_per_particle"], fp["block_size"]),
                      "kernel": "k_force<fp64, FUSED>", "kernel_avg_ms": fp["kernel_avg_ms"],
-                     "bytes_per_atom": fp["bytes_per_atom"]},
+                     "bytes_per_atom": fp["bytes_per_atom"],
+                     "valu_issue": valu_issue(fp["threads_per_particle"], fp["kernel_avg_ms"])},
         "cpu_baseline": cpu,
     }
     if mixed is not None:
