@@ -393,3 +393,30 @@ def test_full_size_fp64_and_mixed(ljmd_mod, oracle_mod):
     o.step(2)
     g.step(2)
     assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
+
+
+def test_full_size_ka_mixture(ljmd_mod, oracle_mod):
+    """The Kob-Andersen mixture at its benchmark size (N = 262,144, density 1.2, per-pair
+    cutoffs) in the launch configuration the library tunes for it: the whole list, and forces,
+    energy and virial on the mixed path (the configuration's precision) and on the FP64 path,
+    against the oracle; then ten steps of both paths."""
+    print_case("full size KA mixture N=262144")
+    s = gen.make_ka_mixture(262_144, seed=1)
+    o = oracle_mod.OracleSystem.from_spec(s)
+    m = ljmd_mod.System.from_spec(s, precision="mixed")
+    _list_parity(o, m, s.pos)
+    assert max_norm_rel(m.forces(), o.forces()) <= 1e-5
+    Uo, _ = o.energy()
+    assert scalar_rel(m.energy()[0], Uo) <= 1e-5
+    assert max_norm_rel(m.virial(), o.virial()) <= 1e-5
+    g = ljmd_mod.System.from_spec(s)
+    assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
+    assert scalar_rel(g.energy()[0], Uo) <= 1e-10
+    o.step(10)
+    g.step(10)
+    m.step(10)
+    assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
+    assert max_norm_rel(m.forces(), o.forces()) <= 1e-4
+    po, _, io, _ = o.state()
+    pg, _, ig, _ = g.state()
+    assert np.abs(unwrapped(pg, ig, s.box) - unwrapped(po, io, s.box)).max() < 1e-10
