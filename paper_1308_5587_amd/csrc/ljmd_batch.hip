@@ -891,6 +891,12 @@ int ljmd_batch_admit(ljmd_batch *b, const ljmd_replica_spec *sp, int32_t *slot_o
     if (rc != LJMD_OK) return undo(rc);
     rc = forced_rebuild(b, {s});
     if (rc != LJMD_OK) return undo(rc);
+    // before the first block tunes the lanes per particle, keep the sorted state at t = 0:
+    // the first half step is taken again with the tuned lanes (redo_first_half_step)
+    if (!b->layout_fixed && !b->cfg.threads_per_particle) {
+        rc = copy_range(b, b->slots[s], true);
+        if (rc != LJMD_OK) return undo(rc);
+    }
 
     // forces at the initial positions, then the first half step
     rc = clear_status(b);
@@ -952,6 +958,56 @@ int ljmd_batch_admit(ljmd_batch *b, const ljmd_replica_spec *sp, int32_t *slot_o
     return LJMD_OK;
 }
 
+namespace {
+
+// Replicas admitted before the first block took their first force evaluation and half step
+// with the default lanes per particle. The lane count orders each particle's force sum, so
+// once the block has tuned the lanes these steps are taken again with them, from the sorted
+// state kept at admission: every replica then follows the trajectory its alone run computes
+// with the same lanes. The sequence is admission's, for all of them at once: build, forces,
+// kick and drift, drifted positions into the current buffer, the builds the drift asks for.
+int redo_first_half_step(ljmd_batch *b, const std::vector<int> &which) {
+    for (int s : which) CHK(copy_range(b, b->slots[s], false));
+    std::fill(b->h_mask.begin(), b->h_mask.end(), 0);
+    for (int s : which) b->h_mask[s] = 1;
+    CHK(upload_mask(b, b->d_go, b->h_mask));
+    CHK(upload_mask(b, b->d_only, b->h_mask));
+    CHK(forced_rebuild(b, which));
+    CHK(clear_status(b));
+    CHK(launch_chk(launch_force(b->stream, force_args(b, b->cur, b->d_only, false), b->prec,
+                                b->tpp, MODE_EVAL, false, b->block), "force eval"));
+    CHK(read_status(b));
+    for (int s : which)
+        if (b->h_status[s] & ST_NONFINITE)
+            return set_err(LJMD_E_NONFINITE, "non-finite force at the initial positions of slot %d", s);
+    KickDriftArgs ka{};
+    ka.reps = b->d_reps;
+    ka.prep = b->d_prep;
+    ka.pos_in = b->d_pos[b->cur];
+    ka.pos_out = b->d_pos[b->cur ^ 1];
+    ka.vel = b->d_vel;
+    ka.img = b->d_img;
+    ka.xb = b->d_xb;
+    ka.force = b->d_force;
+    ka.req = b->d_req;
+    ka.only = b->d_only;
+    ka.cur = b->cur;
+    ka.n = b->p_ext;
+    HIPCHK(hipMemsetAsync(b->d_req, 0, 2 * sizeof(int) * b->max_slots, b->stream));
+    CHK(launch_chk(launch_kick_drift(b->stream, ka), "kick-drift"));
+    CHK(launch_chk(launch_fill_int(b->stream, b->d_go, b->max_slots, 0), "fill"));
+    for (int s : which) {
+        const Slot &sl = b->slots[s];
+        HIPCHK(hipMemcpyAsync(b->d_pos[b->cur] + sl.poff, b->d_pos[b->cur ^ 1] + sl.poff,
+                              (size_t)sl.n * sizeof(double4), hipMemcpyDeviceToDevice, b->stream));
+        HIPCHK(hipMemcpyAsync(b->d_go + s, b->d_req + 2 * s + (b->cur ^ 1), sizeof(int),
+                              hipMemcpyDeviceToDevice, b->stream));
+    }
+    return forced_rebuild(b, which);  // gated by the go words just written
+}
+
+}  // namespace
+
 int ljmd_batch_run_block(ljmd_batch *b) {
     if (!b) return set_err(LJMD_E_INVAL, "null handle");
     std::vector<int> running;
@@ -966,6 +1022,7 @@ int ljmd_batch_run_block(ljmd_batch *b) {
             CHK(upload_mask(b, b->d_go, b->h_mask));
             CHK(upload_mask(b, b->d_only, b->h_mask));
             CHK(tune(b, running));
+            if (!b->cfg.threads_per_particle && b->tpp != 2) CHK(redo_first_half_step(b, running));
             HIPCHK(hipMemsetAsync(b->d_req, 0, 2 * sizeof(int) * b->max_slots, b->stream));
         }
         b->layout_fixed = true;

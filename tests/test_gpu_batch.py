@@ -244,3 +244,37 @@ def test_served_stream_results_equal_alone(ljmd_mod):
     assert rep.peak_resident == 3, rep.peak_resident
     for r in rep.requests:
         _same(r.result, _alone(ljmd_mod, r.spec, r.nsteps, "mixed"))
+
+
+def test_full_size_batch_sampled_replicas(ljmd_mod, oracle_mod):
+    """The benchmark's batch at full size: 512 replicas (N uniform in [256, 8192], density in
+    [0.6, 0.9], T in [0.8, 1.5]), mixed precision, lanes and workgroup autotuned at the first
+    block, one 100-step graph block. Sampled replicas equal their alone runs bit for bit (at
+    the batch's lanes per particle) and track the FP64 oracle."""
+    print_case("full batch: 512 replicas, one block; sampled replicas alone and vs oracle")
+    params = gen.make_replica_specs(512, seed=0)
+    specs = [gen.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed) for p in params]
+    b = ljmd_mod.Batch(8 << 30, 512, precision="mixed", block_steps=100)
+    slots = [b.admit(s, 100) for s in specs]
+    b.run_block()
+    assert set(b.poll()) == set(slots)
+    st = b.stats()
+    assert st["resident"] == 512 and st["running"] == 0
+    tpp, block = st["threads_per_particle"], st["block_size"]
+    for k in np.random.default_rng(5).choice(512, size=3, replace=False):
+        spec = specs[k]
+        got = b.read(slots[k])
+        g = ljmd_mod.System.from_spec(spec, precision="mixed", threads_per_particle=tpp,
+                                      block_size=block)
+        g.step(100)
+        pos, vel, _, _ = g.state()
+        u, kin = g.energy()
+        _same(got, {"pos": pos, "vel": vel, "forces": g.forces(), "potential": u,
+                    "kinetic": kin, "virial": g.virial()})
+        o = oracle_mod.OracleSystem.from_spec(spec)
+        o.step(100)
+        po, _, _, _ = o.state()
+        d = got["pos"] - po
+        d -= spec.box[None, :] * np.rint(d / spec.box[None, :])
+        assert np.abs(d).max() < 1e-3, (k, np.abs(d).max())
+    b.close()
