@@ -93,6 +93,8 @@ def test_droplet_tiles_beyond_capacity(ljmd_mod, oracle_mod):
     g = ljmd_mod.System.from_spec(s)
     _list_parity(o, g, s.pos)
     _pair(o, g)
+    m = ljmd_mod.System.from_spec(s, precision="mixed")  # the fallback in FP32 pair arithmetic
+    _pair(o, m, fp64=False)
     o.step(40)
     g.step(40)
     po, vo, io, _ = o.state()
