@@ -71,6 +71,11 @@ def _load():
         lib.oracle_get_state.argtypes = [C.c_void_p, dp, dp, ip, lp]
         lib.oracle_get_pairs.argtypes = [C.c_void_p, lp, ip, dp]
         lib.oracle_get_counters.argtypes = [C.c_void_p, lp, lp]
+        lib.oracle_set_nvt.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        lib.oracle_set_nve.argtypes = [C.c_void_p]
+        lib.oracle_get_thermostat.argtypes = [C.c_void_p, dp, dp, dp]
+        lib.oracle_set_thermostat.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        lib.oracle_negate_velocities.argtypes = [C.c_void_p]
         _lib = lib
     return _lib
 
@@ -174,6 +179,27 @@ class OracleSystem:
         xb = np.empty((self.n, 3))
         _check(self._lib.oracle_get_pairs(self._h, C.byref(cnt), _ip(out), _dp(xb)))
         return out, xb
+
+    def set_nvt(self, kT, tau):
+        """NVT (Nose-Hoover, symmetric splitting) at kT with time constant tau; tau may be
+        float('inf') for zero coupling."""
+        _check(self._lib.oracle_set_nvt(self._h, float(kT), float(tau)))
+
+    def set_nve(self):
+        _check(self._lib.oracle_set_nve(self._h))
+
+    def thermostat(self):
+        """(xi, eta, thermostat energy Q xi^2/2 + N_f kT eta)."""
+        out = np.zeros(3)
+        _check(self._lib.oracle_get_thermostat(self._h, _dp(out[0:1]), _dp(out[1:2]),
+                                               _dp(out[2:3])))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def set_thermostat(self, xi, eta):
+        _check(self._lib.oracle_set_thermostat(self._h, float(xi), float(eta)))
+
+    def negate_velocities(self):
+        _check(self._lib.oracle_negate_velocities(self._h))
 
     def counters(self):
         st = C.c_int64(0)

@@ -29,6 +29,19 @@
  *   step        velocity Verlet (NVE): v += dt/(2m) F; x += dt v, wrap and count images;
  *               rebuild the list when max |x - x_build|^2 (min image) >= (r_s/2)^2;
  *               recompute F; v += dt/(2m) F.
+ *   NVT         (the integrator of the paper's MD listing, built on the Martyna-Tobias-
+ *               Klein method, Section "Capabilities"): one Nose-Hoover thermostat
+ *               variable xi with "position" eta and mass Q = N_f kT tau^2, N_f = 3N - 3.
+ *               The equations of motion dx/dt = v, dv/dt = F/m - xi v,
+ *               dxi/dt = (2K - N_f kT)/Q, deta/dt = xi are split symmetrically (the
+ *               time-reversible factorisation of Martyna, Tuckerman, Tobias and Klein,
+ *               chain length one): each step is a thermostat half step, the velocity-
+ *               Verlet step above, and another thermostat half step. A thermostat half
+ *               step of length dt/2 is: xi += (dt/4) G(K); eta += (dt/2) xi; every v is
+ *               scaled by s = exp(-(dt/2) xi), so K becomes s^2 K; xi += (dt/4) G(K), with
+ *               G(K) = (2K - N_f kT) / Q and K = sum m v^2 / 2. The conserved quantity is
+ *               K + U + Q xi^2 / 2 + N_f kT eta. tau = +infinity is zero coupling: xi and
+ *               eta stay 0, s = 1, and the step is the NVE step.
  *
  * Every function below is a direct statement of one of these definitions, with no
  * blocking, fusion or reordering beyond what the definition states.
@@ -63,6 +76,9 @@ typedef struct {
     /* results of the last force evaluation */
     double U, W[6];
     double *u_i, *w_i;       /* n, n*6 */
+    /* NVT thermostat (nvt = 0: NVE) */
+    int nvt;
+    double kT, invQ, xi, eta;
 } orc_sys;
 
 /* ---------------------------------------------------------------- basic definitions */
@@ -387,6 +403,84 @@ int oracle_rebuild(orc_sys *s)
 
 /* ---------------------------------------------------------------- integration */
 
+static double kinetic_energy(const orc_sys *s)
+{
+    double k = 0.0;
+    for (int64_t i = 0; i < s->n; ++i)
+        for (int a = 0; a < 3; ++a) k += 0.5 * s->m[i] * s->v[3 * i + a] * s->v[3 * i + a];
+    return k;
+}
+
+/* degrees of freedom of the thermostatted motion: 3N - 3 (total momentum is conserved) */
+static double dof(const orc_sys *s) { return 3.0 * (double)s->n - 3.0; }
+
+/* one thermostat half step of length dt/2 (see the header) */
+static void thermostat_half(orc_sys *s)
+{
+    double g = dof(s) * s->kT;
+    double K = kinetic_energy(s);
+    s->xi += 0.25 * s->dt * (2.0 * K - g) * s->invQ;
+    s->eta += 0.5 * s->dt * s->xi;
+    double sc = exp(-0.5 * s->dt * s->xi);
+    for (int64_t q = 0; q < 3 * s->n; ++q) s->v[q] *= sc;
+    K = sc * sc * K;
+    s->xi += 0.25 * s->dt * (2.0 * K - g) * s->invQ;
+}
+
+/* NVT at temperature kT with thermostat time constant tau (Q = N_f kT tau^2); tau may be
+ * +infinity (zero coupling). The thermostat variables start at 0. */
+int oracle_set_nvt(orc_sys *s, double kT, double tau)
+{
+    if (!s || s->n < 2 || !(kT > 0.0) || !isfinite(kT) || !(tau > 0.0)) return ORC_EINVAL;
+    s->nvt = 1;
+    s->kT = kT;
+    s->invQ = isinf(tau) ? 0.0 : 1.0 / (dof(s) * kT * tau * tau);
+    s->xi = 0.0;
+    s->eta = 0.0;
+    return ORC_OK;
+}
+
+int oracle_set_nve(orc_sys *s)
+{
+    if (!s) return ORC_EINVAL;
+    s->nvt = 0;
+    s->xi = 0.0;
+    s->eta = 0.0;
+    return ORC_OK;
+}
+
+/* xi, eta and the thermostat's share of the conserved quantity, Q xi^2 / 2 + N_f kT eta
+ * (0 for NVE or zero coupling); any pointer may be NULL */
+int oracle_get_thermostat(const orc_sys *s, double *xi, double *eta, double *energy)
+{
+    if (!s) return ORC_EINVAL;
+    if (xi) *xi = s->xi;
+    if (eta) *eta = s->eta;
+    if (energy) {
+        double e = 0.0;
+        if (s->nvt && s->invQ > 0.0)
+            e = 0.5 * s->xi * s->xi / s->invQ + dof(s) * s->kT * s->eta;
+        *energy = e;
+    }
+    return ORC_OK;
+}
+
+int oracle_set_thermostat(orc_sys *s, double xi, double eta)
+{
+    if (!s || !isfinite(xi) || !isfinite(eta)) return ORC_EINVAL;
+    s->xi = xi;
+    s->eta = eta;
+    return ORC_OK;
+}
+
+/* velocities v -> -v (for reversibility checks) */
+int oracle_negate_velocities(orc_sys *s)
+{
+    if (!s) return ORC_EINVAL;
+    for (int64_t q = 0; q < 3 * s->n; ++q) s->v[q] = -s->v[q];
+    return ORC_OK;
+}
+
 static int needs_rebuild(const orc_sys *s)
 {
     double lim = 0.5 * s->skin;
@@ -407,6 +501,7 @@ int oracle_step(orc_sys *s, int64_t nsteps)
     if (rc != ORC_OK) return rc;
     double h = 0.5 * s->dt;
     for (int64_t t = 0; t < nsteps; ++t) {
+        if (s->nvt) thermostat_half(s);
         for (int64_t i = 0; i < s->n; ++i)
             for (int a = 0; a < 3; ++a) s->v[3 * i + a] += h * s->f[3 * i + a] / s->m[i];
         for (int64_t i = 0; i < s->n; ++i)
@@ -420,6 +515,7 @@ int oracle_step(orc_sys *s, int64_t nsteps)
         if (rc != ORC_OK) return rc;
         for (int64_t i = 0; i < s->n; ++i)
             for (int a = 0; a < 3; ++a) s->v[3 * i + a] += h * s->f[3 * i + a] / s->m[i];
+        if (s->nvt) thermostat_half(s);
         s->steps += 1;
     }
     return ORC_OK;
@@ -439,11 +535,8 @@ int oracle_get_energy(orc_sys *s, double *potential, double *kinetic)
 {
     int rc = oracle_compute(s);
     if (rc != ORC_OK) return rc;
-    double k = 0.0;
-    for (int64_t i = 0; i < s->n; ++i)
-        for (int a = 0; a < 3; ++a) k += 0.5 * s->m[i] * s->v[3 * i + a] * s->v[3 * i + a];
     if (potential) *potential = s->U;
-    if (kinetic) *kinetic = k;
+    if (kinetic) *kinetic = kinetic_energy(s);
     return ORC_OK;
 }
 

@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle_md.c")
 PIN_TESTS = ["tests/test_oracle_invariants.py", "tests/test_oracle_vs_brute.py",
-             "tests/test_six_particle.py"]
+             "tests/test_six_particle.py", "tests/test_oracle_nvt.py"]
 
 MUTANTS = {
     "drop_energy_shift": ("lj_energy(s->eps[k], s->sig[k], r2) -\n                   lj_energy(",
@@ -30,6 +30,15 @@ MUTANTS = {
     "wrap_image_sign": ("*x -= L;\n        *img += 1;", "*x -= L;\n        *img -= 1;"),
     "r2_drops_z": ("return t + zz;", "return t + 0.0 * zz;"),
     "force_factor_exponent": ("24.0 * eps * (2.0 * sr12 - sr6) / r2", "24.0 * eps * (2.0 * sr12 - sr6)"),
+    # NVT thermostat
+    "nvt_first_xi_update_half_step": ("s->xi += 0.25 * s->dt * (2.0 * K - g) * s->invQ;\n    s->eta",
+                                      "s->xi += 0.5 * s->dt * (2.0 * K - g) * s->invQ;\n    s->eta"),
+    "nvt_eta_full_step": ("s->eta += 0.5 * s->dt * s->xi;", "s->eta += s->dt * s->xi;"),
+    "nvt_scale_full_step": ("exp(-0.5 * s->dt * s->xi)", "exp(-s->dt * s->xi)"),
+    "nvt_kinetic_not_rescaled": ("K = sc * sc * K;", "K = sc * K;"),
+    "nvt_dof_without_momentum": ("return 3.0 * (double)s->n - 3.0;", "return 3.0 * (double)s->n;"),
+    "nvt_end_half_step_dropped": ("if (s->nvt) thermostat_half(s);\n        s->steps += 1;",
+                                  "s->steps += 1;"),
 }
 
 
