@@ -30,18 +30,39 @@ ORC_ERRORS = {-1: "invalid argument", -2: "out of memory", -4: "box too small",
               -5: "non-finite force", -6: "pair table incomplete"}
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, no FMA contraction, no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-o", tmp, _SRC, "-lm"]
+_NATIVE_LIB = os.path.join(_HERE, "liboracle_md_native.so")
+# Flags of every build: optimised, no FMA contraction, no fast-math (the arithmetic is the
+# definitions' as written). The native build adds -march=native for timing on the host it
+# runs on; it is compiled there, on first use.
+_FLAGS = ["-O3", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+
+
+def build(force: bool = True, native: bool = False) -> str:
+    """Compile the oracle with gcc."""
+    out = _NATIVE_LIB if native else _LIB
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp"
+        cmd = ["gcc", *_FLAGS, *(["-march=native"] if native else []), "-o", tmp, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
+
+
+def build_flags(native: bool = False) -> str:
+    return " ".join(["gcc", *_FLAGS, *(["-march=native"] if native else [])])
 
 
 _lib = None
+_use_native = False
+
+
+def use_native_build():
+    """Load the -march=native build (compiled on this host) instead of the portable one; only
+    before the first oracle system of the process is created. Used for CPU timing."""
+    global _use_native
+    if _lib is not None:
+        raise RuntimeError("the oracle library is already loaded")
+    _use_native = True
 
 
 def _load():
@@ -49,6 +70,8 @@ def _load():
     if _lib is None:
         if _LIB_OVERRIDE:
             lib = C.CDLL(_LIB_OVERRIDE)
+        elif _use_native:
+            lib = C.CDLL(build(force=True, native=True))
         else:
             build(force=False)
             lib = C.CDLL(_LIB)
@@ -72,6 +95,8 @@ def _load():
         lib.oracle_get_pairs.argtypes = [C.c_void_p, lp, ip, dp]
         lib.oracle_get_counters.argtypes = [C.c_void_p, lp, lp]
         lib.oracle_set_nvt.argtypes = [C.c_void_p, C.c_double, C.c_double]
+        lib.oracle_set_pair_style.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, dp,
+                                              C.c_double]
         lib.oracle_set_nve.argtypes = [C.c_void_p]
         lib.oracle_get_thermostat.argtypes = [C.c_void_p, dp, dp, dp]
         lib.oracle_set_thermostat.argtypes = [C.c_void_p, C.c_double, C.c_double]
@@ -179,6 +204,16 @@ class OracleSystem:
         xb = np.empty((self.n, 3))
         _check(self._lib.oracle_get_pairs(self._h, C.byref(cnt), _ip(out), _dp(xb)))
         return out, xb
+
+    STYLES = {"lj": 0, "mie": 1, "gauss": 2, "yukawa": 3}
+
+    def set_pair_style(self, a, b, style, params, rc):
+        """A pair of another form: 'mie' (eps, sigma, n, m), 'gauss' (eps, sigma),
+        'yukawa' (eps, kappa), or 'lj' (eps, sigma)."""
+        p = np.zeros(4)
+        p[:len(params)] = params
+        _check(self._lib.oracle_set_pair_style(self._h, a, b, self.STYLES[style], _dp(p),
+                                               float(rc)))
 
     def set_nvt(self, kT, tau):
         """NVT (Nose-Hoover, symmetric splitting) at kT with time constant tau; tau may be

@@ -29,6 +29,15 @@
  *   step        velocity Verlet (NVE): v += dt/(2m) F; x += dt v, wrap and count images;
  *               rebuild the list when max |x - x_build|^2 (min image) >= (r_s/2)^2;
  *               recompute F; v += dt/(2m) F.
+ *   other pair  forms on the same skeleton (Section "Capabilities" lists Gaussian, Mie, WCA
+ *   potentials  and Yukawa among its pair potentials), each truncated at r_cut with the
+ *               energy shifted to 0 there and the force not shifted; f is the factor with
+ *               F on i = f (x_i - x_j), f = -(du/dr) / r:
+ *                 Mie(eps, sigma, n, m): u = C eps ((s/r)^n - (s/r)^m),
+ *                   C = (n / (n - m)) (n / m)^(m / (n - m)); f = C eps (n (s/r)^n - m (s/r)^m) / r^2
+ *                 Gaussian(eps, sigma): u = eps exp(-r^2 / (2 s^2)); f = eps / s^2 exp(-r^2 / (2 s^2))
+ *                 Yukawa(eps, kappa): u = eps exp(-kappa r) / r; f = eps exp(-kappa r) (1 + kappa r) / r^3
+ *               WCA is the LJ form cut at 2^(1/6) sigma (the shift then is +eps).
  *   NVT         (the integrator of the paper's MD listing, built on the Martyna-Tobias-
  *               Klein method, Section "Capabilities"): one Nose-Hoover thermostat
  *               variable xi with "position" eta and mass Q = N_f kT tau^2, N_f = 3N - 3.
@@ -68,6 +77,8 @@ typedef struct {
     double *xb;              /* positions at the last list build, n*3 */
     double *eps, *sig, *rc;  /* ntypes*ntypes */
     int32_t *is_set;         /* ntypes*ntypes */
+    int32_t *style;          /* ntypes*ntypes: ORC_LJ, ORC_MIE, ORC_GAUSS, ORC_YUKAWA */
+    double *par;             /* ntypes*ntypes*4 form parameters (LJ: eps, sigma) */
     /* neighbour list: half list of index pairs (i < j) */
     int64_t npairs, cap;
     int32_t *pi, *pj;
@@ -119,6 +130,40 @@ static double lj_force_factor(double eps, double sig, double r2)
     return 24.0 * eps * (2.0 * sr12 - sr6) / r2;
 }
 
+#define ORC_LJ 0
+#define ORC_MIE 1
+#define ORC_GAUSS 2
+#define ORC_YUKAWA 3
+
+/* energy of the other forms (see the header), before truncation and shift */
+static double form_energy(int style, const double *p, double r2)
+{
+    if (style == ORC_MIE) {
+        double n = p[2], m = p[3];
+        double c = (n / (n - m)) * pow(n / m, m / (n - m));
+        double sr2 = (p[1] * p[1]) / r2;
+        return c * p[0] * (pow(sr2, 0.5 * n) - pow(sr2, 0.5 * m));
+    }
+    if (style == ORC_GAUSS) return p[0] * exp(-r2 / (2.0 * p[1] * p[1]));
+    /* Yukawa */
+    double r = sqrt(r2);
+    return p[0] * exp(-p[1] * r) / r;
+}
+
+/* force factor f of the other forms: F on i = f (x_i - x_j) */
+static double form_force_factor(int style, const double *p, double r2)
+{
+    if (style == ORC_MIE) {
+        double n = p[2], m = p[3];
+        double c = (n / (n - m)) * pow(n / m, m / (n - m));
+        double sr2 = (p[1] * p[1]) / r2;
+        return c * p[0] * (n * pow(sr2, 0.5 * n) - m * pow(sr2, 0.5 * m)) / r2;
+    }
+    if (style == ORC_GAUSS) return p[0] / (p[1] * p[1]) * exp(-r2 / (2.0 * p[1] * p[1]));
+    double r = sqrt(r2);
+    return p[0] * exp(-p[1] * r) * (1.0 + p[1] * r) / (r2 * r);
+}
+
 static int pair_index(const orc_sys *s, int32_t a, int32_t b) { return a * s->ntypes + b; }
 
 static double list_threshold2(const orc_sys *s, int32_t a, int32_t b)
@@ -159,6 +204,7 @@ void oracle_destroy(orc_sys *s)
     if (!s) return;
     free(s->x); free(s->v); free(s->f); free(s->m); free(s->type); free(s->img);
     free(s->xb); free(s->eps); free(s->sig); free(s->rc); free(s->is_set);
+    free(s->style); free(s->par);
     free(s->pi); free(s->pj); free(s->u_i); free(s->w_i);
     free(s);
 }
@@ -190,10 +236,12 @@ orc_sys *oracle_create(int64_t n, const double *box, const double *pos, const do
     s->sig = (double *)calloc(nt2, sizeof(double));
     s->rc = (double *)calloc(nt2, sizeof(double));
     s->is_set = (int32_t *)calloc(nt2, sizeof(int32_t));
+    s->style = (int32_t *)calloc(nt2, sizeof(int32_t));
+    s->par = (double *)calloc(4 * nt2, sizeof(double));
     s->u_i = (double *)calloc(n, sizeof(double));
     s->w_i = (double *)calloc(6 * n, sizeof(double));
     if (!s->x || !s->v || !s->f || !s->m || !s->type || !s->img || !s->xb || !s->eps ||
-        !s->sig || !s->rc || !s->is_set || !s->u_i || !s->w_i) {
+        !s->sig || !s->rc || !s->is_set || !s->style || !s->par || !s->u_i || !s->w_i) {
         oracle_destroy(s);
         return NULL;
     }
@@ -229,6 +277,30 @@ int oracle_set_pair(orc_sys *s, int32_t a, int32_t b, double eps, double sig, do
     s->sig[k1] = s->sig[k2] = sig;
     s->rc[k1] = s->rc[k2] = rc;
     s->is_set[k1] = s->is_set[k2] = 1;
+    s->style[k1] = s->style[k2] = ORC_LJ;
+    s->list_valid = 0;
+    s->force_valid = 0;
+    return ORC_OK;
+}
+
+/* a pair of one of the other forms: params holds (eps, sigma, n, m) for Mie, (eps, sigma)
+ * for Gaussian, (eps, kappa) for Yukawa */
+int oracle_set_pair_style(orc_sys *s, int32_t a, int32_t b, int32_t style, const double *params,
+                          double rc)
+{
+    if (!s || !params || a < 0 || b < 0 || a >= s->ntypes || b >= s->ntypes) return ORC_EINVAL;
+    if (style == ORC_LJ) return oracle_set_pair(s, a, b, params[0], params[1], rc);
+    if (style != ORC_MIE && style != ORC_GAUSS && style != ORC_YUKAWA) return ORC_EINVAL;
+    if (!(rc >= 0.0) || !isfinite(rc) || !isfinite(params[0])) return ORC_EINVAL;
+    if (style == ORC_MIE && !(params[1] > 0.0 && params[3] > 0.0 && params[2] > params[3]))
+        return ORC_EINVAL;
+    if (style == ORC_GAUSS && !(params[1] > 0.0)) return ORC_EINVAL;
+    if (style == ORC_YUKAWA && !(params[1] >= 0.0)) return ORC_EINVAL;
+    int k1 = pair_index(s, a, b), k2 = pair_index(s, b, a);
+    s->rc[k1] = s->rc[k2] = rc;
+    s->is_set[k1] = s->is_set[k2] = 1;
+    s->style[k1] = s->style[k2] = style;
+    for (int c = 0; c < 4; ++c) s->par[4 * k1 + c] = s->par[4 * k2 + c] = params[c];
     s->list_valid = 0;
     s->force_valid = 0;
     return ORC_OK;
@@ -357,9 +429,16 @@ static int compute_forces(orc_sys *s)
         int k = pair_index(s, s->type[i], s->type[j]);
         double rcut2 = s->rc[k] * s->rc[k];
         if (!(r2 < rcut2)) continue;
-        double ff = lj_force_factor(s->eps[k], s->sig[k], r2);
-        double u = lj_energy(s->eps[k], s->sig[k], r2) -
-                   lj_energy(s->eps[k], s->sig[k], rcut2);
+        double ff, u;
+        if (s->style[k] == ORC_LJ) {
+            ff = lj_force_factor(s->eps[k], s->sig[k], r2);
+            u = lj_energy(s->eps[k], s->sig[k], r2) -
+                lj_energy(s->eps[k], s->sig[k], rcut2);
+        } else {
+            const double *p = s->par + 4 * k;
+            ff = form_force_factor(s->style[k], p, r2);
+            u = form_energy(s->style[k], p, r2) - form_energy(s->style[k], p, rcut2);
+        }
         double rij[3] = {-d[0], -d[1], -d[2]};  /* x_i - x_j */
         for (int a = 0; a < 3; ++a) {
             s->f[3 * i + a] += ff * rij[a];

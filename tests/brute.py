@@ -93,3 +93,51 @@ def lj_pair(r, eps=1.0, sig=1.0, rc=2.5):
     u = 4.0 * eps * (sr6 * sr6 - sr6) - 4.0 * eps * (sc6 * sc6 - sc6)
     f = 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r
     return u, f
+
+
+def _form(style, p, r):
+    """Pair energy and -(du/dr) of the other forms at distance r (arrays), written from the
+    textbook expressions independently of the oracle."""
+    if style == "mie":
+        eps, sig, n, m = p
+        c = (n / (n - m)) * (n / m) ** (m / (n - m))
+        x = sig / r
+        return c * eps * (x ** n - x ** m), c * eps * (n * x ** n - m * x ** m) / r
+    if style == "gauss":
+        eps, sig = p[:2]
+        g = eps * np.exp(-0.5 * (r / sig) ** 2)
+        return g, g * r / sig ** 2
+    if style == "yukawa":
+        eps, kappa = p[:2]
+        e = eps * np.exp(-kappa * r)
+        return e / r, e * (1.0 + kappa * r) / r ** 2
+    eps, sig = p[:2]
+    x6 = (sig / r) ** 6
+    return 4 * eps * (x6 * x6 - x6), 24 * eps * (2 * x6 * x6 - x6) / r
+
+
+def brute_fuw_style(box, pos, style, params, rc):
+    """Forces, total energy and virial of one pair form (single type), truncated at rc and
+    energy-shifted there, over every pair (i < j) within rc."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    F = np.zeros((n, 3))
+    U = 0.0
+    W = np.zeros(6)
+    u_c, _ = _form(style, params, np.array([rc]))
+    for i in range(n - 1):
+        d = np.stack([_min_image(pos[i + 1:, a] - pos[i, a], box[a]) for a in range(3)], 1)
+        r = np.sqrt((d * d).sum(1))
+        inside = r < rc
+        d, r = d[inside], r[inside]
+        j = np.nonzero(inside)[0] + i + 1
+        u, mdu = _form(style, params, r)
+        U += float((u - u_c[0]).sum())
+        fij = (mdu / r)[:, None] * (-d)  # on i, along x_i - x_j
+        F[i] += fij.sum(0)
+        np.add.at(F, j, -fij)
+        rij = -d
+        W += np.stack([rij[:, 0] * fij[:, 0], rij[:, 0] * fij[:, 1], rij[:, 0] * fij[:, 2],
+                       rij[:, 1] * fij[:, 1], rij[:, 1] * fij[:, 2], rij[:, 2] * fij[:, 2]],
+                      1).sum(0)
+    return F, U, W

@@ -13,7 +13,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle_md.c")
 PIN_TESTS = ["tests/test_oracle_invariants.py", "tests/test_oracle_vs_brute.py",
-             "tests/test_six_particle.py", "tests/test_oracle_nvt.py"]
+             "tests/test_six_particle.py", "tests/test_oracle_nvt.py",
+             "tests/test_oracle_styles.py"]
 
 MUTANTS = {
     "drop_energy_shift": ("lj_energy(s->eps[k], s->sig[k], r2) -\n                   lj_energy(",
@@ -37,6 +38,13 @@ MUTANTS = {
     "nvt_scale_full_step": ("exp(-0.5 * s->dt * s->xi)", "exp(-s->dt * s->xi)"),
     "nvt_kinetic_not_rescaled": ("K = sc * sc * K;", "K = sc * K;"),
     "nvt_dof_without_momentum": ("return 3.0 * (double)s->n - 3.0;", "return 3.0 * (double)s->n;"),
+    # other pair forms
+    "mie_prefactor": ("double c = (n / (n - m)) * pow(n / m, m / (n - m));\n        double sr2 = (p[1] * p[1]) / r2;\n        return c * p[0] * (n *",
+                      "double c = (m / (n - m)) * pow(n / m, m / (n - m));\n        double sr2 = (p[1] * p[1]) / r2;\n        return c * p[0] * (n *"),
+    "gauss_force_missing_width": ("return p[0] / (p[1] * p[1]) * exp(", "return p[0] * exp("),
+    "yukawa_force_sign": ("(1.0 + p[1] * r) / (r2 * r)", "(1.0 - p[1] * r) / (r2 * r)"),
+    "form_energy_shift_dropped": ("u = form_energy(s->style[k], p, r2) - form_energy(",
+                                  "u = form_energy(s->style[k], p, r2) - 0.0 * form_energy("),
     "nvt_end_half_step_dropped": ("if (s->nvt) thermostat_half(s);\n        s->steps += 1;",
                                   "s->steps += 1;"),
 }
