@@ -17,8 +17,8 @@ PIN_TESTS = ["tests/test_oracle_invariants.py", "tests/test_oracle_vs_brute.py",
              "tests/test_oracle_styles.py"]
 
 MUTANTS = {
-    "drop_energy_shift": ("lj_energy(s->eps[k], s->sig[k], r2) -\n                   lj_energy(",
-                          "lj_energy(s->eps[k], s->sig[k], r2) -\n                   0.0 * lj_energy("),
+    "drop_energy_shift": ("lj_energy(s->eps[k], s->sig[k], r2) -\n                lj_energy(",
+                          "lj_energy(s->eps[k], s->sig[k], r2) -\n                0.0 * lj_energy("),
     "force_sign_on_i": ("s->f[3 * i + a] += ff * rij[a];", "s->f[3 * i + a] -= ff * rij[a];"),
     "min_image_wrong_sign": ("if (d < -h) return d + L;", "if (d < -h) return d - L;"),
     "list_without_skin": ("double rl = s->rc[k] + s->skin;", "double rl = s->rc[k];"),
