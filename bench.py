@@ -1,33 +1,47 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the LJ MD hot path on one MI355X.
 
-Workload: single-type LJ fluid, N = 1,048,576, density 0.8442, T = 1.2, r_cut = 2.5
-(shifted), skin 0.4, dt = 0.005, velocity-Verlet NVE, synthetic seeded inputs. A "step" is
-one full MD step: fused force + integration kernel, gated list rebuild when any particle has
-moved skin/2. Timed: exactly --steps steps after --warmup steps, inputs resident in HBM,
-bracketed by device synchronisation. Prints ONE JSON line on stdout (progress on stderr).
+Headline workload: single-type LJ fluid, N = 1,048,576, density 0.8442, T = 1.2, r_cut = 2.5
+(shifted), skin 0.4, dt = 0.005, velocity-Verlet NVE, FP64, synthetic seeded inputs. A "step"
+is one full MD step: the fused force + integration kernel and the list-rebuild kernels,
+which rebuild when any particle has moved skin/2. Timed: exactly --steps steps after
+--warmup steps, inputs resident in HBM, bracketed by device synchronisation, with the
+energy, kinetic energy and virial reduced every --thermo-period steps inside the timed
+loop. Prints ONE JSON line on stdout (progress on stderr).
 
 Also reported on that line:
-  roofline      the fused force + integration kernel: algorithmic bytes per launch
-                (N * (2 * mean list length + 128): 16-bit list entries plus the per-atom
-                state) over its mean launch time, measured with HIP events on the library's
-                stream, against 8 TB/s.
+  kernels       per-step time of each kernel class, from HIP events around every launch in
+                a separate pass: the step kernel, the list build and the other rebuild
+                kernels when they rebuild (amortised over the steps), and the same kernels
+                when they return at once (no rebuild asked).
+  roofline      the dominant kernel (largest per-step time): algorithmic bytes per launch
+                over its mean launch time against 8 TB/s; `roofline_kernels` holds the
+                figure for both the fused step kernel and the list build.
   mixed         the same workload with FP32 pair arithmetic (FP64 integration and sums).
+  lj_fluid_N4000   the small correctness workload (N = 4000, FP64, 100 steps): time per step.
+  ka_mixture    the Kob-Andersen mixture (N = 262,144, density 1.2, per-pair cutoffs),
+                mixed precision, 2000 steps: atom-steps/s and its fused kernel's roofline.
+  paper_benchmark  the paper's LJ liquid benchmark (N = 64,000, density 0.382,
+                r_cut = 3.0, NVT kT = 1.2, tau = 1.0, dt = 0.005), beside the paper's own
+                figures for other hardware (context only).
   batched       512 independent replicas (N uniform in [256, 8192], density in [0.6, 0.9],
                 T in [0.8, 1.5]) advanced together in 100-step graph blocks, mixed
                 precision, beside a sample of the same replicas run one by one on the plain
                 FP64 path.
   served        Poisson request streams (N log-uniform in [512, 65536], density 0.8442,
-                T 1.2, 1000-10000 steps) through the continuous-batching loop: p50/p99
-                latency and atom-steps/s, beside the same stream served one request at a
-                time on the plain FP64 path. Arrival rates are fractions (--serve-loads) of
-                the capacity mu = batched atom-steps/s / E[N * steps].
-  cpu_baseline  the CPU FP64 oracle on a bounded sample of the same workload, on this host.
+                T 1.2, 1000-10000 steps) through the continuous-batching loop under a memory
+                budget that limits admission: p50/p99 latency and atom-steps/s at arrival
+                rates that are fractions of the capacity mu = batched atom-steps/s /
+                E[N * steps]; beside the same stream served one request at a time on the
+                plain FP64 path (each request's measured alone time replayed through the
+                same first-come first-served queue).
+  cpu_baseline  the CPU FP64 oracle on a bounded sample of the headline workload, on this
+                host (core count and CPU model stated).
 """
 
 import argparse
-import math
 import json
+import math
 import os
 import sys
 import time
@@ -40,8 +54,16 @@ if ROOT not in sys.path:
 
 METRIC = "atom-steps/s: LJ N=1M FP64 vs mixed; batched replicas; serve p50/p99"
 HBM_PEAK_GBS = 8000.0
-STATE_BYTES = 128  # count 4, x+type 28, v 24, x_build 24 read; x 24, v 24 written
-LIST_ENTRY_BYTES = 2  # 16-bit tile index per list entry
+# fused step kernel, per atom: list count 4, x+type 28, v 24, x_build 24 read; x 24, v 24
+# written; plus 2 bytes per 16-bit list entry
+STATE_BYTES = 128
+LIST_ENTRY_BYTES = 2
+# list build, per atom: the permuted state read (x 32, v 32, images and tag 16) and written
+# back with the build positions (x 32, x_build 32, v 32, images 16), the count 4 and the
+# work-order entry 2; plus 2 bytes per list entry written
+NLIST_STATE_BYTES = 80 + 112 + 4 + 2
+PAPER_CONTEXT = {"xeon_platinum_8160_24_cores": 16.1e6, "v100_fp64": 2.75e8,
+                 "unit": "particle-steps/s", "source": "paper, Section Performance"}
 
 
 def rebuild_bytes(mean_list):
@@ -70,10 +92,11 @@ def _counter_fields(tpp):
         text = open(TRAFFIC_FILE).read()
     except OSError:
         return None
+    keys = ("launch", "traffic-bytes-per-launch", "valu-wave-instructions-per-launch",
+            "kernel-source-sha256", "nlist-traffic-bytes-per-build",
+            "nlist-valu-wave-instructions-per-build")
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line
-                  and line.split(": ", 1)[0] in ("launch", "traffic-bytes-per-launch",
-                                                 "valu-wave-instructions-per-launch",
-                                                 "kernel-source-sha256"))
+                  and line.split(": ", 1)[0] in keys)
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
@@ -84,72 +107,92 @@ def _counter_fields(tpp):
     return fields
 
 
-def measured_traffic(tpp, block):
-    """HBM bytes per launch of the fused FP64 kernel (FETCH_SIZE + WRITE_SIZE, copy-calibrated)
-    from the committed counter passes, or None (see _counter_fields)."""
-    fields = _counter_fields(tpp)
-    return float(fields["traffic-bytes-per-launch"]) if fields else None
-
-
-def valu_issue(tpp, kernel_ms):
-    """VALU issue rate of the fused FP64 kernel: the committed count of wave-level VALU
-    instructions per launch over the launch time measured here, against the issue peak of one
-    VALU instruction per CU per cycle (256 CUs x 2.4 GHz; a wave64 FP64 instruction takes four
-    cycles on a 16-lane SIMD, four SIMDs per CU). None without a matching counter pass."""
-    fields = _counter_fields(tpp)
-    if not fields or "valu-wave-instructions-per-launch" not in fields:
-        return None
-    insts = float(fields["valu-wave-instructions-per-launch"])
+def valu_issue(insts, kernel_ms):
+    """VALU issue rate: wave-level VALU instructions per launch over the launch time measured
+    here, against the issue peak of one VALU instruction per CU per cycle (256 CUs x 2.4 GHz;
+    a wave64 FP64 instruction takes four cycles on a 16-lane SIMD, four SIMDs per CU)."""
     achieved = insts / (kernel_ms * 1e-3) / 1e9
     peak = 256 * 2.4
     return {"achieved": achieved, "peak": peak, "unit": "G wave-instructions/s",
             "frac": achieved / peak, "instructions_per_launch": insts}
 
 
-def run_gpu(spec, precision, steps, warmup, timing_steps):
+def kernel_breakdown(durations, units):
+    """Per-step milliseconds of each kernel class from per-launch durations of `units` timed
+    steps. A unit rebuilt the list when its list-build launch was far longer than the median
+    (most steps do not rebuild, and their gated launches return at once)."""
+    nl = durations["nlist"]
+    thr = 5.0 * float(np.median(nl))
+    active = nl > thr
+    out = {"units": int(units), "rebuilds": int(active.sum()),
+           "step_kernel": float(durations["step"].sum() / units),
+           "step_kernel_avg": float(durations["step"].mean())}
+    other = ("bin", "scan", "scatter", "gather")
+    out["build_active"] = float(nl[active].sum() / units)
+    out["other_rebuild_active"] = float(sum(durations[k][active].sum() for k in other) / units)
+    out["gated_idle"] = float(sum(durations[k][~active].sum() for k in other + ("nlist",)) / units)
+    out["per_build"] = {k: float(durations[k][active].mean()) if active.any() else None
+                        for k in other + ("nlist",)}
+    out["per_idle_launch"] = {k: float(durations[k][~active].mean()) if (~active).any() else None
+                              for k in other + ("nlist",)}
+    out["unit"] = "ms per step (per launch for per_build / per_idle_launch)"
+    return out
+
+
+def run_gpu(spec, precision, steps, warmup, timing_steps, thermo_period=0, nvt=None):
+    """Time `steps` steps of one system; then a separate pass with events around every kernel
+    launch. thermo_period > 0 reduces U, K and W every that many steps inside the timed loop."""
     import torch
 
     from paper_1308_5587_amd import ljmd
 
     g = ljmd.System.from_spec(spec, precision=precision)
+    if nvt:
+        g.set_nvt(*nvt)
     g.step(0)  # list, tuning and forces ready
     g.step(warmup)
     st0 = g.stats()
+    chunk = thermo_period if thermo_period > 0 else steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    g.step(steps)
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        g.step(k)
+        done += k
+        if thermo_period > 0:
+            g.energy()
+            g.virial()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     st1 = g.stats()
     wall = t1 - t0
-    # dominant kernel: per-launch HIP event timing in a separate pass
-    g.set_kernel_timing(True)
-    g.step(timing_steps)
-    launches, ms = g.kernel_time()
-    g.set_kernel_timing(False)
+    out = {"value": spec.n * steps / wall, "ms_per_step": 1e3 * wall / steps,
+           "rebuilds": st1["rebuilds"] - st0["rebuilds"]}
+    out["steps_per_rebuild"] = steps / out["rebuilds"] if out["rebuilds"] else None
+    if timing_steps > 0:
+        g.set_kernel_timing(True)
+        g.step(timing_steps)
+        d = g.kernel_durations()
+        g.set_kernel_timing(False)
+        units = len(d["step"])
+        out["kernels"] = kernel_breakdown(d, units)
     st2 = g.stats()
     n = spec.n
     mean_list = st2["list_entries"] / n
-    per_atom = LIST_ENTRY_BYTES * mean_list + STATE_BYTES
-    avg_ms = ms / max(1, launches)
-    achieved = n * per_atom / (avg_ms * 1e-3) / 1e9
-    rebuilds = st1["rebuilds"] - st0["rebuilds"]
+    out.update({"mean_list_length": mean_list,
+                "threads_per_particle": st2["threads_per_particle"],
+                "block_size": st2["block_size"], "nlist_capacity": st2["nlist_capacity"]})
+    if timing_steps > 0:
+        kb = out["kernels"]
+        per_atom = LIST_ENTRY_BYTES * mean_list + STATE_BYTES
+        out["step_kernel_bytes_per_atom"] = per_atom
+        out["step_kernel_gbs"] = n * per_atom / (kb["step_kernel_avg"] * 1e-3) / 1e9
+        nb = kb["per_build"]["nlist"]
+        out["nlist_bytes_per_atom"] = LIST_ENTRY_BYTES * mean_list + NLIST_STATE_BYTES
+        out["nlist_gbs"] = (n * out["nlist_bytes_per_atom"] / (nb * 1e-3) / 1e9) if nb else None
     U, K = g.energy()
-    out = {
-        "value": n * steps / wall,
-        "ms_per_step": 1e3 * wall / steps,
-        "rebuilds": rebuilds,
-        "steps_per_rebuild": steps / rebuilds if rebuilds else None,
-        "kernel_avg_ms": avg_ms,
-        "kernel_launches": launches,
-        "mean_list_length": mean_list,
-        "bytes_per_atom": per_atom,
-        "achieved_gbs": achieved,
-        "threads_per_particle": st2["threads_per_particle"],
-        "block_size": st2["block_size"],
-        "nlist_capacity": st2["nlist_capacity"],
-        "energy_per_atom": (U + K) / n,
-    }
+    out["energy_per_atom"] = (U + K) / n
     g.close()
     return out
 
@@ -178,9 +221,26 @@ def energy_drift(spec, precision, steps, every, dt=0.005):
             "e0_per_atom": e0 / spec.n}
 
 
+def _host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model}
+
+
 def run_cpu_baseline(spec, steps):
     import oracle
 
+    oracle.use_native_build()
     t0 = time.perf_counter()
     o = oracle.OracleSystem.from_spec(spec)
     o.compute()
@@ -191,8 +251,9 @@ def run_cpu_baseline(spec, steps):
     return {"value": spec.n * steps / (t2 - t1), "unit": "atom-steps/s", "cores": 1,
             "kind": "oracle",
             "sample": f"N={spec.n} fluid, {steps} NVE steps after the initial list build "
-                      f"({t1 - t0:.1f} s, excluded), single-threaded FP64 C oracle, "
-                      f"{builds} list builds in total"}
+                      f"({t1 - t0:.1f} s, excluded), {t2 - t1:.1f} s, single-threaded FP64 C "
+                      f"oracle, {builds} list builds in total",
+            "build": oracle.build_flags(native=True), "host": _host_cpu()}
 
 
 def _replica_spec(p, inputs):
@@ -200,16 +261,18 @@ def _replica_spec(p, inputs):
 
 
 def run_alone_timed(spec, nsteps, precision):
-    """One replica on the single-system path: wall time of step(nsteps) after setup."""
+    """One replica on the single-system path: wall time of create + step(nsteps) + reading
+    its results, as a request served alone takes it."""
     import torch
 
     from paper_1308_5587_amd import ljmd
 
-    g = ljmd.System.from_spec(spec, precision=precision)
-    g.step(0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    g = ljmd.System.from_spec(spec, precision=precision)
     g.step(nsteps)
+    g.state()
+    g.forces()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     g.close()
@@ -233,7 +296,7 @@ def run_batched(count, block_steps, blocks, sample):
     slots = [b.admit(s, nsteps) for s in specs]
     torch.cuda.synchronize()
     t_admit = time.perf_counter() - t0
-    b.run_block()  # warm-up block (captures the graph)
+    b.run_block()  # warm-up block (tunes, captures the graph)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(blocks):
@@ -245,10 +308,19 @@ def run_batched(count, block_steps, blocks, sample):
         assert b.slot_steps(s) == nsteps
     bst = b.stats()
     b.close()
-    # a sample of the same replicas, one by one on the plain FP64 path
+    # a sample of the same replicas, one by one on the plain FP64 path (steps only)
     idx = np.random.default_rng(5).choice(count, size=min(sample, count), replace=False)
     work = sum(specs[k].n for k in idx) * block_steps * blocks
-    t1 = sum(run_alone_timed(specs[k], block_steps * blocks, "fp64") for k in idx)
+    t1 = 0.0
+    for k in idx:
+        g = ljmd.System.from_spec(specs[k], precision="fp64")
+        g.step(0)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        g.step(block_steps * blocks)
+        torch.cuda.synchronize()
+        t1 += time.perf_counter() - ts
+        g.close()
     value = atoms * block_steps * blocks / wall
     alone = work / t1
     return {"value": value, "unit": "atom-steps/s", "replicas": count, "atoms": atoms,
@@ -268,36 +340,67 @@ def served_mean_work():
     return (n_hi - n_lo) / math.log(n_hi / n_lo) * 0.5 * (s_lo + s_hi)
 
 
-def run_served(rates, count, block_steps, loads=None):
+def fifo_replay(arrivals, service):
+    """Latencies of requests served one at a time, first come first served, each taking its
+    measured service time."""
+    free = 0.0
+    lat = []
+    for t, s in zip(arrivals, service):
+        start = max(t, free)
+        free = start + s
+        lat.append(free - t)
+    return np.array(lat), free
+
+
+def run_served(loads, mu, count, block_steps, budget, max_slots):
     from paper_1308_5587_amd import inputs, ljmd, serve
 
+    mk = lambda p: inputs.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed)  # noqa: E731
     out = []
-    for k, rate in enumerate(rates):
+    work = None
+    for load in loads:
+        rate = load * mu
         arrivals = inputs.make_arrivals(count, rate, seed=2)
-        mk = lambda p: inputs.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed)  # noqa: E731
         reqs = serve.requests_from_arrivals(arrivals, mk)
-        b = ljmd.Batch(16 << 30, 64, precision="mixed", block_steps=block_steps)
-        rep = serve.serve(b, reqs).summary()
+        work = [(r.n, r.nsteps) for r in reqs]
+        b = ljmd.Batch(budget, max_slots, precision="mixed", block_steps=block_steps)
+        rep = serve.serve(b, reqs)
         b.close()
-        log(f"[bench] served rate={rate:.3g}/s: p50 {rep['p50_latency_s']:.3f} s, "
-            f"p99 {rep['p99_latency_s']:.3f} s, {rep['atom_steps_per_s']:.4g} atom-steps/s")
+        s = rep.summary()
+        log(f"[bench] served load {load} ({rate:.3g}/s): p50 {s['p50_latency_s']:.3f} s, "
+            f"p99 {s['p99_latency_s']:.3f} s, {s['atom_steps_per_s']:.4g} atom-steps/s, "
+            f"peak resident {s['peak_resident']}, {s['refused_for_capacity']} refused for "
+            f"capacity at least once")
+        out.append({"load": load, "rate_per_s": rate, "requests": count,
+                    **{k: s[k] for k in ("p50_latency_s", "p99_latency_s", "mean_latency_s",
+                                         "atom_steps_per_s", "wall_s", "peak_resident",
+                                         "failed", "refused_for_capacity")},
+                    "_arrivals": [t for t, _ in arrivals]})
+    # one by one on the plain FP64 path: every request's alone time, measured once (the
+    # request sizes and step counts do not depend on the rate), replayed through the queue
+    log(f"[bench] served: measuring {count} requests alone on the FP64 path")
+    arrivals = inputs.make_arrivals(count, 1.0, seed=2)
+    service = [run_alone_timed(mk(p), p.steps, "fp64") for _, p in arrivals]
+    for o in out:
+        lat, end = fifo_replay(o.pop("_arrivals"), service)
+        o["one_by_one_fp64"] = {
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "atom_steps_per_s": float(sum(n * k for n, k in work) / end),
+            "method": "measured alone service times replayed first come first served"}
+    return {"budget_bytes": budget, "max_slots": max_slots, "capacity_requests_per_s": mu,
+            "mean_request_work_atom_steps": served_mean_work(), "loads": out,
+            "alone_service_s": {"mean": float(np.mean(service)), "sum": float(np.sum(service))}}
 
-        def alone(spec, nsteps):
-            g = ljmd.System.from_spec(spec, precision="fp64")
-            g.step(nsteps)
-            g.close()
 
-        reqs1 = serve.requests_from_arrivals(arrivals, mk)
-        base = serve.serve_one_by_one(alone, reqs1).summary()
-        log(f"[bench] one by one fp64 rate={rate:.3g}/s: p50 {base['p50_latency_s']:.3f} s, "
-            f"p99 {base['p99_latency_s']:.3f} s, {base['atom_steps_per_s']:.4g} atom-steps/s")
-        out.append({"rate_per_s": rate, "load": loads[k] if loads else None,
-                    "requests": count, **{k: rep[k] for k in (
-            "p50_latency_s", "p99_latency_s", "mean_latency_s", "atom_steps_per_s", "wall_s",
-            "peak_resident")},
-            "one_by_one_fp64": {k: base[k] for k in ("p50_latency_s", "p99_latency_s",
-                                                     "atom_steps_per_s", "wall_s")}})
-    return out
+def _roof(name, gbs, avg_ms, bytes_per_atom, n, per_step_ms, valu=None, traffic=None):
+    r = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": gbs / HBM_PEAK_GBS, "traffic": traffic, "kernel": name,
+         "kernel_avg_ms": avg_ms, "bytes_per_atom": bytes_per_atom, "atoms_per_launch": n,
+         "ms_per_step": per_step_ms}
+    if valu is not None:
+        r["valu_issue"] = valu
+    return r
 
 
 def main():
@@ -306,20 +409,21 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--n", type=int, default=1_048_576)
+    ap.add_argument("--thermo-period", type=int, default=100)
     ap.add_argument("--timing-steps", type=int, default=200)
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="skip the N=4000, KA and paper legs")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-blocks", type=int, default=5)
+    ap.add_argument("--batched-blocks", type=int, default=10)
     ap.add_argument("--batched-sample", type=int, default=32)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-drift", action="store_true")
-    ap.add_argument("--serve-loads", type=str, default="0.5,0.9",
+    ap.add_argument("--serve-loads", type=str, default="0.25,0.5,0.75,0.9,1.0,1.2",
                     help="arrival rates as fractions of the capacity the batched leg measured")
-    ap.add_argument("--serve-rates", type=str, default="",
-                    help="explicit arrival rates per second (instead of --serve-loads)")
-    ap.add_argument("--serve-count", type=int, default=48)
+    ap.add_argument("--serve-count", type=int, default=100)
+    ap.add_argument("--serve-budget-mib", type=int, default=384)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: multi-GPU runs (--gpus > 1) are not part of "
@@ -334,14 +438,44 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     spec = inputs.make_lj_fluid(args.n, rho=0.8442, T=1.2, seed=1)
-    log(f"[bench] fp64 N={spec.n} steps={args.steps} warmup={args.warmup}")
-    fp = run_gpu(spec, "fp64", args.steps, args.warmup, args.timing_steps)
-    log(f"[bench] fp64 {fp['value']:.4g} atom-steps/s, {fp['ms_per_step']:.4f} ms/step")
+    log(f"[bench] fp64 N={spec.n} steps={args.steps} warmup={args.warmup} "
+        f"thermo every {args.thermo_period}")
+    fp = run_gpu(spec, "fp64", args.steps, args.warmup, args.timing_steps, args.thermo_period)
+    kb = fp["kernels"]
+    log(f"[bench] fp64 {fp['value']:.4g} atom-steps/s, {fp['ms_per_step']:.4f} ms/step; "
+        f"step kernel {kb['step_kernel']:.4f}, build {kb['build_active']:.4f}, other rebuild "
+        f"{kb['other_rebuild_active']:.4f}, idle gated {kb['gated_idle']:.4f} ms/step")
     mixed = None
     if not args.no_mixed:
         log("[bench] mixed")
-        mixed = run_gpu(spec, "mixed", args.steps, args.warmup, args.timing_steps)
+        mixed = run_gpu(spec, "mixed", args.steps, args.warmup, args.timing_steps,
+                        args.thermo_period)
         log(f"[bench] mixed {mixed['value']:.4g} atom-steps/s")
+    configs = {}
+    if not args.no_configs:
+        small = inputs.make_lj_fluid(4000, rho=0.8442, T=1.2, seed=1)
+        c1 = run_gpu(small, "fp64", 100, 20, 0)
+        configs["lj_fluid_N4000"] = {"ms_per_step": c1["ms_per_step"], "value": c1["value"],
+                                     "steps": 100, "dtype": "f64", "note": "cache-resident"}
+        log(f"[bench] N=4000 fp64: {c1['ms_per_step']:.4f} ms/step")
+        ka = inputs.make_ka_mixture(262_144, seed=1)
+        c3 = run_gpu(ka, "mixed", 2000, 50, args.timing_steps)
+        configs["ka_mixture_N262144"] = {
+            "value": c3["value"], "ms_per_step": c3["ms_per_step"], "steps": 2000,
+            "dtype": "f32 pair / f64 state", "steps_per_rebuild": c3["steps_per_rebuild"],
+            "mean_list_length": c3["mean_list_length"], "kernels": c3["kernels"],
+            "roofline": _roof("k_force<mixed, FUSED, multi-type>", c3["step_kernel_gbs"],
+                              c3["kernels"]["step_kernel_avg"], c3["step_kernel_bytes_per_atom"],
+                              ka.n, c3["kernels"]["step_kernel"])}
+        log(f"[bench] KA N=262144 mixed: {c3['value']:.4g} atom-steps/s")
+        pb = inputs.make_lj_fluid(64000, rho=0.382, T=1.2, seed=1, r_cut=3.0)
+        c6 = run_gpu(pb, "fp64", 2000, 100, args.timing_steps, nvt=(1.2, 1.0))
+        configs["paper_lj_liquid_N64000_nvt"] = {
+            "value": c6["value"], "ms_per_step": c6["ms_per_step"], "steps": 2000,
+            "dtype": "f64", "ensemble": "nvt kT=1.2 tau=1.0", "density": 0.382, "r_cut": 3.0,
+            "steps_per_rebuild": c6["steps_per_rebuild"], "kernels": c6["kernels"],
+            "paper_context": PAPER_CONTEXT}
+        log(f"[bench] paper benchmark N=64000 NVT fp64: {c6['value']:.4g} atom-steps/s")
     drift = None
     if not args.no_drift:
         log("[bench] energy drift: N=2^20 over 5 tau, N=4000 over 100 tau")
@@ -362,24 +496,34 @@ def main():
             f"(one by one fp64 {batched['one_by_one_fp64']['value']:.4g})")
     served = None
     if not args.no_serve:
-        if args.serve_rates:
-            rates = [float(r) for r in args.serve_rates.split(",") if r]
-            loads = None
-        else:
-            # capacity in requests per second: the batched throughput (else the single-system
-            # one) over the mean work of a request
-            thr = batched["value"] if batched else fp["value"]
-            mu = thr / served_mean_work()
-            loads = [float(x) for x in args.serve_loads.split(",") if x]
-            rates = [x * mu for x in loads]
-            log(f"[bench] served: capacity {mu:.3g} requests/s, loads {loads}")
-        served = run_served(rates, args.serve_count, 100, loads)
+        thr = batched["value"] if batched else fp["value"]
+        mu = thr / served_mean_work()
+        loads = [float(x) for x in args.serve_loads.split(",") if x]
+        log(f"[bench] served: capacity {mu:.3g} requests/s, loads {loads}")
+        served = run_served(loads, mu, args.serve_count, 100, args.serve_budget_mib << 20, 64)
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] cpu oracle, {args.cpu_steps} steps")
         cpu = run_cpu_baseline(spec, args.cpu_steps)
         log(f"[bench] cpu {cpu['value']:.4g} atom-steps/s")
 
+    fields = _counter_fields(fp["threads_per_particle"])
+    step_valu = (valu_issue(float(fields["valu-wave-instructions-per-launch"]),
+                            kb["step_kernel_avg"])
+                 if fields and "valu-wave-instructions-per-launch" in fields else None)
+    nl_avg = kb["per_build"]["nlist"]
+    nl_valu = (valu_issue(float(fields["nlist-valu-wave-instructions-per-build"]), nl_avg)
+               if fields and "nlist-valu-wave-instructions-per-build" in fields and nl_avg
+               else None)
+    roof_step = _roof("k_force<fp64, FUSED>", fp["step_kernel_gbs"], kb["step_kernel_avg"],
+                      fp["step_kernel_bytes_per_atom"], spec.n, kb["step_kernel"], step_valu,
+                      float(fields["traffic-bytes-per-launch"]) if fields else None)
+    roof_nl = (_roof("k_nlist (list build)", fp["nlist_gbs"], nl_avg, fp["nlist_bytes_per_atom"],
+                     spec.n, kb["build_active"], nl_valu,
+                     float(fields["nlist-traffic-bytes-per-build"])
+                     if fields and "nlist-traffic-bytes-per-build" in fields else None)
+               if nl_avg else None)
+    dominant = roof_nl if (roof_nl and kb["build_active"] > kb["step_kernel"]) else roof_step
     line = {
         "metric": METRIC,
         "value": fp["value"],
@@ -395,23 +539,21 @@ def main():
         "data": "synthetic",
         "config": {"workload": "lj_fluid_N1048576_rho0.8442_fp64_nve", "n": spec.n,
                    "density": 0.8442, "T0": 1.2, "r_cut": 2.5, "skin": 0.4, "dt": 0.005,
+                   "thermo_period": args.thermo_period,
                    "threads_per_particle": fp["threads_per_particle"],
                    "block_size": fp["block_size"], "steps_per_rebuild": fp["steps_per_rebuild"],
                    "mean_list_length": fp["mean_list_length"]},
-        "roofline": {"bound": "hbm", "achieved": fp["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": fp["achieved_gbs"] / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(fp["threads_per_particle"], fp["block_size"]),
-                     "kernel": "k_force<fp64, FUSED>", "kernel_avg_ms": fp["kernel_avg_ms"],
-                     "bytes_per_atom": fp["bytes_per_atom"],
-                     "valu_issue": valu_issue(fp["threads_per_particle"], fp["kernel_avg_ms"])},
+        "roofline": dominant,
+        "roofline_kernels": [r for r in (roof_step, roof_nl) if r],
+        "kernels": kb,
         "cpu_baseline": cpu,
     }
     if mixed is not None:
         line["mixed"] = {"value": mixed["value"], "ms_per_step": mixed["ms_per_step"],
                          "dtype": "f32 pair / f64 state",
                          "speedup_vs_fp64": mixed["value"] / fp["value"],
-                         "roofline_frac": mixed["achieved_gbs"] / HBM_PEAK_GBS,
-                         "kernel_avg_ms": mixed["kernel_avg_ms"],
+                         "roofline_frac": mixed["step_kernel_gbs"] / HBM_PEAK_GBS,
+                         "kernels": mixed["kernels"],
                          "threads_per_particle": mixed["threads_per_particle"],
                          "block_size": mixed["block_size"]}
     # the whole step against the method's bytes: list + state every step, rebuild amortised
@@ -423,6 +565,8 @@ def main():
                              "frac": fp["value"] / (HBM_PEAK_GBS * 1e9 / b_step),
                              "mixed_frac": (mixed["value"] / (HBM_PEAK_GBS * 1e9 / b_step)
                                             if mixed else None)}
+    if configs:
+        line["configs"] = configs
     if drift is not None:
         line["energy_drift"] = drift
     if batched is not None:

@@ -120,11 +120,58 @@ void ljmd_system_destroy(ljmd_system *sys);
 int ljmd_pair_lj_set(ljmd_system *sys, int32_t a, int32_t b, double epsilon, double sigma,
                      double r_cut);
 
-/* Advance nsteps velocity-Verlet NVE steps on the configured stream and synchronise once
- * at the end to report status. nsteps = 0 only makes the list and forces current.
+/* Pair forms on the same skeleton (the paper lists Gaussian, Mie, WCA and Yukawa among its
+ * pair potentials, Section "Capabilities"). Each is truncated at r_cut with its energy
+ * shifted to 0 there and its force not shifted; F on i = f(r) (x_i - x_j):
+ *   LJMD_PAIR_LJ      params (eps, sigma): the LJ form above (as ljmd_pair_lj_set)
+ *   LJMD_PAIR_MIE     params (eps, sigma, n, m), n > m > 0:
+ *                     u = C eps ((s/r)^n - (s/r)^m), C = (n/(n-m)) (n/m)^(m/(n-m))
+ *   LJMD_PAIR_GAUSS   params (eps, sigma): u = eps exp(-r^2 / (2 sigma^2))
+ *   LJMD_PAIR_YUKAWA  params (eps, kappa): u = eps exp(-kappa r) / r
+ *   LJMD_PAIR_WCA     params (eps, sigma), r_cut = 0: the LJ form cut at 2^(1/6) sigma
+ *                     (purely repulsive; the shift is +eps)
+ * Every set pair of a system uses one form (the kernels evaluate one form per system);
+ * batches use the LJ form. Errors: INVAL (unknown form, wrong parameter count, out-of-range
+ * parameter, a second form in one system). */
+#define LJMD_PAIR_LJ 0
+#define LJMD_PAIR_MIE 1
+#define LJMD_PAIR_GAUSS 2
+#define LJMD_PAIR_YUKAWA 3
+#define LJMD_PAIR_WCA 4
+int ljmd_pair_set(ljmd_system *sys, int32_t a, int32_t b, int32_t form, const double *params,
+                  int32_t nparams, double r_cut);
+
+/* Advance nsteps velocity-Verlet steps (NVE, or NVT after ljmd_set_nvt) on the configured
+ * stream and synchronise once at the end to report status. nsteps = 0 only makes the list
+ * and forces current.
  * Errors: INVAL, STATE (pair unset), BOX, NONFINITE, NOMEM, DEVICE. On NONFINITE the
  * state is restored to what it was when the call began. */
 int ljmd_step(ljmd_system *sys, int64_t nsteps);
+
+/* NVT: the integrator of the paper's MD listing (Section "Capabilities": integrate.nvt with
+ * kT and tau, built on the Martyna-Tobias-Klein method). One Nose-Hoover thermostat
+ * variable xi (with "position" eta) of mass Q = N_f kT tau^2, N_f = 3n - 3, acting on
+ *   dx/dt = v,  dv/dt = F/m - xi v,  dxi/dt = (2K - N_f kT) / Q,  deta/dt = xi,
+ * integrated by the symmetric (time-reversible) splitting: each step is a thermostat half
+ * step, the velocity-Verlet step, and another thermostat half step, where a half step of
+ * length dt/2 is xi += (dt/4) G; eta += (dt/2) xi; v *= exp(-(dt/2) xi) (K scales by the
+ * square); xi += (dt/4) G, with G = (2K - N_f kT) / Q. K + U + Q xi^2 / 2 + N_f kT eta is
+ * conserved. tau = +infinity means zero coupling (the NVE step). Sets xi = eta = 0.
+ * Errors: INVAL (kT <= 0, tau <= 0, n < 2). */
+int ljmd_set_nvt(ljmd_system *sys, double kT, double tau);
+
+/* Back to NVE steps (the thermostat variables are kept but no longer used). */
+int ljmd_set_nve(ljmd_system *sys);
+
+/* Thermostat state at the current step: xi, eta and its share of the conserved quantity,
+ * Q xi^2 / 2 + N_f kT eta (all 0 under NVE or zero coupling); pointers may be NULL. */
+int ljmd_get_thermostat(ljmd_system *sys, double *xi, double *eta, double *energy);
+
+/* Set xi and eta (checkpoint/resume, reversibility checks). Errors: INVAL, STATE (not NVT). */
+int ljmd_set_thermostat(ljmd_system *sys, double xi, double eta);
+
+/* v -> -v for every particle (time-reversal checks); forces stay valid. */
+int ljmd_negate_velocities(ljmd_system *sys);
 
 /* Forces at the current positions, n x 3 host doubles, tag order. */
 int ljmd_get_forces(ljmd_system *sys, double *out);
@@ -156,6 +203,16 @@ int ljmd_set_state(ljmd_system *sys, const double *pos, const double *vel, const
 int ljmd_get_neighbor_pairs(ljmd_system *sys, int64_t *count, int32_t *pairs,
                             double *build_pos);
 
+/* The full neighbour list as the force kernel holds it: every particle's row, both
+ * directions of each pair (Section "Performance": the list the pair kernel streams).
+ * counts (n int32, tag order, nullable) receives each row's length and *total their sum;
+ * neighbors (total int32, nullable: then only sizes are returned) receives the tags of
+ * each row's entries in the order they are stored, rows in tag order. build_pos (n x 3,
+ * tag order, nullable) receives the positions the list was built from. Errors: INVAL,
+ * STATE (pair unset), BOX, DEVICE. */
+int ljmd_get_neighbor_list(ljmd_system *sys, int32_t *counts, int64_t *total,
+                           int32_t *neighbors, double *build_pos);
+
 /* Counters and tuned launch parameters. */
 int ljmd_get_stats(ljmd_system *sys, ljmd_stats *out);
 
@@ -165,6 +222,21 @@ int ljmd_get_stats(ljmd_system *sys, ljmd_stats *out);
  * event time in milliseconds since timing was switched on. */
 int ljmd_set_kernel_timing(ljmd_system *sys, int32_t on);
 int ljmd_kernel_time(ljmd_system *sys, int64_t *launches, double *total_ms);
+
+/* Per-launch durations recorded while kernel timing is on, by kernel kind: the step's force
+ * kernel (the fused force + integration kernel; under NVT the force kernel of the step) and
+ * the five list-rebuild kernels, which every step launches and which return at once unless
+ * the displacement check asked for a rebuild. *count receives the number of launches
+ * recorded since timing was switched on; ms (count floats, nullable) their durations in
+ * milliseconds, in launch order. Errors: INVAL (unknown kind). */
+#define LJMD_KERNEL_STEP 0     /* fused force + integration (NVE) or force (NVT) */
+#define LJMD_KERNEL_BIN 1      /* cell binning */
+#define LJMD_KERNEL_SCAN 2     /* cell-count scan */
+#define LJMD_KERNEL_SCATTER 3  /* permutation scatter */
+#define LJMD_KERNEL_GATHER 4   /* in-cell ordering and state gather */
+#define LJMD_KERNEL_NLIST 5    /* Verlet list build */
+#define LJMD_KERNEL_KINDS 6
+int ljmd_kernel_durations(ljmd_system *sys, int32_t kind, int64_t *count, float *ms);
 
 /* ------------------------------------------------------------------ batched replicas
  *
@@ -239,6 +311,12 @@ int ljmd_batch_read(ljmd_batch *b, int32_t slot, double *pos, double *vel, doubl
 
 /* Steps completed by the replica in a slot. */
 int ljmd_batch_slot_steps(ljmd_batch *b, int32_t slot, int64_t *steps);
+
+/* Outcome of the replica in a slot: LJMD_OK while it runs or once it finished its steps,
+ * else the status it was retired with (LJMD_E_NONFINITE: a force became non-finite;
+ * LJMD_E_BOX: a tile outgrew 16-bit indices); its results are then not readable.
+ * Errors: INVAL, STATE (empty slot). */
+int ljmd_batch_slot_status(ljmd_batch *b, int32_t slot, int32_t *status);
 
 /* Free a slot (its memory returns to the budget). */
 int ljmd_batch_release(ljmd_batch *b, int32_t slot);

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libljmd.so")
-SOURCES = ["ljmd_kernels.hip", "ljmd_host.hip", "ljmd_system.hip", "ljmd_batch.hip"]
+SOURCES = ["ljmd_kernels.hip", "ljmd_force_lj.hip", "ljmd_force_mie.hip", "ljmd_force_gauss.hip",
+           "ljmd_force_yukawa.hip", "ljmd_host.hip", "ljmd_system.hip", "ljmd_batch.hip"]
 
 # -ffp-contract=off: the distance arithmetic must not be fused (explicit fma elsewhere).
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.
@@ -27,19 +28,16 @@ def _hipcc():
     return "hipcc"
 
 
-def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
-    """Compile the sources into `out` (default: the in-tree libljmd.so); `defines` are
-    extra -D flags for building variants."""
+def build(verbose: bool = False) -> str:
+    """Compile the sources into the in-tree libljmd.so."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    tag = "" if out == LIB else "_" + os.path.splitext(os.path.basename(out))[0]
-    objdir = os.path.join(HERE, "_build" + tag)
+    objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *HIPFLAGS, *["-D" + d for d in defines], "-c", os.path.join(CSRC, src),
-               "-o", obj]
+        cmd = [hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -49,6 +47,7 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
 
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
         objs = list(ex.map(compile_one, srcs))
+    out = LIB
     tmp = out + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

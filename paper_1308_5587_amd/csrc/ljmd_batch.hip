@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -891,9 +892,10 @@ int ljmd_batch_admit(ljmd_batch *b, const ljmd_replica_spec *sp, int32_t *slot_o
     if (rc != LJMD_OK) return undo(rc);
     rc = forced_rebuild(b, {s});
     if (rc != LJMD_OK) return undo(rc);
-    // before the first block tunes the lanes per particle, keep the sorted state at t = 0:
-    // the first half step is taken again with the tuned lanes (redo_first_half_step)
-    if (!b->layout_fixed && !b->cfg.threads_per_particle) {
+    // before the first block tunes lanes or workgroup size, keep the sorted state at t = 0:
+    // the tuning trials rebuild lists at the drifted positions, so the first half step is
+    // taken again afterwards from this state (redo_first_half_step)
+    if (!b->layout_fixed && (!b->cfg.threads_per_particle || !b->cfg.block_size)) {
         rc = copy_range(b, b->slots[s], true);
         if (rc != LJMD_OK) return undo(rc);
     }
@@ -961,10 +963,11 @@ int ljmd_batch_admit(ljmd_batch *b, const ljmd_replica_spec *sp, int32_t *slot_o
 namespace {
 
 // Replicas admitted before the first block took their first force evaluation and half step
-// with the default lanes per particle. The lane count orders each particle's force sum, so
-// once the block has tuned the lanes these steps are taken again with them, from the sorted
-// state kept at admission: every replica then follows the trajectory its alone run computes
-// with the same lanes. The sequence is admission's, for all of them at once: build, forces,
+// with the default lanes per particle, and the tuning trials then rebuilt their lists (new
+// order and build points) at the drifted positions. The lane count orders each particle's
+// force sum, so once the block has tuned the lanes these steps are taken again with them,
+// from the sorted state kept at admission: every replica then follows the trajectory its
+// alone run computes with the same lanes. The sequence is admission's, for all of them at once: build, forces,
 // kick and drift, drifted positions into the current buffer, the builds the drift asks for.
 int redo_first_half_step(ljmd_batch *b, const std::vector<int> &which) {
     for (int s : which) CHK(copy_range(b, b->slots[s], false));
@@ -1022,7 +1025,9 @@ int ljmd_batch_run_block(ljmd_batch *b) {
             CHK(upload_mask(b, b->d_go, b->h_mask));
             CHK(upload_mask(b, b->d_only, b->h_mask));
             CHK(tune(b, running));
-            if (!b->cfg.threads_per_particle && b->tpp != 2) CHK(redo_first_half_step(b, running));
+            // the trials re-sorted the replicas and moved their build points: every one
+            // takes its first half step again from its state at t = 0
+            CHK(redo_first_half_step(b, running));
             HIPCHK(hipMemsetAsync(b->d_req, 0, 2 * sizeof(int) * b->max_slots, b->stream));
         }
         b->layout_fixed = true;
@@ -1122,18 +1127,35 @@ int ljmd_batch_slot_steps(ljmd_batch *b, int32_t s, int64_t *steps) {
     return LJMD_OK;
 }
 
-int ljmd_batch_read(ljmd_batch *b, int32_t s, double *pos, double *vel, double *force,
-                    double *energy, double *virial) {
+int ljmd_batch_slot_status(ljmd_batch *b, int32_t s, int32_t *status) {
+    if (!b || !status) return set_err(LJMD_E_INVAL, "null argument");
+    if (s < 0 || s >= b->max_slots || !b->slots[s].used) return set_err(LJMD_E_STATE, "slot %d is empty", s);
+    *status = b->slots[s].error;
+    return LJMD_OK;
+}
+
+namespace {
+
+int check_readable(ljmd_batch *b, int32_t s) {
     if (!b) return set_err(LJMD_E_INVAL, "null handle");
     if (s < 0 || s >= b->max_slots || !b->slots[s].used) return set_err(LJMD_E_STATE, "slot %d is empty", s);
-    Slot &sl = b->slots[s];
+    const Slot &sl = b->slots[s];
     if (!sl.done) return set_err(LJMD_E_STATE, "replica in slot %d has not finished", s);
     if (sl.error) return set_err(sl.error, "replica in slot %d was retired with status %d", s, sl.error);
+    return LJMD_OK;
+}
+
+// Results of a finished slot through `stage` (3 n doubles of device staging): positions,
+// velocities and forces are put in tag order there, then copied to the host; energy and virial
+// come from a force evaluation of the replica alone and the fixed-order reductions, in the
+// batch's own buffers.
+int read_slot(ljmd_batch *b, int32_t s, double *stage, double *pos, double *vel, double *force,
+              double *energy, double *virial) {
+    Slot &sl = b->slots[s];
     const size_t N = (size_t)sl.n;
-    CHK(ensure_stage(b, 6 * N));
     auto fetch = [&](const double4 *src, double *out) {
-        CHK(launch_chk(launch_unsort_vec(b->stream, src, b->d_img, sl.poff, sl.n, b->d_stage), "unsort"));
-        HIPCHK(hipMemcpyAsync(out, b->d_stage, 3 * N * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+        CHK(launch_chk(launch_unsort_vec(b->stream, src, b->d_img, sl.poff, sl.n, stage), "unsort"));
+        HIPCHK(hipMemcpyAsync(out, stage, 3 * N * sizeof(double), hipMemcpyDeviceToHost, b->stream));
         return sync(b);
     };
     if (pos) CHK(fetch(b->d_pos[b->cur], pos));
@@ -1166,6 +1188,16 @@ int ljmd_batch_read(ljmd_batch *b, int32_t s, double *pos, double *vel, double *
     }
     return LJMD_OK;
 }
+
+}  // namespace
+
+int ljmd_batch_read(ljmd_batch *b, int32_t s, double *pos, double *vel, double *force,
+                    double *energy, double *virial) {
+    CHK(check_readable(b, s));
+    CHK(ensure_stage(b, 3 * (size_t)b->slots[s].n));
+    return read_slot(b, s, b->d_stage, pos, vel, force, energy, virial);
+}
+
 
 int ljmd_batch_get_stats(ljmd_batch *b, ljmd_batch_stats *out) {
     if (!b || !out) return set_err(LJMD_E_INVAL, "null argument");

@@ -57,6 +57,10 @@ struct PairTable {
 };
 void make_pair_table(int ntypes, const double *eps, const double *sig, const double *rc,
                      double skin, PairTable *out);
+// The table of another pair form (STYLE_MIE, STYLE_GAUSS, STYLE_YUKAWA) from its parameters,
+// 4 per pair: (eps, sigma, n, m), (eps, sigma), (eps, kappa).
+void make_form_table(int ntypes, int style, const double *par, const double *rc, double skin,
+                     PairTable *out);
 
 // Cell grid, bricks and halos of one replica, with replica-local cell indices.
 struct ReplicaGrid {

@@ -88,6 +88,46 @@ void make_pair_table(int nt, const double *eps, const double *sig, const double 
     }
 }
 
+void make_form_table(int nt, int style, const double *par, const double *rc, double skin,
+                     PairTable *out) {
+    out->coef.assign((size_t)nt * nt, PairCoef{});
+    out->rl2.assign((size_t)nt * nt, 0.0);
+    out->rl_max = 0.0;
+    for (int k = 0; k < nt * nt; ++k) {
+        PairCoef c{};
+        const double *p = par + 4 * (size_t)k;
+        const double r = rc[k];
+        if (r > 0.0) {
+            const double rl = r + skin;
+            c.rc2 = r * r;
+            c.rl2 = rl * rl;
+            out->rl_max = std::max(out->rl_max, rl);
+            if (style == STYLE_MIE) {
+                const double e = p[0], sg = p[1], n = p[2], m = p[3];
+                const double cm = (n / (n - m)) * std::pow(n / m, m / (n - m));
+                c.lj1 = cm * e * n * std::pow(sg, n);
+                c.lj2 = cm * e * m * std::pow(sg, m);
+                c.lj3 = 0.5 * n;
+                c.lj4 = 0.5 * m;
+                c.shift = cm * e * (std::pow(sg / r, n) - std::pow(sg / r, m));
+            } else if (style == STYLE_GAUSS) {
+                const double e = p[0], sg = p[1];
+                c.lj1 = e / (sg * sg);
+                c.lj2 = -1.0 / (2.0 * sg * sg);
+                c.lj3 = e;
+                c.shift = e * std::exp(-c.rc2 / (2.0 * sg * sg));
+            } else {  // Yukawa
+                const double e = p[0], kappa = p[1];
+                c.lj1 = e;
+                c.lj2 = kappa;
+                c.shift = e * std::exp(-kappa * r) / r;
+            }
+        }
+        out->coef[k] = c;
+        out->rl2[k] = c.rl2;
+    }
+}
+
 // ------------------------------------------------------------------ cell grid and bricks
 
 static uint64_t spread3(uint64_t v) {  // 10-bit value -> every third bit

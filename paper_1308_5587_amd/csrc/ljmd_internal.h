@@ -8,8 +8,8 @@
 
 namespace ljmd {
 
-// Per type pair coefficients of the truncated-and-shifted LJ potential, FP64.
-// rc2 = r_cut^2 and rl2 = (r_cut + skin)^2 are 0 for a disabled pair.
+// Per type pair coefficients of the truncated-and-shifted pair form, FP64.
+// rc2 = r_cut^2 and rl2 = (r_cut + skin)^2 are 0 for a disabled pair. For the LJ form:
 struct PairCoef {
     double rc2;
     double rl2;
@@ -17,9 +17,10 @@ struct PairCoef {
     double lj2;    // 24 eps sig^6
     double lj3;    // 4 eps sig^12    energy: u = r^-6 (lj3 r^-6 - lj4) - shift
     double lj4;    // 4 eps sig^6
-    double shift;  // 4 eps ((sig/r_cut)^12 - (sig/r_cut)^6)
+    double shift;  // 4 eps ((sig/r_cut)^12 - (sig/r_cut)^6), the energy at r_cut
     double pad;
 };
+// (the other forms keep their coefficients in lj1..lj4 too: see form64 in ljmd_force.h)
 
 // Device status block (one per system or batch). Rebuild requests live in a separate
 // per-replica array: req[2 r + b] for replica r, b the position buffer just written.
@@ -100,16 +101,13 @@ constexpr int TILE_TARGET = 1536;
 constexpr int LJMD_MAX_TYPES_DEVICE = 16;     // type count the kernels' tables allow
 constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr int TILE_INDEX_MAX = 65535; // 16-bit tile indices
-#ifndef LJMD_FORCE_BATCH
-#define LJMD_FORCE_BATCH 2
-#endif
-constexpr int FORCE_BATCH = LJMD_FORCE_BATCH;  // neighbour positions requested together (1, 2, 4, 8)
-#ifndef LJMD_BUILD_BATCH
-#define LJMD_BUILD_BATCH 2
-#endif
-constexpr int BUILD_BATCH = LJMD_BUILD_BATCH;  // candidate rounds tested together in the build
+constexpr int FORCE_BATCH = 2;  // neighbour positions requested together (1, 2, 4, 8)
+constexpr int BUILD_BATCH = 2;  // candidate rounds tested together in the build
 
 enum { MODE_EVAL = 0, MODE_FUSED = 1, MODE_FINAL = 2 };
+// Pair forms (one per system; the batch uses LJ). The PairCoef fields lj1..lj4 hold each
+// form's coefficients (see form64 in ljmd_force.h).
+enum { STYLE_LJ = 0, STYLE_MIE = 1, STYLE_GAUSS = 2, STYLE_YUKAWA = 3, STYLE_COUNT = 4 };
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };
 
 constexpr int LJMD_MAX_TYPES_DEV = 16; // equals LJMD_MAX_TYPES of the public header
@@ -164,8 +162,24 @@ struct ForceArgs {
     int npad, cap, lshift, nbrick, tile_cap, max_ntypes;
 };
 
+// NVT thermostat scalars on the device (doubles): the state at the last step boundary
+// (xi, eta), the scale factor of the last end-of-step thermostat half step that the stored
+// velocities still lack (1 between calls), the thermostat half step that opens the next step
+// (its scale factor, and xi and eta after it), and the kinetic energy after the last scaling.
+enum { TH_XI = 0, TH_ETA = 1, TH_SPEND = 2, TH_SB = 3, TH_XIB = 4, TH_ETAB = 5, TH_K = 6,
+       TH_COUNT = 8 };
+
+struct NvtParams {
+    double dt;
+    double invQ;   // 1 / Q, Q = N_f kT tau^2; 0 for zero coupling
+    double g;      // N_f kT
+    int np;        // partial sums to reduce
+    int begin_only;
+};
+
 struct KickDriftArgs {
     const RepParams *reps;
+    const double *scale;     // NVT: velocities are first scaled by scale[0] * scale[1] (or null)
     const int *prep;         // replica of each particle (null: replica 0)
     const double4 *pos_in;
     double4 *pos_out;
@@ -215,11 +229,25 @@ hipError_t launch_upload(hipStream_t s, const double *pos, const double *vel, co
                          int poff);
 hipError_t launch_kick_drift(hipStream_t s, const KickDriftArgs &a);
 hipError_t launch_force(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
-                        bool energy, int block);
-hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a);
+                        bool energy, int block, int style = STYLE_LJ);
+hipError_t launch_force_lj(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                           bool energy, int block);
+hipError_t launch_force_mie(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                            bool energy, int block);
+hipError_t launch_force_gauss(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                              bool energy, int block);
+hipError_t launch_force_yukawa(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                               bool energy, int block);
+hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev = nullptr);
 hipError_t launch_reduce(hipStream_t s, const double *u, const double *w, const double *ke,
                          const double4 *vel, int poff, int n, double *partials, int nblocks_max,
                          double *out);
+hipError_t launch_ke_partials(hipStream_t s, const double4 *vel, int poff, int n,
+                              double *partials, int nblocks_max, int *np_out);
+hipError_t launch_nvt_thermo(hipStream_t s, const double *partials, const NvtParams &p,
+                             double *th);
+hipError_t launch_nvt_finalize(hipStream_t s, double4 *vel, int poff, int n, double *th);
+hipError_t launch_negate_vel(hipStream_t s, double4 *vel, int poff, int n);
 hipError_t launch_unsort_vec(hipStream_t s, const double4 *src, const int4 *img, int poff,
                              int n, double *dst);
 hipError_t launch_unsort_img(hipStream_t s, const int4 *img, int poff, int n, int *dst);

@@ -13,232 +13,11 @@
 //   img    int4    (image x, y, z, tag)
 //   xb     double4 positions at the last list build
 //   nlist  uint16 indices into the particle's brick tile (see nl_slot for the layout).
-#include "ljmd_internal.h"
+//
+// The force kernels themselves are in ljmd_force.h (one translation unit per pair form).
+#include "ljmd_device.h"
 
 namespace ljmd {
-
-// ---------------------------------------------------------------- arithmetic helpers
-
-// Minimum image of a coordinate difference d in (-L, L): subtract k L with k = rint(d/L).
-// For |d| away from L/2 by more than a few ulps this equals the branch form "if d >= L/2
-// subtract L, else if d < -L/2 add L" bit for bit (fma(-k, L, d) rounds d - L once, as the
-// branch form does); within a few ulps of L/2 the two may pick different images, both of
-// length ~L/2, which is beyond every cutoff and list radius.
-__device__ __forceinline__ double mi_rint(double d, double L, double invL) {
-    double k = __builtin_rint(d * invL);
-    return __builtin_fma(-k, L, d);
-}
-
-// Branch form of the minimum image, used where a list radius may reach L/2.
-__device__ __forceinline__ double mi_branch(double d, double L) {
-    double h = 0.5 * L;
-    double up = d - L;
-    double dn = d + L;
-    return d >= h ? up : (d < -h ? dn : d);
-}
-
-__device__ __forceinline__ double r2_canon(double x, double y, double z) {
-    double xx = x * x;
-    double yy = y * y;
-    double zz = z * z;
-    double t = xx + yy;
-    return t + zz;
-}
-
-// 1/x in FP64: the hardware reciprocal estimate (relative error below 5e-8 on gfx950) refined
-// by one Newton step, which squares the error: below 3e-15 relative (measured over 2^20
-// arguments in [0.3, 12]; a second step reproduces the correctly rounded quotient).
-__device__ __forceinline__ double rcp64(double x) {
-    const double y = __builtin_amdgcn_rcp(x);
-    const double e = __builtin_fma(-x, y, 1.0);
-    return __builtin_fma(y, e, y);
-}
-
-// The image of coordinate x nearest c: x - L rint((x - c) / L), rounded once; x itself when
-// it already is that image.
-__device__ __forceinline__ double near_image(double x, double c, double L, double invL) {
-    const double k = __builtin_rint((x - c) * invL);
-    return __builtin_fma(-k, L, x);
-}
-
-// Workgroup b of nb is dispatched to XCD (b mod 8). Map each XCD to a contiguous range
-// of logical tiles so that spatial neighbours share an L2.
-__device__ __forceinline__ int xcd_remap(int b, int nb) {
-    int per = nb >> 3, rem = nb & 7;
-    int x = b & 7, idx = b >> 3;
-    return x * per + (x < rem ? x : rem) + idx;
-}
-
-__device__ __forceinline__ void wrap_coord(double &x, int &im, double L) {
-    if (x >= L) {
-        x = x - L;
-        im += 1;
-    } else if (x < 0.0) {
-        x = x + L;
-        im -= 1;
-        if (x >= L) {  // x + L rounded up to L: the particle sits at 0 in its old image
-            x = 0.0;
-            im += 1;
-        }
-    }
-}
-
-// List slot of entry k of particle q with 2^ls lanes per particle: lanes own chunks of 8
-// consecutive 16-bit entries, lane l holds chunks l, l + 2^ls, ...; for chunk index c the
-// lanes of consecutive particles are adjacent, so a wavefront reads 64 x 16 contiguous bytes.
-// In closed form: slot = (k >> (3 + ls)) * (npad << (3 + ls)) + (q << (3 + ls))
-//                        + (k & (2^(3 + ls) - 1)).
-__device__ __forceinline__ size_t nl_slot(int q, int k, int npad, int ls) {
-    const int sh = 3 + ls;
-    return (size_t)((unsigned)k >> sh) * ((size_t)npad << sh) + ((size_t)q << sh) +
-           (size_t)(k & ((1 << sh) - 1));
-}
-
-// ---------------------------------------------------------------- brick tiles
-
-// Offsets of a brick's tile: tile atom k belongs to halo cell h with off[h] <= k < off[h+1]
-// and is the particle start[h] + (k - off[h]) of the sorted order.
-struct TileSmem {
-    int off[HALO_MAX + 1];
-    int start[HALO_MAX];
-    int shift[HALO_MAX];
-    int nhalo;
-    int total;
-};
-
-// Wavefront 0 reads the halo cells (lane h, h < nhalo) and scans their atom counts.
-__device__ __forceinline__ void tile_setup(const BrickInfo &bi, const HaloCell *halo_b,
-                                           const int *cell_start, TileSmem &t) {
-    if (threadIdx.x < 64) {
-        const int h = threadIdx.x;
-        int cnt = 0;
-        if (h < bi.nhalo) {
-            const HaloCell hc = halo_b[h];
-            const int st = cell_start[hc.rank];
-            cnt = cell_start[hc.rank + 1] - st;
-            t.start[h] = st;
-            t.shift[h] = hc.shift;
-        }
-        int v = cnt;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(v, o);
-            if (h >= o) v += u;
-        }
-        t.off[h + 1] = v;
-        if (h == 0) {
-            t.off[0] = 0;
-            t.nhalo = bi.nhalo;
-        }
-        if (h == 63) t.total = v;
-    }
-    __syncthreads();
-}
-
-// Halo cell of tile atom k (0 <= k < total): the h with off[h] <= k < off[h+1].
-__device__ __forceinline__ int tile_cell(const TileSmem &t, int k) {
-    int lo = 0, hi = t.nhalo;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (t.off[mid] <= k) lo = mid;
-        else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ int tile_global(const TileSmem &t, int k) {
-    const int h = tile_cell(t, k);
-    return t.start[h] + (k - t.off[h]);
-}
-
-// Brick centre and the axes to centre while staging (CENTER bits not already wrap-free).
-struct Centre {
-    double c[3];
-    int mask;
-};
-
-__device__ __forceinline__ Centre brick_centre(const BrickInfo &bi) {
-    Centre ce;
-    ce.mask = ((bi.dims >> CENTER_SHIFT) & 7) & ~((bi.dims >> MI_FREE_SHIFT) & 7);
-    for (int a = 0; a < 3; ++a) ce.c[a] = bi.centre[a];
-    return ce;
-}
-
-__device__ __forceinline__ double4 centred(double4 p, const Centre &ce, const RepParams &P) {
-    if (ce.mask & 1) p.x = near_image(p.x, ce.c[0], P.L[0], P.invL[0]);
-    if (ce.mask & 2) p.y = near_image(p.y, ce.c[1], P.L[1], P.invL[1]);
-    if (ce.mask & 4) p.z = near_image(p.z, ce.c[2], P.L[2], P.invL[2]);
-    return p;
-}
-
-// The same with the axes fixed at compile time (CM = the centring mask).
-template <int CM>
-__device__ __forceinline__ double4 centred_t(double4 p, const Centre &ce, const RepParams &P) {
-    if (CM & 1) p.x = near_image(p.x, ce.c[0], P.L[0], P.invL[0]);
-    if (CM & 2) p.y = near_image(p.y, ce.c[1], P.L[1], P.invL[1]);
-    if (CM & 4) p.z = near_image(p.z, ce.c[2], P.L[2], P.invL[2]);
-    return p;
-}
-
-// Copy the tile's atoms (x, y, z, type) into LDS as double4 records: blockDim / 64
-// consecutive threads copy one halo cell's atoms (consecutive in memory). The coordinates
-// on the axes in CM are moved to their image nearest the brick centre.
-template <int CM = 0>
-__device__ __forceinline__ void tile_stage(const TileSmem &t, const double4 *pos, double4 *st,
-                                           const Centre *ce = nullptr,
-                                           const RepParams *P = nullptr) {
-    const int per = blockDim.x >= 64 ? (int)blockDim.x / 64 : 1;
-    const int sub = threadIdx.x % per;
-    for (int h = threadIdx.x / per; h < t.nhalo; h += (int)blockDim.x / per) {
-        const int o = t.off[h];
-        const int m = t.off[h + 1] - o;
-        const double4 *src = pos + t.start[h];
-        // four loads in flight per thread before the LDS stores (an index past the cell
-        // reads its first atom, k0 < m, and is not stored)
-        for (int k0 = sub; k0 < m; k0 += 4 * per) {
-            const int k1 = k0 + per, k2 = k0 + 2 * per, k3 = k0 + 3 * per;
-            double4 p0 = src[k0];
-            double4 p1 = src[k1 < m ? k1 : k0];
-            double4 p2 = src[k2 < m ? k2 : k0];
-            double4 p3 = src[k3 < m ? k3 : k0];
-            if (CM) {
-                p0 = centred_t<CM>(p0, *ce, *P);
-                p1 = centred_t<CM>(p1, *ce, *P);
-                p2 = centred_t<CM>(p2, *ce, *P);
-                p3 = centred_t<CM>(p3, *ce, *P);
-            }
-            st[o + k0] = p0;
-            if (k1 < m) st[o + k1] = p1;
-            if (k2 < m) st[o + k2] = p2;
-            if (k3 < m) st[o + k3] = p3;
-        }
-    }
-    __syncthreads();
-}
-
-// Load a brick's tile offsets from the table written by the list build.
-__device__ __forceinline__ void tile_load(const int *tab, TileSmem &t) {
-    for (int k = threadIdx.x; k < TILE_TAB; k += blockDim.x) {
-        const int v = tab[k];
-        if (k <= 64) t.off[k] = v;
-        else if (k < 129) t.start[k - 65] = v;
-        else t.nhalo = v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) t.total = t.off[t.nhalo];
-    __syncthreads();
-}
-
-// Store a brick's tile offsets for the force kernels (after tile_setup).
-__device__ __forceinline__ void tile_save(const TileSmem &t, int *tab) {
-    for (int k = threadIdx.x; k < TILE_TAB; k += blockDim.x) {
-        int v;
-        if (k <= 64) v = t.off[k];
-        else if (k < 129) v = (k - 65 < t.nhalo) ? t.start[k - 65] : 0;
-        else v = t.nhalo;
-        tab[k] = v;
-    }
-}
 
 // ---------------------------------------------------------------- upload (create / set_state)
 
@@ -302,6 +81,13 @@ __global__ void __launch_bounds__(256) k_kick_drift(const KickDriftArgs a) {
             double4 v = a.vel[q];
             const double4 f = a.force[q];
             const double hm = P.half_dt * v.w;
+            if (a.scale) {
+                // NVT: the thermostat half steps between the last kick and this one
+                const double S = a.scale[0] * a.scale[1];
+                v.x = S * v.x;
+                v.y = S * v.y;
+                v.z = S * v.z;
+            }
             v.x = __builtin_fma(hm, f.x, v.x);
             v.y = __builtin_fma(hm, f.y, v.y);
             v.z = __builtin_fma(hm, f.z, v.z);
@@ -332,402 +118,16 @@ hipError_t launch_kick_drift(hipStream_t s, const KickDriftArgs &a) {
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------- force kernel family
-
-template <int TPP>
-__device__ __forceinline__ double lane_sum(double v) {
-#pragma unroll
-    for (int o = TPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, TPP);
-    return v;
-}
-template <int TPP>
-__device__ __forceinline__ float lane_sum(float v) {
-#pragma unroll
-    for (int o = TPP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, TPP);
-    return v;
-}
-
-// Accumulators of one lane. FP64 path: everything double. Mixed path: force in FP32,
-// energy and virial in FP64.
-template <int PREC>
-struct Acc;
-template <>
-struct Acc<PREC_FP64> {
-    double fx = 0, fy = 0, fz = 0;
-};
-template <>
-struct Acc<PREC_MIXED> {
-    float fx = 0, fy = 0, fz = 0;
-};
-
-// One pair inside the cutoff: add the LJ force on i (and, with ENERGY, half the pair
-// energy and virial) for the displacement d = x_j - x_i with r2 = |d|^2.
-template <int PREC, bool ENERGY>
-__device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double dy, double dz,
-                                          double r2, Acc<PREC> &acc, double &ue, double &w0,
-                                          double &w1, double &w2, double &w3, double &w4,
-                                          double &w5) {
-    if (PREC == PREC_FP64) {
-        const double r2i = rcp64(r2);
-        const double r6i = r2i * r2i * r2i;
-        const double ff = r2i * r6i * __builtin_fma(c.lj1, r6i, -c.lj2);
-        // force on i is ff * (x_i - x_j) = -ff * d
-        acc.fx = __builtin_fma(-ff, dx, acc.fx);
-        acc.fy = __builtin_fma(-ff, dy, acc.fy);
-        acc.fz = __builtin_fma(-ff, dz, acc.fz);
-        if (ENERGY) {
-            ue += 0.5 * (r6i * __builtin_fma(c.lj3, r6i, -c.lj4) - c.shift);
-            const double hf = 0.5 * ff;
-            w0 = __builtin_fma(hf * dx, dx, w0);
-            w1 = __builtin_fma(hf * dx, dy, w1);
-            w2 = __builtin_fma(hf * dx, dz, w2);
-            w3 = __builtin_fma(hf * dy, dy, w3);
-            w4 = __builtin_fma(hf * dy, dz, w4);
-            w5 = __builtin_fma(hf * dz, dz, w5);
-        }
-    } else {
-        // FP32 pair arithmetic on the exactly formed FP64 displacement
-        const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
-        const float fr2 = (float)r2;
-        const float r2i = __builtin_amdgcn_rcpf(fr2);
-        const float r6i = r2i * r2i * r2i;
-        const float l1 = (float)c.lj1, l2 = (float)c.lj2;
-        const float ff = r2i * r6i * __builtin_fmaf(l1, r6i, -l2);
-        acc.fx = __builtin_fmaf(-ff, fdx, acc.fx);
-        acc.fy = __builtin_fmaf(-ff, fdy, acc.fy);
-        acc.fz = __builtin_fmaf(-ff, fdz, acc.fz);
-        if (ENERGY) {
-            const float l3 = (float)c.lj3, l4 = (float)c.lj4;
-            const float up = r6i * __builtin_fmaf(l3, r6i, -l4);
-            ue += 0.5 * ((double)up - c.shift);
-            const double hf = 0.5 * (double)ff;
-            w0 = __builtin_fma(hf * (double)fdx, (double)fdx, w0);
-            w1 = __builtin_fma(hf * (double)fdx, (double)fdy, w1);
-            w2 = __builtin_fma(hf * (double)fdx, (double)fdz, w2);
-            w3 = __builtin_fma(hf * (double)fdy, (double)fdy, w3);
-            w4 = __builtin_fma(hf * (double)fdy, (double)fdz, w4);
-            w5 = __builtin_fma(hf * (double)fdz, (double)fdz, w5);
-        }
-    }
-}
-
-// The particle passes of one brick; STAGED selects neighbour positions from the LDS tile
-// (plain LDS reads) or, for a tile larger than the LDS allocation, from global memory.
-// MIF: bit a set when no pair of the brick can wrap on axis a (the minimum image is skipped
-// there; subtracting 0 x L would give the same bits).
-template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI, bool STAGED, int MIF>
-__device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem &t,
-                                             const double4 *__restrict__ st,
-                                             const PairCoef *s_pair, const PairCoef &single,
-                                             const RepParams &P, const Centre &ce, int rep,
-                                             bool last, int first, int natoms) {
-    const int per_pass = blockDim.x / TPP;
-    const int g = threadIdx.x / TPP;
-    const int lane = threadIdx.x & (TPP - 1);
-    const double L0 = P.L[0], L1 = P.L[1], L2 = P.L[2];
-    const double iL0 = P.invL[0], iL1 = P.invL[1], iL2 = P.invL[2];
-    typedef int v4i __attribute__((ext_vector_type(4)));
-    const size_t cstride = (size_t)a.npad << a.lshift;  // 16-byte chunks between rounds
-
-    for (int p0 = 0; p0 < natoms; p0 += per_pass) {
-        const int p = p0 + g;
-        const bool active = p < natoms;
-        const int q = first + (active ? (int)a.work[first + p] : 0);
-        const double4 xi = a.pos_in[q];
-        // the staged tile is centred on the brick: so is the particle in the pair loop
-        const double4 xc = STAGED ? centred(xi, ce, P) : xi;
-        const int ti = MULTI ? (int)xi.w : 0;
-        int cnt = active ? a.nl_count[q] : 0;
-        cnt = cnt < a.cap ? cnt : a.cap;
-
-        // the integration state (velocity, build position, images) is read after the pair
-        // loop: holding it across the loop would cost 20 registers per lane and occupancy
-
-        Acc<PREC> acc;
-        double ue = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, w4 = 0.0, w5 = 0.0;
-        const v4i *row = reinterpret_cast<const v4i *>(a.nlist) + ((size_t)q << a.lshift) + lane;
-        int k0 = lane * 8;
-        v4i nxt = {0, 0, 0, 0};
-        if (k0 < cnt) nxt = __builtin_nontemporal_load(row);
-        for (; k0 < cnt; k0 += 8 * TPP) {
-            const v4i cur = nxt;
-            row += cstride;
-            if (k0 + 8 * TPP < cnt) nxt = __builtin_nontemporal_load(row);
-            const int e[8] = {cur.x & 0xffff, (cur.x >> 16) & 0xffff, cur.y & 0xffff,
-                              (cur.y >> 16) & 0xffff, cur.z & 0xffff, (cur.z >> 16) & 0xffff,
-                              cur.w & 0xffff, (cur.w >> 16) & 0xffff};
-            // entries in groups of FB: all neighbour positions of the group are requested
-            // first, then the arithmetic runs on them
-            constexpr int FB = FORCE_BATCH;
-#pragma unroll
-            for (int u0 = 0; u0 < 8; u0 += FB) {
-                double px[FB], py[FB], pz[FB];
-                int pt[FB];
-                bool pv[FB];
-#pragma unroll
-                for (int v = 0; v < FB; ++v) {
-                    const int u = u0 + v;
-                    pv[v] = k0 + u < cnt && e[u] < t.total;
-                    const int idx = pv[v] ? e[u] : 0;
-                    pt[v] = 0;
-                    if (STAGED) {
-                        const double4 pj = st[idx];
-                        px[v] = pj.x;
-                        py[v] = pj.y;
-                        pz[v] = pj.z;
-                        if (MULTI) pt[v] = (int)pj.w;
-                    } else {
-                        const double4 pj = a.pos_in[tile_global(t, idx)];
-                        px[v] = pj.x;
-                        py[v] = pj.y;
-                        pz[v] = pj.z;
-                        pt[v] = (int)pj.w;
-                    }
-                }
-#pragma unroll
-                for (int v = 0; v < FB; ++v) {
-                    const double dx = (MIF & 1) ? px[v] - xc.x : mi_rint(px[v] - xc.x, L0, iL0);
-                    const double dy = (MIF & 2) ? py[v] - xc.y : mi_rint(py[v] - xc.y, L1, iL1);
-                    const double dz = (MIF & 4) ? pz[v] - xc.z : mi_rint(pz[v] - xc.z, L2, iL2);
-                    const double r2 = r2_canon(dx, dy, dz);
-                    const PairCoef &c = MULTI ? s_pair[ti * P.ntypes + pt[v]] : single;
-                    if (pv[v] && r2 < c.rc2)
-                        pair_term<PREC, ENERGY>(c, dx, dy, dz, r2, acc, ue, w0, w1, w2, w3, w4, w5);
-                }
-            }
-        }
-
-        double fx, fy, fz;
-        if (PREC == PREC_FP64) {
-            fx = lane_sum<TPP>((double)acc.fx);
-            fy = lane_sum<TPP>((double)acc.fy);
-            fz = lane_sum<TPP>((double)acc.fz);
-        } else {
-            fx = (double)lane_sum<TPP>((float)acc.fx);
-            fy = (double)lane_sum<TPP>((float)acc.fy);
-            fz = (double)lane_sum<TPP>((float)acc.fz);
-        }
-        if (ENERGY) {
-            ue = lane_sum<TPP>(ue);
-            w0 = lane_sum<TPP>(w0);
-            w1 = lane_sum<TPP>(w1);
-            w2 = lane_sum<TPP>(w2);
-            w3 = lane_sum<TPP>(w3);
-            w4 = lane_sum<TPP>(w4);
-            w5 = lane_sum<TPP>(w5);
-        }
-        bool exceed = false;
-        if (active && lane == 0) {
-            const bool finite =
-                __builtin_isfinite(fx) && __builtin_isfinite(fy) && __builtin_isfinite(fz);
-            if (!finite) {
-                atomicOr(a.status, ST_NONFINITE);
-                if (a.rep_status) atomicOr(&a.rep_status[rep], ST_NONFINITE);
-            }
-            if (ENERGY) {
-                a.u_out[q] = ue;
-                double *w = a.w_out + 6 * (size_t)q;
-                w[0] = w0; w[1] = w1; w[2] = w2; w[3] = w3; w[4] = w4; w[5] = w5;
-            }
-            if (MODE == MODE_EVAL) {
-                a.force[q] = make_double4(fx, fy, fz, 0.0);
-            } else {
-                double4 v = a.vel[q];
-                const double hm = P.half_dt * v.w;
-                // second half kick of the current step: full-step velocity
-                v.x = __builtin_fma(hm, fx, v.x);
-                v.y = __builtin_fma(hm, fy, v.y);
-                v.z = __builtin_fma(hm, fz, v.z);
-                if (MODE == MODE_FINAL || last) {
-                    // the replica's last step: no drift; the position stays in place
-                    a.vel[q] = v;
-                    a.force[q] = make_double4(fx, fy, fz, 0.0);
-                    if (MODE == MODE_FUSED) a.pos_out[q] = xi;
-                } else {
-                    if (ENERGY) {
-                        const double m = 1.0 / v.w;
-                        a.ke_out[q] = 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
-                    }
-                    // first half kick and drift of the next step
-                    v.x = __builtin_fma(hm, fx, v.x);
-                    v.y = __builtin_fma(hm, fy, v.y);
-                    v.z = __builtin_fma(hm, fz, v.z);
-                    double4 x = xi;
-                    x.x = __builtin_fma(P.dt, v.x, x.x);
-                    x.y = __builtin_fma(P.dt, v.y, x.y);
-                    x.z = __builtin_fma(P.dt, v.z, x.z);
-                    int4 im = a.img[q];
-                    const int4 im0 = im;
-                    wrap_coord(x.x, im.x, L0);
-                    wrap_coord(x.y, im.y, L1);
-                    wrap_coord(x.z, im.z, L2);
-                    a.pos_out[q] = x;
-                    a.vel[q] = v;
-                    if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
-                    const double4 b_pre = a.xb[q];
-                    const double ex = mi_rint(x.x - b_pre.x, L0, iL0);
-                    const double ey = mi_rint(x.y - b_pre.y, L1, iL1);
-                    const double ez = mi_rint(x.z - b_pre.z, L2, iL2);
-                    exceed = r2_canon(ex, ey, ez) >= P.lim2;
-                }
-            }
-        }
-        if (MODE == MODE_FUSED) {
-            // all particles of the workgroup belong to one replica: one atomic per wavefront
-            const unsigned long long vote = __ballot(exceed);
-            if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1)
-                atomicOr(&a.req[2 * rep + (a.cur ^ 1)], 1);
-        }
-    }
-}
-
-// One workgroup per brick. The brick's tile (the atoms of its halo cells, double4 records,
-// moved to their image nearest the brick centre on the centred axes) is staged in LDS; TPP
-// lanes per particle of the brick stride through the particle's list of 16-bit tile
-// indices, 8 per 16-byte load, gathering neighbour positions from LDS. Forces are reduced
-// across the lanes with wavefront shuffles; lane 0 then finishes the particle according to
-// MODE. If a tile is larger than the replica's own tile capacity (or the LDS allocation),
-// the positions are read from global memory through the tile offsets instead, with the
-// minimum image on every axis; the capacity is the replica's, so a replica takes the same
-// path alone and in a batch.
-// Occupancy: a 48 KiB tile lets three 512-thread workgroups share a CU, which needs at most
-// 80 VGPRs (6 waves per SIMD); the single-type variants without energy fit that without
-// spilling and are held to it, the others keep their natural register count.
-template <int PREC, int TPP, int MODE, bool ENERGY, bool MULTI>
-__global__ void __launch_bounds__(512)
-__attribute__((amdgpu_waves_per_eu((ENERGY || MULTI || TPP >= 8) ? 1 : 6)))
-k_force(const ForceArgs a) {
-    extern __shared__ double4 dyn_tile[];
-    __shared__ TileSmem t;
-    // one system: XCD-contiguous brick ranges share halos in L2. A batch (the only caller
-    // with per-replica status words) launches a grid rounded up past its live bricks, so
-    // contiguous ranges would leave the XCDs of the tail idle: consecutive bricks go to
-    // different XCDs there (the dispatcher's round robin)
-    const int b = a.rep_status ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
-    const BrickInfo bi = a.bricks[b];
-    const int rep = bi.rep;
-    if (rep < 0) return;
-    const RepParams &P = a.reps[rep];
-    if (!P.active || (a.only && !a.only[rep])) return;
-    // steps left for this replica: >= 2 full step, 1 last step, 0 finished (positions kept)
-    int r_in = 2;
-    if (MODE == MODE_FUSED) {
-        if (a.rem) r_in = a.rem[2 * rep + a.cur];
-        if (b == P.boff && threadIdx.x == 0) {
-            if (a.rem) a.rem[2 * rep + (a.cur ^ 1)] = r_in > 0 ? r_in - 1 : 0;
-            a.req[2 * rep + a.cur] = 0;  // the request for this buffer was served
-        }
-    }
-    const int first = a.cell_start[bi.first_cell];
-    const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
-    if (MODE == MODE_FUSED && r_in <= 0) {
-        for (int k = threadIdx.x; k < natoms; k += blockDim.x)
-            a.pos_out[first + k] = a.pos_in[first + k];
-        return;
-    }
-    double4 *st = dyn_tile;
-    PairCoef *s_pair = reinterpret_cast<PairCoef *>(st + a.tile_cap);
-    if (MULTI)
-        for (int k = threadIdx.x; k < P.ntypes * P.ntypes; k += blockDim.x)
-            s_pair[k] = a.pair[P.pair_off + k];
-    const PairCoef single = a.pair[P.pair_off];
-    tile_load(a.tile_tab + (size_t)b * TILE_TAB, t);
-    const bool staged = t.total <= a.tile_cap && t.total <= P.tile_cap;
-    const Centre ce = brick_centre(bi);
-    if (staged) {
-        switch (ce.mask) {
-            case 1: tile_stage<1>(t, a.pos_in, st, &ce, &P); break;
-            case 2: tile_stage<2>(t, a.pos_in, st, &ce, &P); break;
-            case 3: tile_stage<3>(t, a.pos_in, st, &ce, &P); break;
-            case 4: tile_stage<4>(t, a.pos_in, st, &ce, &P); break;
-            case 5: tile_stage<5>(t, a.pos_in, st, &ce, &P); break;
-            case 6: tile_stage<6>(t, a.pos_in, st, &ce, &P); break;
-            case 7: tile_stage<7>(t, a.pos_in, st, &ce, &P); break;
-            default: tile_stage(t, a.pos_in, st); break;
-        }
-    }
-    const bool last = MODE == MODE_FUSED && r_in == 1;
-    // axes on which the pair loop takes the plain difference: wrap-free or centred (the
-    // variants that still take the minimum image there get k = 0 and the same bits)
-    const int mif = ((bi.dims >> MI_FREE_SHIFT) | (bi.dims >> CENTER_SHIFT)) & 7;
-#define LJMD_PASSES(M) \
-    force_passes<PREC, TPP, MODE, ENERGY, MULTI, true, M>(a, t, st, s_pair, single, P, ce, rep, last, first, natoms)
-    if (!staged) {
-        force_passes<PREC, TPP, MODE, ENERGY, MULTI, false, 0>(
-            a, t, st, s_pair, single, P, ce, rep, last, first, natoms);
-    } else if (MODE == MODE_FUSED) {
-        // the step kernel: a variant per set of wrap-free axes
-        switch (mif) {
-            case 7: LJMD_PASSES(7); break;
-            case 6: LJMD_PASSES(6); break;
-            case 5: LJMD_PASSES(5); break;
-            case 3: LJMD_PASSES(3); break;
-            case 4: LJMD_PASSES(4); break;
-            case 2: LJMD_PASSES(2); break;
-            case 1: LJMD_PASSES(1); break;
-            default: LJMD_PASSES(0); break;
-        }
-    } else if (mif == 7) {
-        LJMD_PASSES(7);
-    } else {
-        LJMD_PASSES(0);
-    }
-#undef LJMD_PASSES
-}
-
-// A tile capacity or type count outside the kernels' assumptions is refused before launch
-// (the LDS carve-up and the pair-table offset are derived from them).
-static bool lds_args_ok(int tile_cap, int max_ntypes, size_t smem) {
-    return tile_cap >= 64 && tile_cap <= TILE_MAX && max_ntypes >= 1 &&
-           max_ntypes <= LJMD_MAX_TYPES_DEVICE && smem <= LDS_MAX_BYTES;
-}
-
-template <int PREC, int TPP, int MODE, bool ENERGY>
-static hipError_t launch_force_t(hipStream_t s, const ForceArgs &a, int block) {
-    const size_t smem = force_lds_bytes(a.tile_cap, a.max_ntypes);
-    if (!lds_args_ok(a.tile_cap, a.max_ntypes, smem)) return hipErrorInvalidValue;
-    if (a.max_ntypes > 1)
-        hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, true>), dim3(a.nbrick), dim3(block),
-                           smem, s, a);
-    else
-        hipLaunchKernelGGL((k_force<PREC, TPP, MODE, ENERGY, false>), dim3(a.nbrick), dim3(block),
-                           smem, s, a);
-    return hipGetLastError();
-}
-
-template <int PREC, int TPP>
-static hipError_t launch_force_m(hipStream_t s, const ForceArgs &a, int mode, bool energy,
-                                 int block) {
-    switch (mode) {
-        case MODE_EVAL:
-            return energy ? launch_force_t<PREC, TPP, MODE_EVAL, true>(s, a, block)
-                          : launch_force_t<PREC, TPP, MODE_EVAL, false>(s, a, block);
-        case MODE_FUSED:
-            return energy ? launch_force_t<PREC, TPP, MODE_FUSED, true>(s, a, block)
-                          : launch_force_t<PREC, TPP, MODE_FUSED, false>(s, a, block);
-        default:
-            return launch_force_t<PREC, TPP, MODE_FINAL, false>(s, a, block);
-    }
-}
-
-template <int PREC>
-static hipError_t launch_force_p(hipStream_t s, const ForceArgs &a, int tpp, int mode,
-                                 bool energy, int block) {
-    switch (tpp) {
-        case 1: return launch_force_m<PREC, 1>(s, a, mode, energy, block);
-        case 2: return launch_force_m<PREC, 2>(s, a, mode, energy, block);
-        case 4: return launch_force_m<PREC, 4>(s, a, mode, energy, block);
-        case 8: return launch_force_m<PREC, 8>(s, a, mode, energy, block);
-        case 16: return launch_force_m<PREC, 16>(s, a, mode, energy, block);
-        default: return hipErrorInvalidValue;
-    }
-}
 
 hipError_t launch_force(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
-                        bool energy, int block) {
-    if (block < 64 || block > 512 || (block & 63)) return hipErrorInvalidValue;
-    return prec == PREC_MIXED ? launch_force_p<PREC_MIXED>(s, a, tpp, mode, energy, block)
-                              : launch_force_p<PREC_FP64>(s, a, tpp, mode, energy, block);
+                        bool energy, int block, int style) {
+    switch (style) {
+        case STYLE_LJ: return launch_force_lj(s, a, prec, tpp, mode, energy, block);
+        case STYLE_MIE: return launch_force_mie(s, a, prec, tpp, mode, energy, block);
+        case STYLE_GAUSS: return launch_force_gauss(s, a, prec, tpp, mode, energy, block);
+        case STYLE_YUKAWA: return launch_force_yukawa(s, a, prec, tpp, mode, energy, block);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // ---------------------------------------------------------------- rebuild: cell binning
@@ -1228,20 +628,27 @@ hipError_t launch_decode_list(hipStream_t s, const RebuildArgs &a, int *out) {
     return hipGetLastError();
 }
 
-hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a) {
+hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev) {
     if (!lds_args_ok(a.tile_cap, a.max_ntypes, nlist_lds_bytes(a.tile_cap, a.max_ntypes)))
         return hipErrorInvalidValue;
     const int b = 256;
     const int g = (a.n + b - 1) / b;
+    // ev (optional): six events around the five kernels, for measurement
+    if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_bin, dim3(g), dim3(b), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[1], s);
     hipLaunchKernelGGL(k_scan, dim3(a.nrep), dim3(1024), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[2], s);
     hipLaunchKernelGGL(k_scatter, dim3(g), dim3(b), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[3], s);
     hipLaunchKernelGGL(k_cell_gather, dim3(a.ncell < 8192 ? a.ncell : 8192), dim3(64), 0, s, a);
+    if (ev) (void)hipEventRecord(ev[4], s);
     const size_t smem = nlist_lds_bytes(a.tile_cap, a.max_ntypes);
     if (a.max_ntypes > 1)
         hipLaunchKernelGGL(k_nlist<true>, dim3(a.nbrick), dim3(512), smem, s, a);
     else
         hipLaunchKernelGGL(k_nlist<false>, dim3(a.nbrick), dim3(512), smem, s, a);
+    if (ev) (void)hipEventRecord(ev[5], s);
     return hipGetLastError();
 }
 
@@ -1309,6 +716,134 @@ hipError_t launch_reduce(hipStream_t s, const double *u, const double *w, const 
     hipLaunchKernelGGL(k_reduce_partials, dim3(g), dim3(RED_BLOCK), 0, s, u, w, ke, vel, poff, n,
                        partials);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_BLOCK), 0, s, partials, g, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- NVT thermostat
+
+// Kinetic energy partial sums (one per workgroup, fixed order) of particles [poff, poff + n).
+__global__ void __launch_bounds__(RED_BLOCK) k_ke_partials(const double4 *vel, int poff, int n,
+                                                            double *partials) {
+    __shared__ double s[RED_BLOCK];
+    double acc = 0.0;
+    const int stride = gridDim.x * blockDim.x;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const double4 v = vel[(size_t)poff + k];
+        const double m = 1.0 / v.w;
+        acc += 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+    }
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = RED_BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
+}
+
+// One thermostat half step of length dt/2 from kinetic energy K: xi += dt/4 G(K),
+// eta += dt/2 xi, scale s = exp(-dt/2 xi) (K becomes s^2 K), xi += dt/4 G(K), with
+// G(K) = (2K - N_f kT) / Q. Returns s.
+__device__ double nvt_half(double &xi, double &eta, double &K, const NvtParams &p) {
+    xi += 0.25 * p.dt * (2.0 * K - p.g) * p.invQ;
+    eta += 0.5 * p.dt * xi;
+    const double sc = exp(-0.5 * p.dt * xi);
+    K = sc * sc * K;
+    xi += 0.25 * p.dt * (2.0 * K - p.g) * p.invQ;
+    return sc;
+}
+
+// One workgroup: the kinetic energy from the partials, then the thermostat. At the end of a
+// step (begin_only = 0) K is that of the velocities after the second kick: the end half step
+// runs from the state the step opened with (xi_b, eta_b) and is committed, with its scale
+// factor left pending for the stored velocities; the half step that opens the next step is
+// then taken from the scaled K. With begin_only the half step that opens the next step is
+// taken from the committed state and the K of the stored velocities.
+__global__ void __launch_bounds__(RED_BLOCK) k_nvt_thermo(const double *partials, NvtParams p,
+                                                           double *th) {
+    __shared__ double s[RED_BLOCK];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < p.np; k += blockDim.x) acc += partials[k];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = RED_BLOCK / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double K = s[0];
+    double xi, eta;
+    if (p.begin_only) {
+        xi = th[TH_XI];
+        eta = th[TH_ETA];
+        th[TH_SPEND] = 1.0;
+        th[TH_K] = K;
+    } else {
+        xi = th[TH_XIB];
+        eta = th[TH_ETAB];
+        const double s1 = nvt_half(xi, eta, K, p);
+        th[TH_XI] = xi;
+        th[TH_ETA] = eta;
+        th[TH_SPEND] = s1;
+        th[TH_K] = K;
+    }
+    const double s2 = nvt_half(xi, eta, K, p);
+    th[TH_SB] = s2;
+    th[TH_XIB] = xi;
+    th[TH_ETAB] = eta;
+}
+
+// End of a call: the stored velocities take the pending scale factor ...
+__global__ void k_nvt_scale(double4 *vel, int poff, int n, const double *th) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double sc = th[TH_SPEND];
+    double4 v = vel[(size_t)poff + k];
+    v.x = sc * v.x;
+    v.y = sc * v.y;
+    v.z = sc * v.z;
+    vel[(size_t)poff + k] = v;
+}
+
+// ... and only then is it cleared (a separate launch: every workgroup above has read it).
+__global__ void k_nvt_clear_pending(double *th) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) th[TH_SPEND] = 1.0;
+}
+
+__global__ void k_negate_vel(double4 *vel, int poff, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double4 v = vel[(size_t)poff + k];
+    v.x = -v.x;
+    v.y = -v.y;
+    v.z = -v.z;
+    vel[(size_t)poff + k] = v;
+}
+
+hipError_t launch_negate_vel(hipStream_t s, double4 *vel, int poff, int n) {
+    hipLaunchKernelGGL(k_negate_vel, dim3((n + 255) / 256), dim3(256), 0, s, vel, poff, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_ke_partials(hipStream_t s, const double4 *vel, int poff, int n,
+                              double *partials, int nblocks_max, int *np_out) {
+    int g = (n + RED_BLOCK - 1) / RED_BLOCK;
+    if (g > nblocks_max) g = nblocks_max;
+    if (g < 1) g = 1;
+    *np_out = g;
+    hipLaunchKernelGGL(k_ke_partials, dim3(g), dim3(RED_BLOCK), 0, s, vel, poff, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_nvt_thermo(hipStream_t s, const double *partials, const NvtParams &p,
+                             double *th) {
+    hipLaunchKernelGGL(k_nvt_thermo, dim3(1), dim3(RED_BLOCK), 0, s, partials, p, th);
+    return hipGetLastError();
+}
+
+hipError_t launch_nvt_finalize(hipStream_t s, double4 *vel, int poff, int n, double *th) {
+    hipLaunchKernelGGL(k_nvt_scale, dim3((n + 255) / 256), dim3(256), 0, s, vel, poff, n, th);
+    hipLaunchKernelGGL(k_nvt_clear_pending, dim3(1), dim3(64), 0, s, th);
     return hipGetLastError();
 }
 

@@ -39,6 +39,8 @@ std::map<TuneKey, std::pair<int, int>> g_tune;  // -> (tpp, block)
 
 }  // namespace
 
+constexpr int EV_PER_UNIT = 8;  // step kernel (2 events) + five rebuild kernels (6 events)
+
 struct ljmd_system {
     ljmd_config cfg{};
     int device = 0;
@@ -51,6 +53,10 @@ struct ljmd_system {
     int ntypes = 1;
     std::vector<double> eps, sig, rc;
     std::vector<char> is_set;
+    // pair form of the system (all set pairs share it) and each pair's form parameters
+    int style = STYLE_LJ;
+    std::vector<int> pform;       // form of each set pair
+    std::vector<double> par;      // 4 per pair
     std::vector<int32_t> h_type;
     std::vector<double> h_mass;
     bool table_dirty = true;
@@ -83,6 +89,11 @@ struct ljmd_system {
     double *d_stage = nullptr;  // n x 10 doubles of upload/download staging
     double4 *d_snap_pos = nullptr, *d_snap_vel = nullptr;
     int4 *d_snap_img = nullptr;
+    // NVT thermostat: device scalars (TH_*), their snapshot, kinetic-energy partials
+    bool nvt = false;
+    bool nvt_ready = false;  // the half step opening the next step is on the device
+    double nvt_kT = 0.0, nvt_invQ = 0.0, nvt_g = 0.0;
+    double *d_th = nullptr, *d_snap_th = nullptr, *d_kpart = nullptr;
     DevStatus *d_st = nullptr;
     int cur = 0;
     bool list_valid = false, force_valid = false;
@@ -90,8 +101,10 @@ struct ljmd_system {
     int tpp = 4, lshift = 2, block = 128;
     int graph_steps = 64;
     hipGraphExec_t graph[2]{nullptr, nullptr};
-    // timing
+    // timing: per unit EV_PER_UNIT events (around the step's force kernel, then around the
+    // five rebuild kernels), and every recorded duration by kernel kind
     bool timing = false;
+    std::vector<float> dur[LJMD_KERNEL_KINDS];
     std::vector<hipEvent_t> ev;
     int64_t t_launches = 0;
     double t_ms = 0.0;
@@ -142,7 +155,10 @@ int setup_table(ljmd_system *s) {
         if (!s->is_set[k])
             return set_err(LJMD_E_STATE, "pair (%d,%d) has not been set", k / nt, k % nt);
     PairTable pt;
-    make_pair_table(nt, s->eps.data(), s->sig.data(), s->rc.data(), s->cfg.skin, &pt);
+    if (s->style == STYLE_LJ)
+        make_pair_table(nt, s->eps.data(), s->sig.data(), s->rc.data(), s->cfg.skin, &pt);
+    else
+        make_form_table(nt, s->style, s->par.data(), s->rc.data(), s->cfg.skin, &pt);
     ReplicaGrid g;
     CHK(make_grid(s->L, pt.rl_max, &g, s->n, tile_limit_for(nt, s->lds_limit)));
     const int ncell = g.ncell;
@@ -350,7 +366,7 @@ int enqueue_forced_rebuild(ljmd_system *s) {
 
 int enqueue_eval(ljmd_system *s, bool energy) {
     ForceArgs a = force_args(s, s->cur);
-    return launch_chk(launch_force(s->stream, a, precision(s), s->tpp, MODE_EVAL, energy, s->block),
+    return launch_chk(launch_force(s->stream, a, precision(s), s->tpp, MODE_EVAL, energy, s->block, s->style),
                       "force eval");
 }
 
@@ -499,14 +515,58 @@ int tune(ljmd_system *s) {
 
 // ------------------------------------------------------------ stepping
 
-int enqueue_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_index) {
-    ForceArgs fa = force_args(s, cur);
-    if (timed) HIPCHK(hipEventRecord(s->ev[2 * ev_index], st));
-    CHK(launch_chk(launch_force(st, fa, precision(s), s->tpp, MODE_FUSED, false, s->block),
-                   "fused step"));
-    if (timed) HIPCHK(hipEventRecord(s->ev[2 * ev_index + 1], st));
+NvtParams nvt_params(ljmd_system *s, int np, bool begin_only) {
+    NvtParams p{};
+    p.dt = s->cfg.dt;
+    p.invQ = s->nvt_invQ;
+    p.g = s->nvt_g;
+    p.np = np;
+    p.begin_only = begin_only ? 1 : 0;
+    return p;
+}
+
+// The thermostat half step that opens the next step, from the stored velocities.
+int enqueue_nvt_begin(ljmd_system *s, hipStream_t st) {
+    int np = 0;
+    CHK(launch_chk(launch_ke_partials(st, s->d_vel, 0, s->n, s->d_kpart, s->red_blocks, &np),
+                   "kinetic energy"));
+    return launch_chk(launch_nvt_thermo(st, s->d_kpart, nvt_params(s, np, true), s->d_th),
+                      "thermostat");
+}
+
+// One NVT step from a full-step state at buffer cur (forces current): the opening thermostat
+// half step's scaling with the first kick and the drift, the gated rebuild, the forces and
+// second kick, then the kinetic energy and the thermostat (end half step, and the opening
+// half step of the next one).
+int enqueue_nvt_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_index) {
+    KickDriftArgs ka = kick_drift_args(s, cur);
+    ka.scale = s->d_th + TH_SPEND;  // TH_SPEND, TH_SB
+    CHK(launch_chk(launch_kick_drift(st, ka), "kick-drift"));
     RebuildArgs ra = rebuild_args(s, s->d_req + (cur ^ 1), cur ^ 1);
-    return launch_chk(launch_rebuild(st, ra), "rebuild");
+    hipEvent_t *rev = timed ? &s->ev[EV_PER_UNIT * ev_index + 2] : nullptr;
+    CHK(launch_chk(launch_rebuild(st, ra, rev), "rebuild"));
+    ForceArgs fa = force_args(s, cur ^ 1);
+    if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index], st));
+    CHK(launch_chk(launch_force(st, fa, precision(s), s->tpp, MODE_FINAL, false, s->block, s->style),
+                   "force"));
+    if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index + 1], st));
+    int np = 0;
+    CHK(launch_chk(launch_ke_partials(st, s->d_vel, 0, s->n, s->d_kpart, s->red_blocks, &np),
+                   "kinetic energy"));
+    return launch_chk(launch_nvt_thermo(st, s->d_kpart, nvt_params(s, np, false), s->d_th),
+                      "thermostat");
+}
+
+int enqueue_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_index) {
+    if (s->nvt) return enqueue_nvt_unit(s, st, cur, timed, ev_index);
+    ForceArgs fa = force_args(s, cur);
+    if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index], st));
+    CHK(launch_chk(launch_force(st, fa, precision(s), s->tpp, MODE_FUSED, false, s->block, s->style),
+                   "fused step"));
+    if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index + 1], st));
+    RebuildArgs ra = rebuild_args(s, s->d_req + (cur ^ 1), cur ^ 1);
+    hipEvent_t *rev = timed ? &s->ev[EV_PER_UNIT * ev_index + 2] : nullptr;
+    return launch_chk(launch_rebuild(st, ra, rev), "rebuild");
 }
 
 int capture_graph(ljmd_system *s, int cur) {
@@ -534,7 +594,7 @@ int capture_graph(ljmd_system *s, int cur) {
 }
 
 int ensure_events(ljmd_system *s, int64_t count) {
-    while ((int64_t)s->ev.size() < 2 * count) {
+    while ((int64_t)s->ev.size() < EV_PER_UNIT * count) {
         hipEvent_t e;
         HIPCHK(hipEventCreate(&e));
         s->ev.push_back(e);
@@ -550,6 +610,8 @@ int snapshot(ljmd_system *s) {
                           s->stream));
     HIPCHK(hipMemcpyAsync(s->d_snap_img, s->d_img, n * sizeof(int4), hipMemcpyDeviceToDevice,
                           s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_snap_th, s->d_th, TH_COUNT * sizeof(double),
+                          hipMemcpyDeviceToDevice, s->stream));
     return LJMD_OK;
 }
 
@@ -562,8 +624,56 @@ int restore(ljmd_system *s, int cur0) {
                           s->stream));
     HIPCHK(hipMemcpyAsync(s->d_img, s->d_snap_img, n * sizeof(int4), hipMemcpyDeviceToDevice,
                           s->stream));
+    HIPCHK(hipMemcpyAsync(s->d_th, s->d_snap_th, TH_COUNT * sizeof(double),
+                          hipMemcpyDeviceToDevice, s->stream));
     s->list_valid = false;
     s->force_valid = false;
+    return LJMD_OK;
+}
+
+int collect_timing(ljmd_system *s, int64_t units) {
+    for (int64_t u = 0; u < units; ++u) {
+        const hipEvent_t *e = &s->ev[EV_PER_UNIT * u];
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e[0], e[1]));
+        s->t_ms += ms;
+        s->dur[LJMD_KERNEL_STEP].push_back(ms);
+        for (int k = 0; k < 5; ++k) {
+            HIPCHK(hipEventElapsedTime(&ms, e[2 + k], e[3 + k]));
+            s->dur[LJMD_KERNEL_BIN + k].push_back(ms);
+        }
+    }
+    s->t_launches += units;
+    return LJMD_OK;
+}
+
+// NVT: every step is one unit (no fused kick-kick-drift: the thermostat needs the kinetic
+// energy between the two kicks); at the end the stored velocities take the pending scale.
+int run_nvt_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
+    if (!s->nvt_ready) {
+        CHK(enqueue_nvt_begin(s, s->stream));
+        s->nvt_ready = true;
+    }
+    const bool use_graph = s->graph_steps > 0 && !s->timing;
+    if (s->timing) CHK(ensure_events(s, nsteps));
+    int64_t done = 0;
+    while (done < nsteps) {
+        if (use_graph && nsteps - done >= s->graph_steps) {
+            if (!s->graph[s->cur]) CHK(capture_graph(s, s->cur));
+            HIPCHK(hipGraphLaunch(s->graph[s->cur], s->stream));
+            done += s->graph_steps;
+        } else {
+            CHK(enqueue_nvt_unit(s, s->stream, s->cur, s->timing, (int)done));
+            s->cur ^= 1;
+            done += 1;
+        }
+    }
+    CHK(launch_chk(launch_nvt_finalize(s->stream, s->d_vel, 0, s->n, s->d_th), "thermostat"));
+    DevStatus st{};
+    CHK(sync_status(s, &st));
+    if (s->timing) CHK(collect_timing(s, nsteps));
+    *overflow = (st.status & ST_OVERFLOW) != 0;
+    *nonfinite = (st.status & (ST_NONFINITE | ST_TILE)) != 0;
     return LJMD_OK;
 }
 
@@ -573,6 +683,7 @@ int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
     *overflow = false;
     *nonfinite = false;
     CHK(clear_status_bits(s));
+    if (s->nvt) return run_nvt_steps(s, nsteps, overflow, nonfinite);
     // first half step from the stored forces
     {
         KickDriftArgs ka = kick_drift_args(s, s->cur);
@@ -597,18 +708,11 @@ int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
         }
     }
     ForceArgs fa = force_args(s, s->cur);
-    CHK(launch_chk(launch_force(s->stream, fa, precision(s), s->tpp, MODE_FINAL, false, s->block),
+    CHK(launch_chk(launch_force(s->stream, fa, precision(s), s->tpp, MODE_FINAL, false, s->block, s->style),
                    "final"));
     DevStatus st{};
     CHK(sync_status(s, &st));
-    if (s->timing) {
-        for (int64_t u = 0; u < units; ++u) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, s->ev[2 * u], s->ev[2 * u + 1]));
-            s->t_ms += ms;
-        }
-        s->t_launches += units;
-    }
+    if (s->timing) CHK(collect_timing(s, units));
     *overflow = (st.status & ST_OVERFLOW) != 0;
     *nonfinite = (st.status & (ST_NONFINITE | ST_TILE)) != 0;
     return LJMD_OK;
@@ -637,6 +741,29 @@ int eval_thermo(ljmd_system *s, double red[RED_QUANT]) {
     HIPCHK(hipMemcpyAsync(red, s->d_red, RED_QUANT * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
     return LJMD_OK;
+}
+
+// The current list with every entry as a sorted-order particle index: cnt[q] entries of row
+// q at ent[q * cap ...]; img gives the tag of each sorted index (img[q].w).
+int decode_list(ljmd_system *s, std::vector<int> &cnt, std::vector<int> &ent,
+                std::vector<int4> &img) {
+    CHK(ensure_ready(s));
+    const size_t N = (size_t)s->n;
+    int *d_out = nullptr;
+    CHK(dalloc_t(s, &d_out, N * (size_t)s->cap));
+    RebuildArgs ra = rebuild_args(s, s->d_one, s->cur);
+    int rc = launch_chk(launch_decode_list(s->stream, ra, d_out), "decode list");
+    cnt.assign(N, 0);
+    ent.assign(N * (size_t)s->cap, 0);
+    img.assign(N, int4{});
+    if (rc == LJMD_OK &&
+        (hipMemcpyAsync(cnt.data(), s->d_count, N * sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+         hipMemcpyAsync(img.data(), s->d_img, N * sizeof(int4), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+         hipMemcpyAsync(ent.data(), d_out, ent.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+         hipStreamSynchronize(s->stream) != hipSuccess))
+        rc = set_err(LJMD_E_DEVICE, "copy of the decoded list failed");
+    dfree(s, d_out);
+    return rc;
 }
 
 }  // namespace
@@ -749,6 +876,8 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
     s->sig.assign(nt2, 1.0);
     s->rc.assign(nt2, 0.0);
     s->is_set.assign(nt2, 0);
+    s->pform.assign(nt2, STYLE_LJ);
+    s->par.assign(4 * (size_t)nt2, 0.0);
     s->h_type.assign(type, type + n);
     if (mass) s->h_mass.assign(mass, mass + n);
     s->tpp = tpp;
@@ -787,6 +916,9 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
     rc = rc ? rc : dalloc_t(s, &s->d_snap_vel, N);
     rc = rc ? rc : dalloc_t(s, &s->d_snap_img, N);
     rc = rc ? rc : dalloc_t(s, &s->d_st, 1);
+    rc = rc ? rc : dalloc_t(s, &s->d_th, TH_COUNT);
+    rc = rc ? rc : dalloc_t(s, &s->d_snap_th, TH_COUNT);
+    rc = rc ? rc : dalloc_t(s, &s->d_kpart, (size_t)s->red_blocks);
     if (rc != LJMD_OK) {
         ljmd_system_destroy(s);
         return rc;
@@ -799,7 +931,9 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
         return code;
     };
     static const int one = 1;
+    static const double th0[TH_COUNT] = {0.0, 0.0, 1.0, 1.0, 0.0, 0.0, 0.0, 0.0};
     if (hipMemcpyAsync(st_pos, pos, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+        hipMemcpyAsync(s->d_th, th0, sizeof th0, hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(st_vel, vel, 3 * N * sizeof(double), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(st_type, type, N * sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
         hipMemcpyAsync(s->d_one, &one, sizeof(int), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
@@ -827,6 +961,36 @@ void ljmd_system_destroy(ljmd_system *s) {
     delete s;
 }
 
+namespace {
+
+// Store pair (a, b) of form `style` with parameters p[4] and cutoff rc (validated).
+int store_pair(ljmd_system *s, int32_t a, int32_t b, int style, const double *p, double rc) {
+    const int nt = s->ntypes;
+    for (int k = 0; k < nt * nt; ++k) {
+        const int x = k / nt, y = k % nt;
+        const bool this_pair = (x == a && y == b) || (x == b && y == a);
+        if (!this_pair && s->is_set[k] && s->pform[k] != style)
+            return set_err(LJMD_E_INVAL, "pair (%d,%d) already uses another pair form: the "
+                                         "kernels evaluate one form per system", x, y);
+    }
+    const int k1 = a * nt + b, k2 = b * nt + a;
+    for (int k : {k1, k2}) {
+        s->eps[k] = p[0];
+        s->sig[k] = style == STYLE_YUKAWA ? 1.0 : p[1];
+        s->rc[k] = rc;
+        s->is_set[k] = 1;
+        s->pform[k] = style;
+        for (int c = 0; c < 4; ++c) s->par[4 * (size_t)k + c] = p[c];
+    }
+    s->style = style;
+    s->table_dirty = true;
+    s->list_valid = false;
+    s->force_valid = false;
+    return LJMD_OK;
+}
+
+}  // namespace
+
 int ljmd_pair_lj_set(ljmd_system *s, int32_t a, int32_t b, double epsilon, double sigma, double r_cut) {
     if (!s) return set_err(LJMD_E_INVAL, "null handle");
     if (a < 0 || b < 0 || a >= s->ntypes || b >= s->ntypes)
@@ -834,15 +998,45 @@ int ljmd_pair_lj_set(ljmd_system *s, int32_t a, int32_t b, double epsilon, doubl
     if (!std::isfinite(epsilon) || !(sigma > 0.0) || !std::isfinite(sigma) || !(r_cut >= 0.0) ||
         !std::isfinite(r_cut))
         return set_err(LJMD_E_INVAL, "need finite epsilon, sigma > 0, r_cut >= 0");
-    const int k1 = a * s->ntypes + b, k2 = b * s->ntypes + a;
-    s->eps[k1] = s->eps[k2] = epsilon;
-    s->sig[k1] = s->sig[k2] = sigma;
-    s->rc[k1] = s->rc[k2] = r_cut;
-    s->is_set[k1] = s->is_set[k2] = 1;
-    s->table_dirty = true;
-    s->list_valid = false;
-    s->force_valid = false;
-    return LJMD_OK;
+    const double p[4] = {epsilon, sigma, 0.0, 0.0};
+    return store_pair(s, a, b, STYLE_LJ, p, r_cut);
+}
+
+int ljmd_pair_set(ljmd_system *s, int32_t a, int32_t b, int32_t form, const double *params,
+                  int32_t nparams, double r_cut) {
+    if (!s || !params) return set_err(LJMD_E_INVAL, "null argument");
+    if (a < 0 || b < 0 || a >= s->ntypes || b >= s->ntypes)
+        return set_err(LJMD_E_INVAL, "type pair (%d,%d) out of range", a, b);
+    const int need = form == LJMD_PAIR_MIE ? 4 : 2;
+    if (form < LJMD_PAIR_LJ || form > LJMD_PAIR_WCA)
+        return set_err(LJMD_E_INVAL, "unknown pair form %d", form);
+    if (nparams != need) return set_err(LJMD_E_INVAL, "pair form %d takes %d parameters", form, need);
+    double p[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < need; ++c) {
+        if (!std::isfinite(params[c])) return set_err(LJMD_E_INVAL, "non-finite parameter");
+        p[c] = params[c];
+    }
+    if (form == LJMD_PAIR_WCA) {
+        if (r_cut != 0.0) return set_err(LJMD_E_INVAL, "WCA takes r_cut = 0 (its cut is 2^(1/6) sigma)");
+        if (!(p[1] > 0.0)) return set_err(LJMD_E_INVAL, "need sigma > 0");
+        return store_pair(s, a, b, STYLE_LJ, p, std::pow(2.0, 1.0 / 6.0) * p[1]);
+    }
+    if (!(r_cut >= 0.0) || !std::isfinite(r_cut)) return set_err(LJMD_E_INVAL, "need r_cut >= 0");
+    switch (form) {
+        case LJMD_PAIR_LJ:
+            if (!(p[1] > 0.0)) return set_err(LJMD_E_INVAL, "need sigma > 0");
+            return store_pair(s, a, b, STYLE_LJ, p, r_cut);
+        case LJMD_PAIR_MIE:
+            if (!(p[1] > 0.0) || !(p[3] > 0.0) || !(p[2] > p[3]))
+                return set_err(LJMD_E_INVAL, "Mie needs sigma > 0 and n > m > 0");
+            return store_pair(s, a, b, STYLE_MIE, p, r_cut);
+        case LJMD_PAIR_GAUSS:
+            if (!(p[1] > 0.0)) return set_err(LJMD_E_INVAL, "need sigma > 0");
+            return store_pair(s, a, b, STYLE_GAUSS, p, r_cut);
+        default:
+            if (!(p[1] >= 0.0)) return set_err(LJMD_E_INVAL, "Yukawa needs kappa >= 0");
+            return store_pair(s, a, b, STYLE_YUKAWA, p, r_cut);
+    }
 }
 
 int ljmd_step(ljmd_system *s, int64_t nsteps) {
@@ -854,6 +1048,12 @@ int ljmd_step(ljmd_system *s, int64_t nsteps) {
     while (left > 0) {
         const int64_t k = std::min(left, seg);
         const int cur0 = s->cur;
+        if (s->nvt && !s->nvt_ready) {
+            // the thermostat half step opening the first step, before the snapshot that a
+            // re-run after a list overflow restores
+            CHK(enqueue_nvt_begin(s, s->stream));
+            s->nvt_ready = true;
+        }
         CHK(snapshot(s));
         for (int attempt = 0;; ++attempt) {
             bool over = false, nonfin = false;
@@ -960,28 +1160,76 @@ int ljmd_set_state(ljmd_system *s, const double *pos, const double *vel, const i
     if (step) s->steps = *step;
     s->list_valid = false;
     s->force_valid = false;
+    s->nvt_ready = false;  // new velocities: the opening thermostat half step is redone
+    return LJMD_OK;
+}
+
+int ljmd_set_nvt(ljmd_system *s, double kT, double tau) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (!(kT > 0.0) || !std::isfinite(kT) || !(tau > 0.0) || std::isnan(tau))
+        return set_err(LJMD_E_INVAL, "need kT > 0 and tau > 0 (tau may be infinite)");
+    if (s->n < 2) return set_err(LJMD_E_INVAL, "NVT needs at least two particles");
+    const double ndof = 3.0 * (double)s->n - 3.0;
+    s->nvt = true;
+    s->nvt_kT = kT;
+    s->nvt_g = ndof * kT;
+    s->nvt_invQ = std::isinf(tau) ? 0.0 : 1.0 / (ndof * kT * tau * tau);
+    s->nvt_ready = false;
+    drop_graphs(s);
+    static const double th0[TH_COUNT] = {0.0, 0.0, 1.0, 1.0, 0.0, 0.0, 0.0, 0.0};
+    HIPCHK(hipMemcpyAsync(s->d_th, th0, sizeof th0, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return LJMD_OK;
+}
+
+int ljmd_set_nve(ljmd_system *s) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (s->nvt) drop_graphs(s);
+    s->nvt = false;
+    s->nvt_ready = false;
+    return LJMD_OK;
+}
+
+int ljmd_get_thermostat(ljmd_system *s, double *xi, double *eta, double *energy) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    double th[TH_COUNT];
+    HIPCHK(hipMemcpyAsync(th, s->d_th, sizeof th, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (!s->nvt) th[TH_XI] = th[TH_ETA] = 0.0;
+    if (xi) *xi = th[TH_XI];
+    if (eta) *eta = th[TH_ETA];
+    if (energy)
+        *energy = (s->nvt && s->nvt_invQ > 0.0)
+                      ? 0.5 * th[TH_XI] * th[TH_XI] / s->nvt_invQ + s->nvt_g * th[TH_ETA]
+                      : 0.0;
+    return LJMD_OK;
+}
+
+int ljmd_set_thermostat(ljmd_system *s, double xi, double eta) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (!std::isfinite(xi) || !std::isfinite(eta)) return set_err(LJMD_E_INVAL, "non-finite value");
+    if (!s->nvt) return set_err(LJMD_E_STATE, "the system is not under NVT (ljmd_set_nvt)");
+    const double v[2] = {xi, eta};
+    HIPCHK(hipMemcpyAsync(s->d_th + TH_XI, v, sizeof v, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->nvt_ready = false;
+    return LJMD_OK;
+}
+
+int ljmd_negate_velocities(ljmd_system *s) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    CHK(launch_chk(launch_negate_vel(s->stream, s->d_vel, 0, s->n), "negate"));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->nvt_ready = false;
     return LJMD_OK;
 }
 
 int ljmd_get_neighbor_pairs(ljmd_system *s, int64_t *count, int32_t *pairs, double *build_pos) {
     if (!s || !count) return set_err(LJMD_E_INVAL, "null argument");
-    CHK(ensure_ready(s));
+    std::vector<int> cnt, ent;
+    std::vector<int4> img;
+    CHK(decode_list(s, cnt, ent, img));
     const size_t N = (size_t)s->n;
-    // global index of every entry, row q at q * cap, decoded on the device
-    int *d_out = nullptr;
-    CHK(dalloc_t(s, &d_out, N * (size_t)s->cap));
-    RebuildArgs ra = rebuild_args(s, s->d_one, s->cur);
-    int rc = launch_chk(launch_decode_list(s->stream, ra, d_out), "decode list");
-    std::vector<int> cnt(N), ent(N * (size_t)s->cap);
-    std::vector<int4> img(N);
-    if (rc == LJMD_OK &&
-        (hipMemcpyAsync(cnt.data(), s->d_count, N * sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-         hipMemcpyAsync(img.data(), s->d_img, N * sizeof(int4), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-         hipMemcpyAsync(ent.data(), d_out, ent.size() * sizeof(int), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-         hipStreamSynchronize(s->stream) != hipSuccess))
-        rc = set_err(LJMD_E_DEVICE, "copy of the decoded list failed");
-    dfree(s, d_out);
-    if (rc != LJMD_OK) return rc;
     std::vector<std::pair<int, int>> pr;
     for (size_t q = 0; q < N; ++q) {
         const int c = std::min(cnt[q], s->cap);
@@ -998,6 +1246,30 @@ int ljmd_get_neighbor_pairs(ljmd_system *s, int64_t *count, int32_t *pairs, doub
             pairs[2 * p] = pr[p].first;
             pairs[2 * p + 1] = pr[p].second;
         }
+    if (build_pos) CHK(fetch_vec(s, s->d_xb, build_pos));
+    return LJMD_OK;
+}
+
+int ljmd_get_neighbor_list(ljmd_system *s, int32_t *counts, int64_t *total, int32_t *neighbors,
+                           double *build_pos) {
+    if (!s || !total) return set_err(LJMD_E_INVAL, "null argument");
+    std::vector<int> cnt, ent;
+    std::vector<int4> img;
+    CHK(decode_list(s, cnt, ent, img));
+    const size_t N = (size_t)s->n;
+    // rows by tag: the sorted index of each tag
+    std::vector<int> at(N);
+    for (size_t q = 0; q < N; ++q) at[(size_t)img[q].w] = (int)q;
+    int64_t tot = 0;
+    for (size_t t = 0; t < N; ++t) {
+        const int c = std::min(cnt[at[t]], s->cap);
+        if (counts) counts[t] = c;
+        if (neighbors)
+            for (int k = 0; k < c; ++k)
+                neighbors[tot + k] = img[ent[(size_t)at[t] * s->cap + k]].w;
+        tot += c;
+    }
+    *total = tot;
     if (build_pos) CHK(fetch_vec(s, s->d_xb, build_pos));
     return LJMD_OK;
 }
@@ -1026,6 +1298,7 @@ int ljmd_set_kernel_timing(ljmd_system *s, int32_t on) {
     s->timing = on != 0;
     s->t_launches = 0;
     s->t_ms = 0.0;
+    for (auto &d : s->dur) d.clear();
     return LJMD_OK;
 }
 
@@ -1033,6 +1306,15 @@ int ljmd_kernel_time(ljmd_system *s, int64_t *launches, double *total_ms) {
     if (!s) return set_err(LJMD_E_INVAL, "null handle");
     if (launches) *launches = s->t_launches;
     if (total_ms) *total_ms = s->t_ms;
+    return LJMD_OK;
+}
+
+int ljmd_kernel_durations(ljmd_system *s, int32_t kind, int64_t *count, float *ms) {
+    if (!s || !count) return set_err(LJMD_E_INVAL, "null argument");
+    if (kind < 0 || kind >= LJMD_KERNEL_KINDS) return set_err(LJMD_E_INVAL, "unknown kernel kind %d", kind);
+    const std::vector<float> &d = s->dur[kind];
+    *count = (int64_t)d.size();
+    if (ms && !d.empty()) std::memcpy(ms, d.data(), d.size() * sizeof(float));
     return LJMD_OK;
 }
 

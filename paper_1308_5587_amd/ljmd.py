@@ -15,8 +15,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# LJMD_LIBRARY may name another build of the same library (for A/B timing of variants).
-LIB_PATH = os.environ.get("LJMD_LIBRARY") or os.path.join(HERE, "libljmd.so")
+LIB_PATH = os.path.join(HERE, "libljmd.so")
 
 LJMD_OK = 0
 LJMD_E_INVAL = -1
@@ -93,12 +92,16 @@ class LjmdTuningEntry(C.Structure):
 
 
 EXPORTED = [
-    "ljmd_system_create", "ljmd_system_destroy", "ljmd_pair_lj_set", "ljmd_step",
+    "ljmd_system_create", "ljmd_system_destroy", "ljmd_pair_lj_set", "ljmd_pair_set",
+    "ljmd_step",
     "ljmd_get_forces", "ljmd_get_energy", "ljmd_get_virial", "ljmd_get_per_particle",
-    "ljmd_get_state", "ljmd_set_state", "ljmd_get_neighbor_pairs", "ljmd_get_stats",
-    "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_last_error", "ljmd_version",
+    "ljmd_get_state", "ljmd_set_state", "ljmd_get_neighbor_pairs", "ljmd_get_neighbor_list",
+    "ljmd_get_stats", "ljmd_set_nvt", "ljmd_set_nve", "ljmd_get_thermostat",
+    "ljmd_set_thermostat", "ljmd_negate_velocities",
+    "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_kernel_durations", "ljmd_last_error", "ljmd_version",
     "ljmd_batch_create", "ljmd_batch_destroy", "ljmd_batch_footprint", "ljmd_batch_admit",
     "ljmd_batch_run_block", "ljmd_batch_poll", "ljmd_batch_read", "ljmd_batch_slot_steps",
+    "ljmd_batch_slot_status",
     "ljmd_batch_release", "ljmd_batch_get_stats", "ljmd_tuning_get", "ljmd_tuning_set",
 ]
 
@@ -116,6 +119,8 @@ def load(path: str = LIB_PATH):
         "ljmd_system_create": ([C.POINTER(LjmdConfig), C.c_int64, dp, dp, ip, dp, C.POINTER(vp)], C.c_int),
         "ljmd_system_destroy": ([vp], None),
         "ljmd_pair_lj_set": ([vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double], C.c_int),
+        "ljmd_pair_set": ([vp, C.c_int32, C.c_int32, C.c_int32, dp, C.c_int32, C.c_double],
+                          C.c_int),
         "ljmd_step": ([vp, C.c_int64], C.c_int),
         "ljmd_get_forces": ([vp, dp], C.c_int),
         "ljmd_get_energy": ([vp, dp, dp], C.c_int),
@@ -124,9 +129,16 @@ def load(path: str = LIB_PATH):
         "ljmd_get_state": ([vp, dp, dp, ip, lp], C.c_int),
         "ljmd_set_state": ([vp, dp, dp, ip, lp], C.c_int),
         "ljmd_get_neighbor_pairs": ([vp, lp, ip, dp], C.c_int),
+        "ljmd_get_neighbor_list": ([vp, ip, lp, ip, dp], C.c_int),
         "ljmd_get_stats": ([vp, C.POINTER(LjmdStats)], C.c_int),
+        "ljmd_set_nvt": ([vp, C.c_double, C.c_double], C.c_int),
+        "ljmd_set_nve": ([vp], C.c_int),
+        "ljmd_get_thermostat": ([vp, dp, dp, dp], C.c_int),
+        "ljmd_set_thermostat": ([vp, C.c_double, C.c_double], C.c_int),
+        "ljmd_negate_velocities": ([vp], C.c_int),
         "ljmd_set_kernel_timing": ([vp, C.c_int32], C.c_int),
         "ljmd_kernel_time": ([vp, lp, dp], C.c_int),
+        "ljmd_kernel_durations": ([vp, C.c_int32, lp, C.POINTER(C.c_float)], C.c_int),
         "ljmd_last_error": ([], C.c_char_p),
         "ljmd_version": ([], C.c_char_p),
         "ljmd_batch_create": ([C.POINTER(LjmdBatchConfig), C.POINTER(vp)], C.c_int),
@@ -137,6 +149,7 @@ def load(path: str = LIB_PATH):
         "ljmd_batch_poll": ([vp, ip, ip], C.c_int),
         "ljmd_batch_read": ([vp, C.c_int32, dp, dp, dp, dp, dp], C.c_int),
         "ljmd_batch_slot_steps": ([vp, C.c_int32, lp], C.c_int),
+        "ljmd_batch_slot_status": ([vp, C.c_int32, ip], C.c_int),
         "ljmd_batch_release": ([vp, C.c_int32], C.c_int),
         "ljmd_batch_get_stats": ([vp, C.POINTER(LjmdBatchStats)], C.c_int),
         "ljmd_tuning_get": ([C.POINTER(LjmdTuningEntry), C.c_int32, ip], C.c_int),
@@ -265,6 +278,15 @@ class System:
         _check(self._lib.ljmd_pair_lj_set(self._h, int(a), int(b), float(epsilon), float(sigma),
                                           float(r_cut)))
 
+    PAIR_FORMS = {"lj": 0, "mie": 1, "gauss": 2, "yukawa": 3, "wca": 4}
+
+    def pair_set(self, a, b, form, params, r_cut):
+        """Pair (a, b) of another form: 'mie' (eps, sigma, n, m), 'gauss' (eps, sigma),
+        'yukawa' (eps, kappa), 'wca' (eps, sigma; r_cut 0) or 'lj' (eps, sigma)."""
+        p = np.ascontiguousarray(params, dtype=np.float64)
+        _check(self._lib.ljmd_pair_set(self._h, a, b, self.PAIR_FORMS[form], _dp(p), len(p),
+                                       float(r_cut)))
+
     def step(self, nsteps=1):
         _check(self._lib.ljmd_step(self._h, int(nsteps)))
 
@@ -314,6 +336,38 @@ class System:
         _check(self._lib.ljmd_get_neighbor_pairs(self._h, C.byref(cnt), _ip(out), _dp(xb)))
         return out, xb
 
+    def set_nvt(self, kT, tau):
+        """NVT at kT with thermostat time constant tau (float('inf'): zero coupling)."""
+        _check(self._lib.ljmd_set_nvt(self._h, float(kT), float(tau)))
+
+    def set_nve(self):
+        _check(self._lib.ljmd_set_nve(self._h))
+
+    def thermostat(self):
+        """(xi, eta, thermostat energy Q xi^2/2 + N_f kT eta)."""
+        out = np.zeros(3)
+        _check(self._lib.ljmd_get_thermostat(self._h, _dp(out[0:1]), _dp(out[1:2]),
+                                             _dp(out[2:3])))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def set_thermostat(self, xi, eta):
+        _check(self._lib.ljmd_set_thermostat(self._h, float(xi), float(eta)))
+
+    def negate_velocities(self):
+        _check(self._lib.ljmd_negate_velocities(self._h))
+
+    def neighbor_list(self):
+        """The full list: (counts[n], neighbours[total]) with rows in tag order and each
+        row's entries in stored order, plus the build positions."""
+        tot = C.c_int64(0)
+        counts = np.empty(self.n, dtype=np.int32)
+        _check(self._lib.ljmd_get_neighbor_list(self._h, _ip(counts), C.byref(tot), None, None))
+        nb = np.empty(max(1, tot.value), dtype=np.int32)
+        xb = np.empty((self.n, 3))
+        _check(self._lib.ljmd_get_neighbor_list(self._h, _ip(counts), C.byref(tot), _ip(nb),
+                                                _dp(xb)))
+        return counts, nb[:tot.value], xb
+
     def stats(self):
         st = LjmdStats()
         _check(self._lib.ljmd_get_stats(self._h, C.byref(st)))
@@ -322,6 +376,20 @@ class System:
 
     def set_kernel_timing(self, on=True):
         _check(self._lib.ljmd_set_kernel_timing(self._h, 1 if on else 0))
+
+    KERNEL_KINDS = ("step", "bin", "scan", "scatter", "gather", "nlist")
+
+    def kernel_durations(self):
+        """Per-launch durations (ms) recorded while kernel timing was on, by kernel kind."""
+        out = {}
+        for k, name in enumerate(self.KERNEL_KINDS):
+            cnt = C.c_int64(0)
+            _check(self._lib.ljmd_kernel_durations(self._h, k, C.byref(cnt), None))
+            buf = np.empty(max(1, cnt.value), dtype=np.float32)
+            _check(self._lib.ljmd_kernel_durations(self._h, k, C.byref(cnt),
+                                                    buf.ctypes.data_as(C.POINTER(C.c_float))))
+            out[name] = buf[:cnt.value].astype(np.float64)
+        return out
 
     def kernel_time(self):
         n = C.c_int64(0)
@@ -439,6 +507,12 @@ class Batch:
         k = C.c_int32(0)
         _check(self._lib.ljmd_batch_poll(self._h, _ip(out), C.byref(k)))
         return [int(v) for v in out[:k.value]]
+
+    def slot_status(self, slot):
+        """LJMD_OK, or the status the replica in `slot` was retired with."""
+        out = C.c_int32(0)
+        _check(self._lib.ljmd_batch_slot_status(self._h, int(slot), C.byref(out)))
+        return int(out.value)
 
     def slot_steps(self, slot):
         out = C.c_int64(0)

@@ -8,8 +8,11 @@ that arrives while other replicas are on the GPU joins them at the next block bo
 Replica state stays on the device from admission to retirement.
 
 The executor is anything with the batch interface of ``ljmd.Batch`` (footprint, admit,
-run_block, poll, read, release); the scheduling logic here holds no simulation arithmetic.
-Latency of a request is its completion time minus its arrival time on the loop's clock.
+run_block, poll, read, release, and optionally slot_status); the scheduling logic here
+holds no simulation arithmetic. Latency of a request is its completion time minus its
+arrival time on the loop's clock. A request whose replica the executor retired with an
+error (slot_status non-zero) is reported as failed: it is neither read nor counted in the
+latency and throughput figures.
 """
 
 from __future__ import annotations
@@ -32,6 +35,8 @@ class Request:
     admitted: float = -1.0
     finished: float = -1.0
     slot: int = -1
+    status: int = 0         # 0, or the error code the replica was retired with
+    refused: int = 0        # admissions refused for capacity (no slot or budget) while at the head
     result: dict = field(default=None, repr=False)
 
     @property
@@ -45,10 +50,11 @@ class Request:
 
 @dataclass
 class ServeReport:
-    requests: list
+    requests: list          # finished requests, by id
     wall_s: float
     blocks: int
     peak_resident: int
+    failed: list = field(default_factory=list)  # requests retired with an error
 
     def latencies(self):
         return np.array([r.latency for r in self.requests], dtype=np.float64)
@@ -65,6 +71,8 @@ class ServeReport:
             "mean_latency_s": float(lat.mean()) if len(lat) else 0.0,
             "blocks": self.blocks,
             "peak_resident": self.peak_resident,
+            "failed": len(self.failed),
+            "refused_for_capacity": sum(1 for r in self.requests if r.refused),
         }
 
 
@@ -96,6 +104,8 @@ def serve(executor, requests, clock=None, keep_results=False, max_blocks=10_000_
     blocks = 0
     peak = 0
     done = []
+    failed = []
+    slot_status = getattr(executor, "slot_status", None)
     while incoming or waiting or resident:
         now = clock.now()
         while incoming and incoming[0].arrival <= now:
@@ -108,6 +118,7 @@ def serve(executor, requests, clock=None, keep_results=False, max_blocks=10_000_
                 slot = executor.admit(r.spec, r.nsteps)
             except Exception as e:  # noqa: BLE001 - only the capacity code is expected
                 if _is_capacity(e) and resident:
+                    r.refused += 1
                     break
                 raise
             waiting.popleft()
@@ -128,13 +139,19 @@ def serve(executor, requests, clock=None, keep_results=False, max_blocks=10_000_
             if r is None:
                 continue
             r.finished = clock.now()
+            r.status = int(slot_status(slot)) if slot_status else 0
+            if r.status != 0:
+                executor.release(slot)
+                failed.append(r)
+                continue
             if keep_results:
                 r.result = executor.read(slot)
             executor.release(slot)
             done.append(r)
     wall = clock.now()
     done.sort(key=lambda r: r.rid)
-    return ServeReport(done, wall, blocks, peak)
+    failed.sort(key=lambda r: r.rid)
+    return ServeReport(done, wall, blocks, peak, failed)
 
 
 def serve_one_by_one(run_alone, requests, clock=None, keep_results=False):

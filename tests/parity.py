@@ -34,3 +34,24 @@ def unwrapped(pos, img, box):
 
 def print_case(msg):
     print(f"[case] {msg}", flush=True)
+
+
+def full_list_keys(counts, neighbours):
+    """Every stored entry of a full list as the key row * 2^32 + neighbour, sorted."""
+    counts = np.asarray(counts, dtype=np.int64)
+    rows = np.repeat(np.arange(len(counts), dtype=np.int64), counts)
+    return np.sort(rows * (1 << 32) + np.asarray(neighbours, dtype=np.int64))
+
+
+def assert_full_list_equals_pairs(counts, neighbours, pairs):
+    """A full list (rows of neighbour tags) against an unordered pair set (i < j): no row
+    holds an entry twice or lists its own particle, every pair appears in both rows, and
+    nothing else appears."""
+    keys = full_list_keys(counts, neighbours)
+    assert int(np.asarray(counts).sum()) == len(keys)
+    assert not np.any((keys >> 32) == (keys & 0xFFFFFFFF)), "a row lists its own particle"
+    assert np.all(np.diff(keys) > 0), "a row holds the same neighbour twice"
+    p = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    ref = np.sort(np.concatenate([p[:, 0] * (1 << 32) + p[:, 1], p[:, 1] * (1 << 32) + p[:, 0]]))
+    assert keys.shape == ref.shape, (keys.shape, ref.shape)
+    assert np.array_equal(keys, ref)

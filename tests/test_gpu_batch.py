@@ -82,6 +82,33 @@ def test_batch_equals_alone_bitwise(ljmd_mod, precision):
     b.close()
 
 
+@pytest.mark.parametrize("want_tpp,want_block", [(2, 0), (0, 0), (4, 0)])
+def test_tuned_batch_equals_alone(ljmd_mod, want_tpp, want_block):
+    # the first block tunes what is not given (workgroup size, or lanes and workgroup size);
+    # the tuning trials rebuild the replicas' lists at their drifted positions, and the block
+    # then retakes every replica's first half step from its state at t = 0, so each replica
+    # still follows its alone run (with the lanes the batch settled on) bit for bit
+    print_case(f"tuned batch (tpp={want_tpp}, block={want_block}) vs alone")
+    mix = _mix()
+    b = ljmd_mod.Batch(256 << 20, 8, precision="mixed", block_steps=20,
+                       threads_per_particle=want_tpp, block_size=want_block)
+    slots = [b.admit(spec, n) for spec, n in mix]
+    _run_until_done(b, slots)
+    st = b.stats()
+    tpp, block = st["threads_per_particle"], st["block_size"]
+    if want_tpp:
+        assert tpp == want_tpp
+    for (spec, n), s in zip(mix, slots):
+        g = ljmd_mod.System.from_spec(spec, precision="mixed", threads_per_particle=tpp,
+                                      block_size=block)
+        g.step(n)
+        pos, vel, _, _ = g.state()
+        u, k = g.energy()
+        _same(b.read(s), {"pos": pos, "vel": vel, "forces": g.forces(), "potential": u,
+                          "kinetic": k, "virial": g.virial()})
+    b.close()
+
+
 def test_tile_overflow_decided_per_replica(ljmd_mod):
     # alone, the droplet's tile capacity is sized for its mean cell count and the bricks
     # around its dense block read neighbours from global memory. Beside a dense fluid the
@@ -244,6 +271,51 @@ def test_served_stream_results_equal_alone(ljmd_mod):
     assert rep.peak_resident == 3, rep.peak_resident
     for r in rep.requests:
         _same(r.result, _alone(ljmd_mod, r.spec, r.nsteps, "mixed"))
+
+
+def test_served_stream_matches_oracle_autotuned(ljmd_mod, oracle_mod):
+    """A served stream on an autotuned batch (lanes and workgroup chosen at its first block):
+    every request's result is checked against the FP64 oracle (one-step requests to the
+    mixed single-step bar, longer ones to the mixed trajectory bound) and against its alone
+    run with the lanes the batch settled on, bit for bit."""
+    print_case("served autotuned stream vs oracle and vs alone")
+    from paper_1308_5587_amd import serve
+
+    arrivals = gen.make_arrivals(8, rate=5000.0, seed=9, n_lo=512, n_hi=4000, steps_lo=100,
+                                 steps_hi=160)
+    mk = lambda p: gen.make_lj_fluid(p.n, rho=p.rho, T=p.T, seed=p.seed)  # noqa: E731
+    reqs = serve.requests_from_arrivals(arrivals, mk)
+    for r in reqs[::3]:
+        r.nsteps = 1  # single-step requests: checked to the single-evaluation bar
+    b = ljmd_mod.Batch(128 << 20, 3, precision="mixed", block_steps=10)
+    rep = serve.serve(b, reqs, keep_results=True)
+    st = b.stats()
+    b.close()
+    assert len(rep.requests) == 8 and not rep.failed
+    assert rep.peak_resident == 3
+    tpp, block = st["threads_per_particle"], st["block_size"]
+    for r in rep.requests:
+        got = r.result
+        o = oracle_mod.OracleSystem.from_spec(r.spec)
+        o.step(r.nsteps)
+        po, vo, _, _ = o.state()
+        d = got["pos"] - po
+        d -= r.spec.box[None, :] * np.rint(d / r.spec.box[None, :])
+        if r.nsteps == 1:
+            assert max_norm_rel(got["forces"], o.forces()) <= 1e-5, r.rid
+            assert np.abs(d).max() < 1e-7
+        else:
+            assert np.abs(d).max() < 1e-3, (r.rid, np.abs(d).max())
+        uo, ko = o.energy()
+        tol = 1e-5 if r.nsteps == 1 else 1e-3
+        assert scalar_rel(got["potential"] + got["kinetic"], uo + ko) < tol, r.rid
+        g = ljmd_mod.System.from_spec(r.spec, precision="mixed", threads_per_particle=tpp,
+                                      block_size=block)
+        g.step(r.nsteps)
+        pos, vel, _, _ = g.state()
+        u, k = g.energy()
+        _same(got, {"pos": pos, "vel": vel, "forces": g.forces(), "potential": u,
+                    "kinetic": k, "virial": g.virial()})
 
 
 def test_full_size_batch_sampled_replicas(ljmd_mod, oracle_mod):

@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 from paper_1308_5587_amd import inputs as gen
-from parity import max_norm_rel, print_case, scalar_rel, sort_pairs, unwrapped
+from parity import (assert_full_list_equals_pairs, max_norm_rel, print_case, scalar_rel,
+                    sort_pairs, unwrapped)
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +55,35 @@ def _list_parity(o_sys, g_sys, pos):
     b = sort_pairs(pg)
     assert a.shape == b.shape, (a.shape, b.shape)
     assert np.array_equal(a, b)
+    # the full list the force kernel streams: both rows of every pair, nothing else
+    counts, nb, xbf = g_sys.neighbor_list()
+    assert np.array_equal(xbf, xbg)
+    assert_full_list_equals_pairs(counts, nb, po)
+
+
+def _step_past_rebuilds(g_sys, count=3, chunk=10, max_steps=400):
+    """Step until the device has rebuilt the list at least `count` more times."""
+    b0 = g_sys.stats()["rebuilds"]
+    done = 0
+    while g_sys.stats()["rebuilds"] < b0 + count:
+        assert done < max_steps, "too few rebuilds"
+        g_sys.step(chunk)
+        done += chunk
+    return done
+
+
+def _rebuilt_list_parity(oracle_mod, g_sys, spec):
+    """The list a device rebuild inside ljmd_step produced (from a drifted, cell-sorted
+    state) against the oracle's list built at the same build positions."""
+    counts, nb, xb = g_sys.neighbor_list()
+    assert np.all(xb >= 0.0) and np.all(xb < spec.box[None, :])
+    o = oracle_mod.OracleSystem(spec.box, xb, np.zeros_like(xb), spec.type, spec.ntypes,
+                                spec.pairs)
+    po, xbo = o.pairs()
+    assert np.array_equal(xbo, xb)
+    assert_full_list_equals_pairs(counts, nb, po)
+    pg, _ = g_sys.neighbor_pairs()
+    assert np.array_equal(sort_pairs(pg), sort_pairs(po))
 
 
 @pytest.mark.parametrize("n,seed", [(4000, 1), (1, 3), (2, 4), (37, 5), (1001, 6), (6859, 7)])
@@ -213,6 +243,31 @@ def test_one_and_hundred_steps(ljmd_mod, oracle_mod):
     assert np.abs(vg - vo).max() < 1e-8
     assert max_norm_rel(g.forces(), o.forces()) < 1e-8
     assert g.stats()["rebuilds"] >= 5
+
+
+@pytest.mark.parametrize("case,precision", [("fluid4000", "fp64"), ("fluid4000", "mixed"),
+                                            ("box3cells", "fp64"), ("box2cells", "fp64"),
+                                            ("ka8000", "mixed"), ("droplet", "fp64")])
+def test_lists_after_device_rebuilds(ljmd_mod, oracle_mod, case, precision):
+    """Lists rebuilt on the device inside ljmd_step (gated by the displacement check, from a
+    drifted and cell-sorted state) are compared as full lists with the oracle's list at the
+    same build positions, after at least three device rebuilds."""
+    print_case(f"lists after device rebuilds: {case} {precision}")
+    if case == "fluid4000":
+        s = gen.make_lj_fluid(4000, seed=1)
+    elif case == "box3cells":
+        s = gen.make_lj_fluid(1000, rho=0.75, T=1.2, seed=31)
+    elif case == "box2cells":
+        s = gen.make_lj_fluid(256, rho=256 / 6.58 ** 3, T=1.0, seed=11)
+    elif case == "ka8000":
+        s = gen.make_ka_mixture(8000, seed=2)
+    else:
+        s = gen.make_lj_droplet(seed=5)
+    g = ljmd_mod.System.from_spec(s, precision=precision)
+    g.step(1)
+    for chunk in (7, 11):
+        _step_past_rebuilds(g, 3, chunk)
+        _rebuilt_list_parity(oracle_mod, g, s)
 
 
 @pytest.mark.parametrize("n,rho,box", [
@@ -390,11 +445,22 @@ def test_full_size_fp64_and_mixed(ljmd_mod, oracle_mod):
     assert max_norm_rel(g.virial(), o.virial()) <= 1e-10
     m = ljmd_mod.System.from_spec(s, precision="mixed")
     assert max_norm_rel(m.forces(), o.forces()) <= 1e-5
+    assert scalar_rel(m.energy()[0], Uo) <= 1e-5
     assert max_norm_rel(m.virial(), o.virial()) <= 1e-5
+    uo, wo = o.per_particle()
+    um, wm = m.per_particle()
+    assert max_norm_rel(um, uo) <= 1e-5 and max_norm_rel(wm, wo) <= 1e-5
+    ug, wg = g.per_particle()
+    assert max_norm_rel(ug, uo) <= 1e-10 and max_norm_rel(wg, wo) <= 1e-10
+    del uo, wo, um, wm, ug, wg
     # two steps on both paths
     o.step(2)
     g.step(2)
     assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
+    del o
+    # lists rebuilt on the device during steps, against the oracle at their build positions
+    _step_past_rebuilds(g, 3, 9)
+    _rebuilt_list_parity(oracle_mod, g, s)
 
 
 def test_full_size_ka_mixture(ljmd_mod, oracle_mod):
@@ -414,11 +480,21 @@ def test_full_size_ka_mixture(ljmd_mod, oracle_mod):
     g = ljmd_mod.System.from_spec(s)
     assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
     assert scalar_rel(g.energy()[0], Uo) <= 1e-10
-    o.step(10)
-    g.step(10)
-    m.step(10)
+    o.step(1)
+    g.step(1)
+    m.step(1)
+    # one full step of the mixed path from the identical state
+    assert max_norm_rel(m.forces(), o.forces()) <= 1e-5
+    assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
+    o.step(9)
+    g.step(9)
+    m.step(9)
     assert max_norm_rel(g.forces(), o.forces()) <= 1e-10
     assert max_norm_rel(m.forces(), o.forces()) <= 1e-4
     po, _, io, _ = o.state()
     pg, _, ig, _ = g.state()
     assert np.abs(unwrapped(pg, ig, s.box) - unwrapped(po, io, s.box)).max() < 1e-10
+    del o
+    # lists rebuilt on the device during steps (mixed path), against the oracle
+    _step_past_rebuilds(m, 3, 10)
+    _rebuilt_list_parity(oracle_mod, m, s)

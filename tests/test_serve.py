@@ -146,3 +146,36 @@ def test_one_by_one_baseline():
     assert np.allclose(f, [0.1, 0.15, 0.35])
     assert [r.result for r in rep.requests] == [100, 100, 100]
     assert rep.summary()["p50_latency_s"] == pytest.approx(0.14)
+
+
+class FailingBatch(FakeBatch):
+    """Retires the replicas of the given request sizes with an error status (as the library
+    does for a non-finite force); reading such a slot raises."""
+
+    def __init__(self, *a, fail_sizes=(), **kw):
+        super().__init__(*a, **kw)
+        self.fail_sizes = set(fail_sizes)
+
+    def slot_status(self, s):
+        return -5 if self.res[s][0] in self.fail_sizes else 0
+
+    def read(self, s):
+        if self.slot_status(s):
+            raise RuntimeError("read of a failed slot")
+        return super().read(s)
+
+
+def test_failed_requests_reported_apart():
+    clock = SimClock()
+    ex = FailingBatch(clock, budget=1_000_000, slots=3, fail_sizes={777})
+    sizes = [500, 777, 600, 777, 900]
+    rep = serve.serve(ex, _reqs(sizes, [0.0, 0.01, 0.02, 0.03, 0.04], [30, 30, 30, 30, 30]),
+                      clock=clock, keep_results=True)
+    assert [r.rid for r in rep.failed] == [1, 3]
+    assert all(r.status == -5 and r.result is None for r in rep.failed)
+    assert [r.rid for r in rep.requests] == [0, 2, 4]
+    s = rep.summary()
+    assert s["requests"] == 3 and s["failed"] == 2
+    # throughput counts only the finished requests' work
+    assert abs(s["atom_steps_per_s"] * s["wall_s"] - (500 + 600 + 900) * 30) < 1e-6
+    assert ex.used == 0  # failed slots were released too
