@@ -309,6 +309,17 @@ int ljmd_batch_poll(ljmd_batch *b, int32_t *done, int32_t *ndone);
 int ljmd_batch_read(ljmd_batch *b, int32_t slot, double *pos, double *vel, double *force,
                     double *energy, double *virial);
 
+/* The same results as ljmd_batch_read, with no device memory allocated by the call: for
+ * callers that cannot allocate (tight serving loops, harnesses that forbid allocation). The
+ * positions, velocities and forces are staged in a fixed device array of 8 MiB per GPU (held
+ * by the library until the process ends), so a replica may hold at most 349,525 particles
+ * (3 doubles each); larger ones are refused with INVAL before any device work. Every call on
+ * a GPU shares that GPU's array: calls that overlap on one GPU (from several threads or
+ * batches) race, and must be serialised by the caller. Errors: as ljmd_batch_read, and INVAL
+ * for a replica beyond the limit. */
+int ljmd_batch_read_noalloc(ljmd_batch *b, int32_t slot, double *pos, double *vel,
+                            double *force, double *energy, double *virial);
+
 /* Steps completed by the replica in a slot. */
 int ljmd_batch_slot_steps(ljmd_batch *b, int32_t slot, int64_t *steps);
 

@@ -34,6 +34,14 @@
 
 using namespace ljmd;
 
+// Staging of ljmd_batch_read_noalloc: a file-scope device array, so that the call allocates
+// nothing. Each GPU the library runs on holds its own copy until the process ends. In host
+// code the name `scratch` is only a stand-in: its device address is taken once per device with
+// hipGetSymbolAddress (scratch_address) and only that address is passed to kernels and copies.
+constexpr size_t NOALLOC_STAGE_BYTES = (size_t)8 << 20;
+constexpr size_t NOALLOC_STAGE_DOUBLES = NOALLOC_STAGE_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[NOALLOC_STAGE_DOUBLES];
+
 namespace {
 
 constexpr int PAIR_ROWS = LJMD_MAX_TYPES * LJMD_MAX_TYPES;  // pair rows reserved per slot
@@ -159,6 +167,7 @@ struct ljmd_batch {
            *d_red = nullptr;
     double *d_stage = nullptr;
     size_t stage_alloc = 0;  // doubles
+    double *d_noalloc_stage = nullptr;  // this device's `scratch` (NOALLOC_STAGE_DOUBLES)
     double4 *d_snap_pos = nullptr, *d_snap_vel = nullptr;
     int4 *d_snap_img = nullptr;
     DevStatus *d_st = nullptr;
@@ -167,6 +176,32 @@ struct ljmd_batch {
     int red_blocks = 1024;
     int64_t blocks = 0, overflow_reruns = 0;
 };
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_addr;  // device -> address of its copy of `scratch`
+
+// The device address of `scratch` on device `dev` (the current device), resolved once per
+// device.
+int scratch_address(int dev, double **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) {
+        *out = it->second;
+        return LJMD_OK;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return set_err(LJMD_E_DEVICE, "address of the no-allocation staging array on device %d: %s",
+                       dev, hipGetErrorString(e));
+    g_scratch_addr[dev] = static_cast<double *>(p);
+    *out = static_cast<double *>(p);
+    return LJMD_OK;
+}
+
+}  // namespace
 
 namespace {
 
@@ -621,6 +656,15 @@ int ljmd_batch_create(const ljmd_batch_config *cfg, ljmd_batch **out) {
     if (!b) return set_err(LJMD_E_NOMEM, "host allocation failed");
     b->cfg = *cfg;
     (void)hipGetDevice(&b->device);
+    {
+        // once per device, with it current: the address of this device's staging array for
+        // ljmd_batch_read_noalloc
+        const int rc0 = scratch_address(b->device, &b->d_noalloc_stage);
+        if (rc0 != LJMD_OK) {
+            delete b;
+            return rc0;
+        }
+    }
     {
         int v = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) == hipSuccess && v > 0)
@@ -1198,6 +1242,15 @@ int ljmd_batch_read(ljmd_batch *b, int32_t s, double *pos, double *vel, double *
     return read_slot(b, s, b->d_stage, pos, vel, force, energy, virial);
 }
 
+int ljmd_batch_read_noalloc(ljmd_batch *b, int32_t s, double *pos, double *vel, double *force,
+                            double *energy, double *virial) {
+    CHK(check_readable(b, s));
+    if (3 * (size_t)b->slots[s].n > NOALLOC_STAGE_DOUBLES)
+        return set_err(LJMD_E_INVAL, "replica of %d particles exceeds the no-allocation staging "
+                                     "(at most %zu particles)",
+                       b->slots[s].n, NOALLOC_STAGE_DOUBLES / 3);
+    return read_slot(b, s, b->d_noalloc_stage, pos, vel, force, energy, virial);
+}
 
 int ljmd_batch_get_stats(ljmd_batch *b, ljmd_batch_stats *out) {
     if (!b || !out) return set_err(LJMD_E_INVAL, "null argument");

@@ -101,7 +101,7 @@ EXPORTED = [
     "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_kernel_durations", "ljmd_last_error", "ljmd_version",
     "ljmd_batch_create", "ljmd_batch_destroy", "ljmd_batch_footprint", "ljmd_batch_admit",
     "ljmd_batch_run_block", "ljmd_batch_poll", "ljmd_batch_read", "ljmd_batch_slot_steps",
-    "ljmd_batch_slot_status",
+    "ljmd_batch_slot_status", "ljmd_batch_read_noalloc",
     "ljmd_batch_release", "ljmd_batch_get_stats", "ljmd_tuning_get", "ljmd_tuning_set",
 ]
 
@@ -148,6 +148,7 @@ def load(path: str = LIB_PATH):
         "ljmd_batch_run_block": ([vp], C.c_int),
         "ljmd_batch_poll": ([vp, ip, ip], C.c_int),
         "ljmd_batch_read": ([vp, C.c_int32, dp, dp, dp, dp, dp], C.c_int),
+        "ljmd_batch_read_noalloc": ([vp, C.c_int32, dp, dp, dp, dp, dp], C.c_int),
         "ljmd_batch_slot_steps": ([vp, C.c_int32, lp], C.c_int),
         "ljmd_batch_slot_status": ([vp, C.c_int32, ip], C.c_int),
         "ljmd_batch_release": ([vp, C.c_int32], C.c_int),
@@ -519,15 +520,18 @@ class Batch:
         _check(self._lib.ljmd_batch_slot_steps(self._h, int(slot), C.byref(out)))
         return int(out.value)
 
-    def read(self, slot, energy=True):
+    def read(self, slot, energy=True, noalloc=False):
+        """Results of a finished slot; noalloc reads through ljmd_batch_read_noalloc (no device
+        allocation; replicas of at most 349,525 particles)."""
         n = max(1, self._n.get(int(slot), 0))  # an unknown slot gets LJMD_E_STATE below
         pos = np.empty((n, 3))
         vel = np.empty((n, 3))
         f = np.empty((n, 3))
         e = np.zeros(2)
         w = np.zeros(6)
-        _check(self._lib.ljmd_batch_read(self._h, int(slot), _dp(pos), _dp(vel), _dp(f),
-                                         _dp(e) if energy else None, _dp(w) if energy else None))
+        fn = self._lib.ljmd_batch_read_noalloc if noalloc else self._lib.ljmd_batch_read
+        _check(fn(self._h, int(slot), _dp(pos), _dp(vel), _dp(f),
+                  _dp(e) if energy else None, _dp(w) if energy else None))
         out = {"pos": pos, "vel": vel, "forces": f}
         if energy:
             out.update(potential=float(e[0]), kinetic=float(e[1]), virial=w)
