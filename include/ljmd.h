@@ -197,6 +197,21 @@ int ljmd_get_state(ljmd_system *sys, double *pos, double *vel, int32_t *img, int
 int ljmd_set_state(ljmd_system *sys, const double *pos, const double *vel, const int32_t *img,
                    const int64_t *step);
 
+/* Neighbour-list method (Section "Performance": the cell list, and the bounding volume
+ * hierarchy of nlist.tree for size-disperse systems, where a cell list sized for the largest
+ * cutoff makes small particles scan many cells to find few neighbours):
+ *   LJMD_NLIST_CELL  (default) cells at least as wide as the largest list radius, grouped into
+ *                    bricks whose halo atoms are staged in LDS; 16-bit tile-index lists.
+ *   LJMD_NLIST_TREE  one binary radix tree per particle type over that type's particles (in
+ *                    Morton order of fine cells), walked by each particle with its list radius
+ *                    for that type pair; 32-bit index lists. LJ form only.
+ * Both produce the same pair set (the definition above); list order, and hence the rounding
+ * of the force sums, differs. Changing the method rebuilds the list before the next step or
+ * read. Errors: INVAL (unknown method; the tree with another pair form at the next step). */
+#define LJMD_NLIST_CELL 0
+#define LJMD_NLIST_TREE 1
+int ljmd_set_nlist(ljmd_system *sys, int32_t method);
+
 /* The current neighbour list as unordered tag pairs (i < j), 2 x count int32, sorted by
  * (i, j); pairs = NULL only returns the count. build_pos (n x 3, tag order, nullable)
  * receives the positions the list was built from. */

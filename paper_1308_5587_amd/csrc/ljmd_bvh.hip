@@ -1,0 +1,288 @@
+// Tree (bounding volume hierarchy) neighbour lists for size-disperse systems (the paper's
+// nlist.tree, Section "Performance": a cell list sized for the largest cutoff makes small
+// particles scan many cells to find few neighbours).
+//
+// After the sort of a rebuild (typed sort grid: the particles of each type are contiguous and
+// in Morton order of fine cells), every type gets a binary radix tree over its particles built
+// by the Karras construction on the unique sorted keys (cell << 32 | index); node boxes are
+// formed bottom-up (the second child to finish forms its parent's box); then each particle
+// walks every type's tree with its list radius for that type pair and appends, as 32-bit sorted
+// indices, the particles j with r^2 < (r_cut + skin)^2 in the canonical FP64 arithmetic. The
+// walk order is fixed by the tree, so the list order is deterministic.
+//
+// Periodic images: a particle near a face also walks the tree with its position shifted by a
+// box length (at most 8 images); a leaf is accepted only in the image the minimum image of the
+// pair selects, so no pair is listed twice. Compiled with -ffp-contract=off.
+#include "ljmd_device.h"
+
+namespace ljmd {
+
+__device__ __forceinline__ bool bvh_go(const BvhArgs &b) {
+    return b.reps[0].active && b.go[0] != 0;
+}
+
+// Entry k of particle q in the 32-bit list: chunks of 4 entries per lane, lane l holds chunks
+// l, l + 2^ls, ...; for chunk index c the lanes of consecutive particles are adjacent.
+__device__ __forceinline__ size_t slot32(int q, int k, int npad, int ls) {
+    const int sh = 2 + ls;
+    return (size_t)((unsigned)k >> sh) * ((size_t)npad << sh) + ((size_t)q << sh) +
+           (size_t)(k & ((1 << sh) - 1));
+}
+
+// The type of sorted particle i and its type's range [s, e).
+__device__ __forceinline__ int bvh_type_range(const BvhArgs &b, int i, int &s, int &e) {
+    int t = 0;
+    while (t + 1 < b.ntypes && b.cell_start[(t + 1) * b.ncs] <= i) ++t;
+    s = b.cell_start[t * b.ncs];
+    e = b.cell_start[(t + 1) * b.ncs];
+    return t;
+}
+
+// The permuted state becomes the main state and the build positions.
+__global__ void __launch_bounds__(256) k_bvh_copy(const BvhArgs b) {
+    if (!bvh_go(b)) return;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) atomicAdd(&b.st->builds, 1ull);
+    if (q >= b.n) return;
+    const double4 x = b.pos_scr[q];
+    b.pos[q] = x;
+    b.xb[q] = x;
+    b.vel[q] = b.vel_scr[q];
+    b.img[q] = b.img_scr[q];
+}
+
+// Length of the common prefix of the keys of local leaves i and j of a type's range, or -1
+// when j is outside it. Keys (cell << 32 | global index) are unique and sorted.
+__device__ __forceinline__ int bvh_delta(const BvhArgs &b, int s, int nt, int i, int j) {
+    if (j < 0 || j >= nt) return -1;
+    const unsigned long long ki = ((unsigned long long)(unsigned)b.cell_of[s + i] << 32) |
+                                  (unsigned)(s + i);
+    const unsigned long long kj = ((unsigned long long)(unsigned)b.cell_of[s + j] << 32) |
+                                  (unsigned)(s + j);
+    return __clzll((long long)(ki ^ kj));
+}
+
+// Internal node i (local to its type's range) of the Karras construction: the direction of
+// its range from the prefix lengths to its neighbours, the range's other end by a doubling
+// then halving search, and the split where the prefix length drops.
+__global__ void __launch_bounds__(256) k_bvh_nodes(const BvhArgs b) {
+    if (!bvh_go(b)) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.n) return;
+    int s, e;
+    bvh_type_range(b, g, s, e);
+    const int nt = e - s;
+    const int i = g - s;
+    if (nt == 1) {
+        b.parent_leaf[s] = -1;
+        return;
+    }
+    if (i >= nt - 1) return;
+    const int node = s + i;
+    b.flag[node] = 0;
+    if (i == 0) b.parent_node[node] = -1;
+    const int dr = bvh_delta(b, s, nt, i, i + 1), dl = bvh_delta(b, s, nt, i, i - 1);
+    const int d = dr > dl ? 1 : -1;
+    const int dmin = d > 0 ? dl : dr;
+    int lmax = 2;
+    while (bvh_delta(b, s, nt, i, i + lmax * d) > dmin) lmax *= 2;
+    int l = 0;
+    for (int t = lmax / 2; t >= 1; t /= 2)
+        if (bvh_delta(b, s, nt, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = bvh_delta(b, s, nt, i, j);
+    int sp = 0;
+    int t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (bvh_delta(b, s, nt, i, i + (sp + t) * d) > dnode) sp += t;
+    } while (t > 1);
+    const int gamma = i + sp * d + (d < 0 ? -1 : 0);
+    const int lo = i < j ? i : j, hi = i < j ? j : i;
+    int left, right;
+    if (lo == gamma) {
+        left = (s + gamma) | BVH_LEAF;
+        b.parent_leaf[s + gamma] = node;
+    } else {
+        left = s + gamma;
+        b.parent_node[s + gamma] = node;
+    }
+    if (hi == gamma + 1) {
+        right = (s + gamma + 1) | BVH_LEAF;
+        b.parent_leaf[s + gamma + 1] = node;
+    } else {
+        right = s + gamma + 1;
+        b.parent_node[s + gamma + 1] = node;
+    }
+    b.left[node] = left;
+    b.right[node] = right;
+}
+
+__device__ __forceinline__ double coherent_load(const double *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The box of a child: a leaf's build position, or an internal node's stored box (read past
+// the non-coherent caches while boxes are still being formed, COHERENT).
+template <bool COHERENT>
+__device__ __forceinline__ void child_box(const BvhArgs &b, int c, double lo[3], double hi[3]) {
+    if (c & BVH_LEAF) {
+        const double4 x = b.xb[c & ~BVH_LEAF];
+        lo[0] = hi[0] = x.x;
+        lo[1] = hi[1] = x.y;
+        lo[2] = hi[2] = x.z;
+    } else {
+        const double *bx = b.box + 6 * (size_t)c;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = COHERENT ? coherent_load(bx + a) : bx[a];
+            hi[a] = COHERENT ? coherent_load(bx + 3 + a) : bx[3 + a];
+        }
+    }
+}
+
+// Boxes bottom-up: from each leaf, the second of a node's two children to arrive forms the
+// node's box from both children and climbs on; the first stops.
+__global__ void __launch_bounds__(256) k_bvh_boxes(const BvhArgs b) {
+    if (!bvh_go(b)) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= b.n) return;
+    int node = b.parent_leaf[g];
+    while (node >= 0) {
+        __threadfence();
+        if (atomicAdd(&b.flag[node], 1) == 0) return;
+        __threadfence();
+        double l0[3], h0[3], l1[3], h1[3];
+        child_box<true>(b, b.left[node], l0, h0);
+        child_box<true>(b, b.right[node], l1, h1);
+        double *bx = b.box + 6 * (size_t)node;
+        for (int a = 0; a < 3; ++a) {
+            bx[a] = fmin(l0[a], l1[a]);
+            bx[3 + a] = fmax(h0[a], h1[a]);
+        }
+        node = b.parent_node[node];
+    }
+}
+
+// Squared distance from q to a box (0 inside).
+__device__ __forceinline__ double box_dist2(const double q[3], const double lo[3],
+                                            const double hi[3]) {
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double d = q[a] < lo[a] ? lo[a] - q[a] : (q[a] > hi[a] ? q[a] - hi[a] : 0.0);
+        d2 = __builtin_fma(d, d, d2);
+    }
+    return d2;
+}
+
+// The image the branch-form minimum image of d picks: +1 when d >= L/2 (x_j lies near
+// x_i + L), -1 when d < -L/2, else 0; and the minimum-image difference.
+__device__ __forceinline__ int mi_side(double d, double L, double &out) {
+    const double h = 0.5 * L;
+    if (d >= h) {
+        out = d - L;
+        return 1;
+    }
+    if (d < -h) {
+        out = d + L;
+        return -1;
+    }
+    out = d;
+    return 0;
+}
+
+// One thread per particle: every type's tree, in every periodic image the particle's list
+// sphere reaches, in a fixed depth-first order.
+__global__ void __launch_bounds__(256) k_bvh_list(const BvhArgs b) {
+    if (!bvh_go(b)) return;
+    const RepParams &P = b.reps[0];
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int count = 0;
+    if (p < b.n) {
+        const double4 xi = b.xb[p];
+        const int ti = (int)xi.w;
+        const double xq[3] = {xi.x, xi.y, xi.z};
+        // depth-first walk: the stack never holds more than the tree depth + 1 nodes, and the
+        // depth is at most the number of key bits that vary (cells < 2^22, indices < 2^26)
+        int stack[BVH_STACK];
+        for (int t = 0; t < b.ntypes; ++t) {
+            const double rl2 = b.rl2_table[ti * b.ntypes + t];
+            const int s = b.cell_start[t * b.ncs], e = b.cell_start[(t + 1) * b.ncs];
+            if (!(rl2 > 0.0) || e <= s) continue;
+            const double rl = sqrt(rl2);
+            // box test with a relative margin: a box is never skipped for rounding
+            const double rl2_box = rl2 * (1.0 + 1e-12) + 1e-300;
+            const int root = (e - s == 1) ? (s | BVH_LEAF) : s;
+            int lo_img[3], hi_img[3];
+            for (int a = 0; a < 3; ++a) {
+                lo_img[a] = xq[a] >= P.L[a] - rl ? -1 : 0;
+                hi_img[a] = xq[a] < rl ? 1 : 0;
+            }
+            for (int sx = lo_img[0]; sx <= hi_img[0]; ++sx)
+                for (int sy = lo_img[1]; sy <= hi_img[1]; ++sy)
+                    for (int sz = lo_img[2]; sz <= hi_img[2]; ++sz) {
+                        const double q[3] = {xq[0] + sx * P.L[0], xq[1] + sy * P.L[1],
+                                             xq[2] + sz * P.L[2]};
+                        int top = 0;
+                        stack[top++] = root;
+                        while (top > 0) {
+                            const int c = stack[--top];
+                            if (c & BVH_LEAF) {
+                                const int j = c & ~BVH_LEAF;
+                                if (j == p) continue;
+                                const double4 xj = b.xb[j];
+                                double dx, dy, dz;
+                                const int kx = mi_side(xj.x - xi.x, P.L[0], dx);
+                                const int ky = mi_side(xj.y - xi.y, P.L[1], dy);
+                                const int kz = mi_side(xj.z - xi.z, P.L[2], dz);
+                                if (kx != sx || ky != sy || kz != sz) continue;
+                                const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+                                const double r2 = (xx + yy) + zz;
+                                if (r2 < rl2) {
+                                    if (count < b.cap)
+                                        b.nlist32[slot32(p, count, b.npad, b.lshift)] = j;
+                                    ++count;
+                                }
+                                continue;
+                            }
+                            // children: the right one is pushed first so the left is walked first
+                            const int ch[2] = {b.right[c], b.left[c]};
+                            for (int u = 0; u < 2; ++u) {
+                                double lo[3], hi[3];
+                                child_box<false>(b, ch[u], lo, hi);
+                                if (box_dist2(q, lo, hi) <= rl2_box && top < BVH_STACK)
+                                    stack[top++] = ch[u];
+                            }
+                        }
+                    }
+        }
+        b.nl_count[p] = count;
+        if (count > b.cap) atomicOr(&b.st->status, ST_OVERFLOW);
+    }
+    // build statistics, one atomic each per wavefront
+    int mx = count;
+    unsigned long long ent = (unsigned long long)(count < b.cap ? count : b.cap);
+    for (int o = 32; o > 0; o >>= 1) {
+        const int om = __shfl_xor(mx, o);
+        mx = om > mx ? om : mx;
+        ent += __shfl_xor(ent, o);
+    }
+    if ((threadIdx.x & 63) == 0 && mx > 0) {
+        atomicMax(&b.st->max_count, mx);
+        atomicAdd(&b.st->entries, ent);
+    }
+}
+
+hipError_t launch_rebuild_bvh(hipStream_t s, const RebuildArgs &a, const BvhArgs &b,
+                              hipEvent_t *ev) {
+    hipError_t e = launch_sort_cells(s, a, ev);
+    if (e != hipSuccess) return e;
+    const int g = (b.n + 255) / 256;
+    hipLaunchKernelGGL(k_bvh_copy, dim3(g), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bvh_nodes, dim3(g), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bvh_boxes, dim3(g), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bvh_list, dim3(g), dim3(256), 0, s, b);
+    if (ev) (void)hipEventRecord(ev[5], s);
+    return hipGetLastError();
+}
+
+}  // namespace ljmd

@@ -145,6 +145,97 @@ __device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double d
     }
 }
 
+// The end of a particle's pass: its force (and, with ENERGY, energy and virial halves) summed
+// over its TPP lanes with wavefront shuffles, then, on lane 0, the finish MODE asks for: the
+// force stored (MODE_EVAL), or the velocity-Verlet epilogue (MODE_FINAL: second half kick;
+// MODE_FUSED: second half kick, first half kick of the next step, drift, wrap and the
+// displacement check, which is returned).
+template <int PREC, int TPP, int MODE, bool ENERGY>
+__device__ __forceinline__ bool finish_particle(const ForceArgs &a, const RepParams &P, int q,
+                                                int rep, bool active, int lane, bool last,
+                                                const double4 &xi, const Acc<PREC> &acc,
+                                                double ue, double w0, double w1, double w2,
+                                                double w3, double w4, double w5) {
+    const double L0 = P.L[0], L1 = P.L[1], L2 = P.L[2];
+    const double iL0 = P.invL[0], iL1 = P.invL[1], iL2 = P.invL[2];
+    double fx, fy, fz;
+    if (PREC == PREC_FP64) {
+        fx = lane_sum<TPP>((double)acc.fx);
+        fy = lane_sum<TPP>((double)acc.fy);
+        fz = lane_sum<TPP>((double)acc.fz);
+    } else {
+        fx = (double)lane_sum<TPP>((float)acc.fx);
+        fy = (double)lane_sum<TPP>((float)acc.fy);
+        fz = (double)lane_sum<TPP>((float)acc.fz);
+    }
+    if (ENERGY) {
+        ue = lane_sum<TPP>(ue);
+        w0 = lane_sum<TPP>(w0);
+        w1 = lane_sum<TPP>(w1);
+        w2 = lane_sum<TPP>(w2);
+        w3 = lane_sum<TPP>(w3);
+        w4 = lane_sum<TPP>(w4);
+        w5 = lane_sum<TPP>(w5);
+    }
+    bool exceed = false;
+    if (active && lane == 0) {
+        const bool finite =
+            __builtin_isfinite(fx) && __builtin_isfinite(fy) && __builtin_isfinite(fz);
+        if (!finite) {
+            atomicOr(a.status, ST_NONFINITE);
+            if (a.rep_status) atomicOr(&a.rep_status[rep], ST_NONFINITE);
+        }
+        if (ENERGY) {
+            a.u_out[q] = ue;
+            double *w = a.w_out + 6 * (size_t)q;
+            w[0] = w0; w[1] = w1; w[2] = w2; w[3] = w3; w[4] = w4; w[5] = w5;
+        }
+        if (MODE == MODE_EVAL) {
+            a.force[q] = make_double4(fx, fy, fz, 0.0);
+        } else {
+            double4 v = a.vel[q];
+            const double hm = P.half_dt * v.w;
+            // second half kick of the current step: full-step velocity
+            v.x = __builtin_fma(hm, fx, v.x);
+            v.y = __builtin_fma(hm, fy, v.y);
+            v.z = __builtin_fma(hm, fz, v.z);
+            if (MODE == MODE_FINAL || last) {
+                // the replica's last step: no drift; the position stays in place
+                a.vel[q] = v;
+                a.force[q] = make_double4(fx, fy, fz, 0.0);
+                if (MODE == MODE_FUSED) a.pos_out[q] = xi;
+            } else {
+                if (ENERGY) {
+                    const double m = 1.0 / v.w;
+                    a.ke_out[q] = 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
+                }
+                // first half kick and drift of the next step
+                v.x = __builtin_fma(hm, fx, v.x);
+                v.y = __builtin_fma(hm, fy, v.y);
+                v.z = __builtin_fma(hm, fz, v.z);
+                double4 x = xi;
+                x.x = __builtin_fma(P.dt, v.x, x.x);
+                x.y = __builtin_fma(P.dt, v.y, x.y);
+                x.z = __builtin_fma(P.dt, v.z, x.z);
+                int4 im = a.img[q];
+                const int4 im0 = im;
+                wrap_coord(x.x, im.x, L0);
+                wrap_coord(x.y, im.y, L1);
+                wrap_coord(x.z, im.z, L2);
+                a.pos_out[q] = x;
+                a.vel[q] = v;
+                if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
+                const double4 b_pre = a.xb[q];
+                const double ex = mi_rint(x.x - b_pre.x, L0, iL0);
+                const double ey = mi_rint(x.y - b_pre.y, L1, iL1);
+                const double ez = mi_rint(x.z - b_pre.z, L2, iL2);
+                exceed = r2_canon(ex, ey, ez) >= P.lim2;
+            }
+        }
+    }
+    return exceed;
+}
+
 // The particle passes of one brick; STAGED selects neighbour positions from the LDS tile
 // (plain LDS reads) or, for a tile larger than the LDS allocation, from global memory.
 // MIF: bit a set when no pair of the brick can wrap on axis a (the minimum image is skipped
@@ -231,81 +322,8 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
             }
         }
 
-        double fx, fy, fz;
-        if (PREC == PREC_FP64) {
-            fx = lane_sum<TPP>((double)acc.fx);
-            fy = lane_sum<TPP>((double)acc.fy);
-            fz = lane_sum<TPP>((double)acc.fz);
-        } else {
-            fx = (double)lane_sum<TPP>((float)acc.fx);
-            fy = (double)lane_sum<TPP>((float)acc.fy);
-            fz = (double)lane_sum<TPP>((float)acc.fz);
-        }
-        if (ENERGY) {
-            ue = lane_sum<TPP>(ue);
-            w0 = lane_sum<TPP>(w0);
-            w1 = lane_sum<TPP>(w1);
-            w2 = lane_sum<TPP>(w2);
-            w3 = lane_sum<TPP>(w3);
-            w4 = lane_sum<TPP>(w4);
-            w5 = lane_sum<TPP>(w5);
-        }
-        bool exceed = false;
-        if (active && lane == 0) {
-            const bool finite =
-                __builtin_isfinite(fx) && __builtin_isfinite(fy) && __builtin_isfinite(fz);
-            if (!finite) {
-                atomicOr(a.status, ST_NONFINITE);
-                if (a.rep_status) atomicOr(&a.rep_status[rep], ST_NONFINITE);
-            }
-            if (ENERGY) {
-                a.u_out[q] = ue;
-                double *w = a.w_out + 6 * (size_t)q;
-                w[0] = w0; w[1] = w1; w[2] = w2; w[3] = w3; w[4] = w4; w[5] = w5;
-            }
-            if (MODE == MODE_EVAL) {
-                a.force[q] = make_double4(fx, fy, fz, 0.0);
-            } else {
-                double4 v = a.vel[q];
-                const double hm = P.half_dt * v.w;
-                // second half kick of the current step: full-step velocity
-                v.x = __builtin_fma(hm, fx, v.x);
-                v.y = __builtin_fma(hm, fy, v.y);
-                v.z = __builtin_fma(hm, fz, v.z);
-                if (MODE == MODE_FINAL || last) {
-                    // the replica's last step: no drift; the position stays in place
-                    a.vel[q] = v;
-                    a.force[q] = make_double4(fx, fy, fz, 0.0);
-                    if (MODE == MODE_FUSED) a.pos_out[q] = xi;
-                } else {
-                    if (ENERGY) {
-                        const double m = 1.0 / v.w;
-                        a.ke_out[q] = 0.5 * m * ((v.x * v.x + v.y * v.y) + v.z * v.z);
-                    }
-                    // first half kick and drift of the next step
-                    v.x = __builtin_fma(hm, fx, v.x);
-                    v.y = __builtin_fma(hm, fy, v.y);
-                    v.z = __builtin_fma(hm, fz, v.z);
-                    double4 x = xi;
-                    x.x = __builtin_fma(P.dt, v.x, x.x);
-                    x.y = __builtin_fma(P.dt, v.y, x.y);
-                    x.z = __builtin_fma(P.dt, v.z, x.z);
-                    int4 im = a.img[q];
-                    const int4 im0 = im;
-                    wrap_coord(x.x, im.x, L0);
-                    wrap_coord(x.y, im.y, L1);
-                    wrap_coord(x.z, im.z, L2);
-                    a.pos_out[q] = x;
-                    a.vel[q] = v;
-                    if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
-                    const double4 b_pre = a.xb[q];
-                    const double ex = mi_rint(x.x - b_pre.x, L0, iL0);
-                    const double ey = mi_rint(x.y - b_pre.y, L1, iL1);
-                    const double ez = mi_rint(x.z - b_pre.z, L2, iL2);
-                    exceed = r2_canon(ex, ey, ez) >= P.lim2;
-                }
-            }
-        }
+        const bool exceed = finish_particle<PREC, TPP, MODE, ENERGY>(
+            a, P, q, rep, active, lane, last, xi, acc, ue, w0, w1, w2, w3, w4, w5);
         if (MODE == MODE_FUSED) {
             // all particles of the workgroup belong to one replica: one atomic per wavefront
             const unsigned long long vote = __ballot(exceed);

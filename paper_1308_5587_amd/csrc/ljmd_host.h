@@ -4,7 +4,7 @@
 #pragma once
 
 #include "ljmd_internal.h"
-#include "../../include/ljmd.h"
+#include "ljmd.h"
 
 #include <cstdint>
 #include <string>

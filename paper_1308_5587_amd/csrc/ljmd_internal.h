@@ -145,6 +145,7 @@ struct ForceArgs {
     double4 *force;          // MODE_EVAL / MODE_FINAL output
     const int *nl_count;
     const uint16_t *nlist;   // 16-bit tile indices
+    const int32_t *nlist32;  // tree lists: 32-bit sorted-order indices (k_force_glist)
     const uint16_t *work;    // per brick: order in which its particles are taken
     const BrickInfo *bricks;
     const int *cell_start;
@@ -220,6 +221,33 @@ struct RebuildArgs {
     int *rep_status;         // per-replica status bits (or null)
     int n, ncell, nbrick, nrep;   // slot counts of the arrays
     int npad, cap, lshift, tile_cap, max_ntypes;
+    // tree (BVH) lists: the sort grid's cells are (type, cx, cy, cz), type-major, so each
+    // type's particles are contiguous; the gather then records each particle's cell
+    int typed_cells;              // spatial cells per type (0: cells are spatial only)
+    int *cell_of;                 // cell of each particle in the new order (or null)
+};
+
+// Tree (BVH) neighbour lists, one tree per particle type over the type's particles in their
+// sorted order: the Karras construction on the keys (cell << 32 | index), boxes bottom-up,
+// and one traversal per particle and tree.
+constexpr int BVH_LEAF = 1 << 30;   // child code: a leaf (particle index | BVH_LEAF)
+constexpr int BVH_STACK = 64;       // traversal stack (tree depth is at most the 64 key bits)
+struct BvhArgs {
+    const RepParams *reps;
+    const int *go;           // rebuild gate (go[0])
+    double4 *pos, *pos_scr, *vel, *vel_scr, *xb;
+    int4 *img, *img_scr;
+    const int *cell_start;   // typed cells: type t is [cell_start[t ncs], cell_start[(t+1) ncs])
+    const int *cell_of;
+    int *left, *right;       // internal node children (node of type t at s_t + local index)
+    int *parent_leaf, *parent_node;
+    int *flag;               // bottom-up arrival counters (cleared by the node kernel)
+    double *box;             // 6 doubles per internal node: lo x y z, hi x y z
+    const double *rl2_table; // list radii squared per type pair (0: pair disabled)
+    int *nl_count;
+    int32_t *nlist32;        // 32-bit sorted-order indices, 4 per 16-byte chunk (see slot32)
+    DevStatus *st;
+    int n, ntypes, ncs, npad, cap, lshift;
 };
 
 // ---------------------------------------------------------------- launchers
@@ -239,6 +267,13 @@ hipError_t launch_force_gauss(hipStream_t s, const ForceArgs &a, int prec, int t
 hipError_t launch_force_yukawa(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
                                bool energy, int block);
 hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev = nullptr);
+// The sort of launch_rebuild (bin, scan, scatter, gather) over the typed sort grid, then the
+// tree build and traversal; ev as for launch_rebuild (the tree kernels in the last slot).
+hipError_t launch_rebuild_bvh(hipStream_t s, const RebuildArgs &a, const BvhArgs &b,
+                              hipEvent_t *ev = nullptr);
+hipError_t launch_sort_cells(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev);
+hipError_t launch_force_glist(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                              bool energy, int block);
 hipError_t launch_reduce(hipStream_t s, const double *u, const double *w, const double *ke,
                          const double4 *vel, int poff, int n, double *partials, int nblocks_max,
                          double *out);

@@ -159,7 +159,8 @@ __global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
             const int cx = cell_coord(x.x * P.inv_w[0], P.nc[0]);
             const int cy = cell_coord(x.y * P.inv_w[1], P.nc[1]);
             const int cz = cell_coord(x.z * P.inv_w[2], P.nc[2]);
-            r = a.cell_rank[P.coff + (cx * P.nc[1] + cy) * P.nc[2] + cz];
+            const int tcell = a.typed_cells ? (int)x.w * a.typed_cells : 0;
+            r = a.cell_rank[P.coff + tcell + (cx * P.nc[1] + cy) * P.nc[2] + cz];
         }
     }
     const int prev = __shfl_up(r, 1);
@@ -244,10 +245,11 @@ __global__ void __launch_bounds__(256) k_scatter(const RebuildArgs a) {
 // Order each cell's members by their previous sorted index (a stable counting sort) and
 // gather their state into the new order. One workgroup of 64 lanes per cell (grid-stride);
 // the rank of a member is the number of members with a smaller index.
-__device__ __forceinline__ void gather_member(const RebuildArgs &a, int dst, int k) {
+__device__ __forceinline__ void gather_member(const RebuildArgs &a, int dst, int k, int c) {
     a.pos_scr[dst] = a.pos[k];
     a.vel_scr[dst] = a.vel[k];
     a.img_scr[dst] = a.img[k];
+    if (a.cell_of) a.cell_of[dst] = c;
 }
 
 __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
                 const int v = s_in[t];
                 int rank = 0;
                 for (int u = 0; u < m; ++u) rank += s_in[u] < v;
-                gather_member(a, beg + rank, v);
+                gather_member(a, beg + rank, v, c);
             }
         } else {
             if (threadIdx.x == 0) {
@@ -281,7 +283,7 @@ __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
             }
             __syncthreads();
             for (int t = threadIdx.x; t < m; t += blockDim.x)
-                gather_member(a, beg + t, a.perm[beg + t]);
+                gather_member(a, beg + t, a.perm[beg + t], c);
         }
     }
 }
@@ -628,12 +630,11 @@ hipError_t launch_decode_list(hipStream_t s, const RebuildArgs &a, int *out) {
     return hipGetLastError();
 }
 
-hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev) {
-    if (!lds_args_ok(a.tile_cap, a.max_ntypes, nlist_lds_bytes(a.tile_cap, a.max_ntypes)))
-        return hipErrorInvalidValue;
+// The sort of a rebuild: bin, scan, scatter and in-cell gather; ev (optional): the first five
+// of the six events around a rebuild's kernels, for measurement.
+hipError_t launch_sort_cells(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev) {
     const int b = 256;
     const int g = (a.n + b - 1) / b;
-    // ev (optional): six events around the five kernels, for measurement
     if (ev) (void)hipEventRecord(ev[0], s);
     hipLaunchKernelGGL(k_bin, dim3(g), dim3(b), 0, s, a);
     if (ev) (void)hipEventRecord(ev[1], s);
@@ -643,6 +644,15 @@ hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[3], s);
     hipLaunchKernelGGL(k_cell_gather, dim3(a.ncell < 8192 ? a.ncell : 8192), dim3(64), 0, s, a);
     if (ev) (void)hipEventRecord(ev[4], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev) {
+    if (!lds_args_ok(a.tile_cap, a.max_ntypes, nlist_lds_bytes(a.tile_cap, a.max_ntypes)))
+        return hipErrorInvalidValue;
+    // ev (optional): six events around the five kernels, for measurement
+    const hipError_t e = launch_sort_cells(s, a, ev);
+    if (e != hipSuccess) return e;
     const size_t smem = nlist_lds_bytes(a.tile_cap, a.max_ntypes);
     if (a.max_ntypes > 1)
         hipLaunchKernelGGL(k_nlist<true>, dim3(a.nbrick), dim3(512), smem, s, a);

@@ -89,6 +89,15 @@ struct ljmd_system {
     double *d_stage = nullptr;  // n x 10 doubles of upload/download staging
     double4 *d_snap_pos = nullptr, *d_snap_vel = nullptr;
     int4 *d_snap_img = nullptr;
+    // neighbour-list method: cell-list bricks (16-bit tile lists) or one tree per type
+    // (32-bit lists, LJMD_NLIST_TREE); the tree method's typed sort grid has ncs spatial cells
+    int nlist_method = LJMD_NLIST_CELL;
+    int ncs = 0;
+    int *d_cell_of = nullptr, *d_bvh_left = nullptr, *d_bvh_right = nullptr,
+        *d_bvh_pleaf = nullptr, *d_bvh_pnode = nullptr, *d_bvh_flag = nullptr;
+    double *d_bvh_box = nullptr;
+    int32_t *d_nlist32 = nullptr;
+    size_t nlist32_alloc = 0;
     // NVT thermostat: device scalars (TH_*), their snapshot, kinetic-energy partials
     bool nvt = false;
     bool nvt_ready = false;  // the half step opening the next step is on the device
@@ -149,6 +158,55 @@ int launch_chk(hipError_t e, const char *what) {
 
 // ------------------------------------------------------------ pair table and cell grid
 
+// The tree method's sort grid: fine cells of about four particles, at most 1023 per axis and
+// 2^22 in all with the type as the slowest index; cells in Morton order within each type, so
+// each type's particles end up contiguous and spatially ordered (the trees' leaf order).
+int make_sort_grid(ljmd_system *s, double rl_max, ReplicaGrid *g) {
+    for (int a = 0; a < 3; ++a)
+        if (rl_max > 0.5 * s->L[a])
+            return set_err(LJMD_E_BOX, "r_cut + skin = %g exceeds half the box edge %g", rl_max,
+                           s->L[a]);
+    const double vol = s->L[0] * s->L[1] * s->L[2];
+    double w = std::cbrt(4.0 * vol / std::max(1, s->n));
+    int nc[3];
+    for (;;) {
+        int64_t tot = s->ntypes;
+        for (int a = 0; a < 3; ++a) {
+            nc[a] = (int)std::max(1.0, std::min(1023.0, std::floor(s->L[a] / w)));
+            tot *= nc[a];
+        }
+        if (tot <= ((int64_t)1 << 22)) break;
+        w *= 1.25;
+    }
+    const int ncs = nc[0] * nc[1] * nc[2];
+    std::vector<std::pair<uint64_t, int>> order(ncs);
+    for (int x = 0; x < nc[0]; ++x)
+        for (int y = 0; y < nc[1]; ++y)
+            for (int z = 0; z < nc[2]; ++z) {
+                uint64_t code = 0;
+                for (int bit = 0; bit < 10; ++bit)
+                    code |= ((uint64_t)((x >> bit) & 1) << (3 * bit + 2)) |
+                            ((uint64_t)((y >> bit) & 1) << (3 * bit + 1)) |
+                            ((uint64_t)((z >> bit) & 1) << (3 * bit));
+                const int lin = (x * nc[1] + y) * nc[2] + z;
+                order[lin] = {code, lin};
+            }
+    std::sort(order.begin(), order.end());
+    g->rank.assign((size_t)ncs * s->ntypes, 0);
+    g->xyz.assign((size_t)ncs * s->ntypes, 0);
+    for (int r = 0; r < ncs; ++r)
+        for (int t = 0; t < s->ntypes; ++t) g->rank[(size_t)t * ncs + order[r].second] = t * ncs + r;
+    for (int a = 0; a < 3; ++a) g->nc[a] = nc[a];
+    g->canonical = false;
+    g->ncell = ncs * s->ntypes;
+    g->nbrick = 0;
+    g->max_halo = 0;
+    s->ncs = ncs;
+    return LJMD_OK;
+}
+
+int ensure_tree_arrays(ljmd_system *s);
+
 int setup_table(ljmd_system *s) {
     const int nt = s->ntypes;
     for (int k = 0; k < nt * nt; ++k)
@@ -160,7 +218,13 @@ int setup_table(ljmd_system *s) {
     else
         make_form_table(nt, s->style, s->par.data(), s->rc.data(), s->cfg.skin, &pt);
     ReplicaGrid g;
-    CHK(make_grid(s->L, pt.rl_max, &g, s->n, tile_limit_for(nt, s->lds_limit)));
+    if (s->nlist_method == LJMD_NLIST_TREE) {
+        if (s->style != STYLE_LJ)
+            return set_err(LJMD_E_INVAL, "tree neighbour lists evaluate the LJ form only");
+        CHK(make_sort_grid(s, pt.rl_max, &g));
+    } else {
+        CHK(make_grid(s->L, pt.rl_max, &g, s->n, tile_limit_for(nt, s->lds_limit)));
+    }
     const int ncell = g.ncell;
     if (ncell + 1 > s->ncell_alloc) {
         dfree(s, s->d_cell_rank);
@@ -175,7 +239,7 @@ int setup_table(ljmd_system *s) {
         CHK(dalloc_t(s, &s->d_cell_start, ncell + 1));
         s->ncell_alloc = ncell + 1;
     }
-    if (g.nbrick > s->nbrick_alloc) {
+    if (g.nbrick > 0 && g.nbrick > s->nbrick_alloc) {
         dfree(s, s->d_bricks);
         dfree(s, s->d_halo);
         dfree(s, s->d_tile_tab);
@@ -211,7 +275,7 @@ int setup_table(ljmd_system *s) {
     P.ntypes = nt;
     P.pair_off = 0;
     P.active = 1;
-    P.tile_cap = grid_tile_cap(g, s->n, nt, s->lds_limit);
+    P.tile_cap = g.nbrick > 0 ? grid_tile_cap(g, s->n, nt, s->lds_limit) : 64;
     HIPCHK(hipMemcpyAsync(s->d_rep, &P, sizeof(RepParams), hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->d_pair, pt.coef.data(), sizeof(PairCoef) * nt * nt,
                           hipMemcpyHostToDevice, s->stream));
@@ -222,10 +286,14 @@ int setup_table(ljmd_system *s) {
     HIPCHK(hipMemcpyAsync(s->d_cell_xyz, g.xyz.data(), sizeof(int) * ncell, hipMemcpyHostToDevice,
                           s->stream));
     HIPCHK(hipMemsetAsync(s->d_cell_count, 0, sizeof(int) * (ncell + 1), s->stream));
-    HIPCHK(hipMemcpyAsync(s->d_bricks, g.bricks.data(), sizeof(BrickInfo) * g.nbrick,
-                          hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(s->d_halo, g.halo.data(), sizeof(HaloCell) * (size_t)g.nbrick * HALO_MAX,
-                          hipMemcpyHostToDevice, s->stream));
+    if (g.nbrick > 0) {
+        HIPCHK(hipMemcpyAsync(s->d_bricks, g.bricks.data(), sizeof(BrickInfo) * g.nbrick,
+                              hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(s->d_halo, g.halo.data(),
+                              sizeof(HaloCell) * (size_t)g.nbrick * HALO_MAX,
+                              hipMemcpyHostToDevice, s->stream));
+    }
+    if (s->nlist_method == LJMD_NLIST_TREE) CHK(ensure_tree_arrays(s));
     HIPCHK(hipStreamSynchronize(s->stream));  // host vectors go out of scope
     s->rl_max = pt.rl_max;
     s->ncell = ncell;
@@ -238,19 +306,42 @@ int setup_table(ljmd_system *s) {
     return LJMD_OK;
 }
 
-// The list build addresses rounds of 8 x lanes entries with a 32-bit stride.
+// The tree method's node, box and cell arrays (n each; boxes 6 doubles per node).
+int ensure_tree_arrays(ljmd_system *s) {
+    if (s->d_cell_of) return LJMD_OK;
+    const size_t N = (size_t)s->n;
+    CHK(dalloc_t(s, &s->d_cell_of, N));
+    CHK(dalloc_t(s, &s->d_bvh_left, N));
+    CHK(dalloc_t(s, &s->d_bvh_right, N));
+    CHK(dalloc_t(s, &s->d_bvh_pleaf, N));
+    CHK(dalloc_t(s, &s->d_bvh_pnode, N));
+    CHK(dalloc_t(s, &s->d_bvh_flag, N));
+    CHK(dalloc_t(s, &s->d_bvh_box, 6 * N));
+    return LJMD_OK;
+}
+
+// The list build addresses rounds of 8 x lanes entries (16-bit lists) or 4 x lanes entries
+// (32-bit tree lists) with a 32-bit stride.
 bool lanes_fit(int npad, int lshift) { return ((uint64_t)npad << (3 + lshift)) <= 0xFFFFFFFFull; }
 
 int ensure_list_alloc(ljmd_system *s, int cap) {
     if (!lanes_fit(s->npad, s->lshift))
         return set_err(LJMD_E_INVAL, "%d lanes per particle is too many for %d particles",
                        1 << s->lshift, s->n);
-    // a multiple of 8 x lanes per particle (whole chunks of 8 entries per lane) keeps every
-    // slot of k < cap inside cap * npad
-    const int unit = 8 << s->lshift;
+    // a multiple of (entries per chunk) x lanes per particle (whole chunks per lane) keeps
+    // every slot of k < cap inside cap * npad
+    const bool tree = s->nlist_method == LJMD_NLIST_TREE;
+    const int unit = (tree ? 4 : 8) << s->lshift;
     cap = std::max(unit, (cap + unit - 1) / unit * unit);
     const size_t need = (size_t)cap * (size_t)s->npad;
-    if (need > s->nlist_alloc) {
+    if (tree && need > s->nlist32_alloc) {
+        dfree(s, s->d_nlist32);
+        s->d_nlist32 = nullptr;
+        s->nlist32_alloc = 0;
+        CHK(dalloc_t(s, &s->d_nlist32, need));
+        s->nlist32_alloc = need;
+    }
+    if (!tree && need > s->nlist_alloc) {
         dfree(s, s->d_nlist);
         s->d_nlist = nullptr;
         s->nlist_alloc = 0;
@@ -305,7 +396,51 @@ RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
     a.lshift = s->lshift;
     a.tile_cap = s->tile_cap;
     a.max_ntypes = s->ntypes;
+    const bool tree = s->nlist_method == LJMD_NLIST_TREE;
+    a.typed_cells = tree ? s->ncs : 0;
+    a.cell_of = tree ? s->d_cell_of : nullptr;
     return a;
+}
+
+BvhArgs bvh_args(ljmd_system *s, const int *go, int cur) {
+    BvhArgs b{};
+    b.reps = s->d_rep;
+    b.go = go;
+    b.pos = s->d_pos[cur];
+    b.pos_scr = s->d_pos_scr;
+    b.vel = s->d_vel;
+    b.vel_scr = s->d_vel_scr;
+    b.xb = s->d_xb;
+    b.img = s->d_img;
+    b.img_scr = s->d_img_scr;
+    b.cell_start = s->d_cell_start;
+    b.cell_of = s->d_cell_of;
+    b.left = s->d_bvh_left;
+    b.right = s->d_bvh_right;
+    b.parent_leaf = s->d_bvh_pleaf;
+    b.parent_node = s->d_bvh_pnode;
+    b.flag = s->d_bvh_flag;
+    b.box = s->d_bvh_box;
+    b.rl2_table = s->d_rl2;
+    b.nl_count = s->d_count;
+    b.nlist32 = s->d_nlist32;
+    b.st = s->d_st;
+    b.n = s->n;
+    b.ntypes = s->ntypes;
+    b.ncs = s->ncs;
+    b.npad = s->npad;
+    b.cap = s->cap;
+    b.lshift = s->lshift;
+    return b;
+}
+
+// The rebuild kernels of the system's list method at buffer cur, gated by go[0].
+hipError_t launch_list_rebuild(ljmd_system *s, hipStream_t st, const int *go, int cur,
+                               hipEvent_t *ev = nullptr) {
+    RebuildArgs ra = rebuild_args(s, go, cur);
+    if (s->nlist_method == LJMD_NLIST_TREE)
+        return launch_rebuild_bvh(st, ra, bvh_args(s, go, cur), ev);
+    return launch_rebuild(st, ra, ev);
 }
 
 ForceArgs force_args(ljmd_system *s, int cur) {
@@ -319,6 +454,7 @@ ForceArgs force_args(ljmd_system *s, int cur) {
     a.force = s->d_force;
     a.nl_count = s->d_count;
     a.nlist = s->d_nlist;
+    a.nlist32 = s->d_nlist32;
     a.work = s->d_work;
     a.bricks = s->d_bricks;
     a.cell_start = s->d_cell_start;
@@ -360,14 +496,20 @@ KickDriftArgs kick_drift_args(ljmd_system *s, int cur) {
 
 // unconditional rebuild at the current positions
 int enqueue_forced_rebuild(ljmd_system *s) {
-    RebuildArgs a = rebuild_args(s, s->d_one, s->cur);
-    return launch_chk(launch_rebuild(s->stream, a), "rebuild");
+    return launch_chk(launch_list_rebuild(s, s->stream, s->d_one, s->cur), "rebuild");
+}
+
+// The force kernel of the system's list method and pair form.
+hipError_t launch_forces(ljmd_system *s, hipStream_t st, const ForceArgs &fa, int mode,
+                         bool energy) {
+    if (s->nlist_method == LJMD_NLIST_TREE)
+        return launch_force_glist(st, fa, precision(s), s->tpp, mode, energy, s->block);
+    return launch_force(st, fa, precision(s), s->tpp, mode, energy, s->block, s->style);
 }
 
 int enqueue_eval(ljmd_system *s, bool energy) {
     ForceArgs a = force_args(s, s->cur);
-    return launch_chk(launch_force(s->stream, a, precision(s), s->tpp, MODE_EVAL, energy, s->block, s->style),
-                      "force eval");
+    return launch_chk(launch_forces(s, s->stream, a, MODE_EVAL, energy), "force eval");
 }
 
 // Build the list at the current positions, growing the capacity until it fits.
@@ -542,13 +684,11 @@ int enqueue_nvt_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev
     KickDriftArgs ka = kick_drift_args(s, cur);
     ka.scale = s->d_th + TH_SPEND;  // TH_SPEND, TH_SB
     CHK(launch_chk(launch_kick_drift(st, ka), "kick-drift"));
-    RebuildArgs ra = rebuild_args(s, s->d_req + (cur ^ 1), cur ^ 1);
     hipEvent_t *rev = timed ? &s->ev[EV_PER_UNIT * ev_index + 2] : nullptr;
-    CHK(launch_chk(launch_rebuild(st, ra, rev), "rebuild"));
+    CHK(launch_chk(launch_list_rebuild(s, st, s->d_req + (cur ^ 1), cur ^ 1, rev), "rebuild"));
     ForceArgs fa = force_args(s, cur ^ 1);
     if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index], st));
-    CHK(launch_chk(launch_force(st, fa, precision(s), s->tpp, MODE_FINAL, false, s->block, s->style),
-                   "force"));
+    CHK(launch_chk(launch_forces(s, st, fa, MODE_FINAL, false), "force"));
     if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index + 1], st));
     int np = 0;
     CHK(launch_chk(launch_ke_partials(st, s->d_vel, 0, s->n, s->d_kpart, s->red_blocks, &np),
@@ -561,12 +701,10 @@ int enqueue_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_ind
     if (s->nvt) return enqueue_nvt_unit(s, st, cur, timed, ev_index);
     ForceArgs fa = force_args(s, cur);
     if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index], st));
-    CHK(launch_chk(launch_force(st, fa, precision(s), s->tpp, MODE_FUSED, false, s->block, s->style),
-                   "fused step"));
+    CHK(launch_chk(launch_forces(s, st, fa, MODE_FUSED, false), "fused step"));
     if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index + 1], st));
-    RebuildArgs ra = rebuild_args(s, s->d_req + (cur ^ 1), cur ^ 1);
     hipEvent_t *rev = timed ? &s->ev[EV_PER_UNIT * ev_index + 2] : nullptr;
-    return launch_chk(launch_rebuild(st, ra, rev), "rebuild");
+    return launch_chk(launch_list_rebuild(s, st, s->d_req + (cur ^ 1), cur ^ 1, rev), "rebuild");
 }
 
 int capture_graph(ljmd_system *s, int cur) {
@@ -689,8 +827,7 @@ int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
         KickDriftArgs ka = kick_drift_args(s, s->cur);
         CHK(launch_chk(launch_kick_drift(s->stream, ka), "kick-drift"));
         s->cur ^= 1;
-        RebuildArgs ra = rebuild_args(s, s->d_req + s->cur, s->cur);
-        CHK(launch_chk(launch_rebuild(s->stream, ra), "rebuild"));
+        CHK(launch_chk(launch_list_rebuild(s, s->stream, s->d_req + s->cur, s->cur), "rebuild"));
     }
     const int64_t units = nsteps - 1;
     const bool use_graph = s->graph_steps > 0 && !s->timing;
@@ -708,8 +845,7 @@ int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
         }
     }
     ForceArgs fa = force_args(s, s->cur);
-    CHK(launch_chk(launch_force(s->stream, fa, precision(s), s->tpp, MODE_FINAL, false, s->block, s->style),
-                   "final"));
+    CHK(launch_chk(launch_forces(s, s->stream, fa, MODE_FINAL, false), "final"));
     DevStatus st{};
     CHK(sync_status(s, &st));
     if (s->timing) CHK(collect_timing(s, units));
@@ -749,6 +885,28 @@ int decode_list(ljmd_system *s, std::vector<int> &cnt, std::vector<int> &ent,
                 std::vector<int4> &img) {
     CHK(ensure_ready(s));
     const size_t N = (size_t)s->n;
+    if (s->nlist_method == LJMD_NLIST_TREE) {
+        // 32-bit lists hold sorted indices already: copy and reorder rows on the host
+        std::vector<int32_t> raw((size_t)s->cap * s->npad);
+        cnt.assign(N, 0);
+        img.assign(N, int4{});
+        HIPCHK(hipMemcpyAsync(cnt.data(), s->d_count, N * sizeof(int), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipMemcpyAsync(img.data(), s->d_img, N * sizeof(int4), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipMemcpyAsync(raw.data(), s->d_nlist32, raw.size() * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        ent.assign(N * (size_t)s->cap, 0);
+        const int sh = 2 + s->lshift;
+        for (size_t q = 0; q < N; ++q) {
+            const int c = std::min(cnt[q], s->cap);
+            for (int k = 0; k < c; ++k) {
+                const size_t slot = (size_t)((unsigned)k >> sh) * ((size_t)s->npad << sh) +
+                                    (q << sh) + (size_t)(k & ((1 << sh) - 1));
+                ent[q * (size_t)s->cap + k] = raw[slot];
+            }
+        }
+        return LJMD_OK;
+    }
     int *d_out = nullptr;
     CHK(dalloc_t(s, &d_out, N * (size_t)s->cap));
     RebuildArgs ra = rebuild_args(s, s->d_one, s->cur);
@@ -1221,6 +1379,21 @@ int ljmd_negate_velocities(ljmd_system *s) {
     CHK(launch_chk(launch_negate_vel(s->stream, s->d_vel, 0, s->n), "negate"));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->nvt_ready = false;
+    return LJMD_OK;
+}
+
+int ljmd_set_nlist(ljmd_system *s, int32_t method) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (method != LJMD_NLIST_CELL && method != LJMD_NLIST_TREE)
+        return set_err(LJMD_E_INVAL, "unknown neighbour-list method %d", method);
+    if (method == s->nlist_method) return LJMD_OK;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->nlist_method = method;
+    s->cap = 0;  // the list is sized afresh for the method's layout
+    s->table_dirty = true;
+    s->list_valid = false;
+    s->force_valid = false;
+    drop_graphs(s);
     return LJMD_OK;
 }
 

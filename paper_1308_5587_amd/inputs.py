@@ -178,6 +178,61 @@ def make_lj_droplet(
     )
 
 
+def colloid_pair_table(sigma_l: float, cut_factor: float = 2.5):
+    """Size-disperse binary LJ mixture: small particles (type 0, sigma 1) and large ones
+    (type 1, sigma sigma_l), mixed sigma the arithmetic mean, epsilon 1, r_cut = cut_factor
+    sigma_ab (2^(1/6) sigma_ab gives the purely repulsive WCA form)."""
+    sig = {(0, 0): 1.0, (0, 1): 0.5 * (1.0 + sigma_l), (1, 1): sigma_l}
+    return [(a, b, 1.0, sig[(a, b)], cut_factor * sig[(a, b)]) for (a, b) in sig]
+
+
+def make_colloid_mixture(
+    n_large_side: int = 6,
+    sigma_l: float = 3.0,
+    spacing_l: float = 5.5,
+    rho_small: float = 0.6,
+    T: float = 1.0,
+    seed: int = 1,
+    cut_factor: float = 2.5,
+    jitter: float = 0.05,
+) -> LJSystemSpec:
+    """Size-disperse binary mixture (the case a cell list sized for the largest cutoff serves
+    badly): large particles (type 1) on a simple-cubic lattice of n_large_side^3 sites at
+    spacing ``spacing_l`` and small particles (type 0) on a simple-cubic lattice at density
+    ``rho_small``, without the small sites closer to a large centre than (1 + sigma_l) / 2;
+    uniform jitter, Maxwell-Boltzmann velocities at T."""
+    rng = np.random.default_rng(seed)
+    L = n_large_side * spacing_l
+    g = (np.arange(n_large_side) + 0.5) * spacing_l
+    large = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    m = int(round(L * rho_small ** (1.0 / 3.0)))
+    h = (np.arange(m) + 0.5) * (L / m)
+    small = np.stack(np.meshgrid(h, h, h, indexing="ij"), -1).reshape(-1, 3)
+    excl = 0.5 * (1.0 + sigma_l)
+    keep = np.ones(len(small), dtype=bool)
+    for c in large:
+        d = small - c
+        d -= L * np.rint(d / L)
+        keep &= (d * d).sum(1) >= excl * excl
+    pos = np.concatenate([small[keep], large])
+    pos += rng.uniform(-jitter, jitter, size=pos.shape)
+    pos %= L
+    n = pos.shape[0]
+    vel = _mb_velocities(rng, n, T)
+    typ = np.zeros(n, dtype=np.int32)
+    typ[int(keep.sum()):] = 1
+    return LJSystemSpec(
+        box=np.array([L, L, L], dtype=np.float64),
+        pos=np.ascontiguousarray(pos),
+        vel=np.ascontiguousarray(vel),
+        type=typ,
+        ntypes=2,
+        pairs=colloid_pair_table(sigma_l, cut_factor),
+        seed=seed,
+        name=f"colloid_N{n}_sigma{sigma_l}",
+    )
+
+
 def ka_pair_table(cut_factor: float = 2.5):
     """Kob-Andersen 80:20 binary mixture parameters; r_cut = cut_factor * sigma_ab."""
     eps = {(0, 0): 1.0, (0, 1): 1.5, (1, 1): 0.5}
