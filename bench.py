@@ -24,6 +24,9 @@ Also reported on that line:
   paper_benchmark  the paper's LJ liquid benchmark (N = 64,000, density 0.382,
                 r_cut = 3.0, NVT kT = 1.2, tau = 1.0, dt = 0.005), beside the paper's own
                 figures for other hardware (context only).
+  size_disperse a size-disperse LJ mixture (size ratio 3:1, N = 1.1 M, of which 13,824 large),
+                FP64, with the cell list and with the tree lists: atom-steps/s of each and
+                the list build's per-build time.
   batched       512 independent replicas (N uniform in [256, 8192], density in [0.6, 0.9],
                 T in [0.8, 1.5]) advanced together in 100-step graph blocks, mixed
                 precision, beside a sample of the same replicas run one by one on the plain
@@ -139,7 +142,8 @@ def kernel_breakdown(durations, units):
     return out
 
 
-def run_gpu(spec, precision, steps, warmup, timing_steps, thermo_period=0, nvt=None):
+def run_gpu(spec, precision, steps, warmup, timing_steps, thermo_period=0, nvt=None,
+            nlist="cell"):
     """Time `steps` steps of one system; then a separate pass with events around every kernel
     launch. thermo_period > 0 reduces U, K and W every that many steps inside the timed loop."""
     import torch
@@ -147,6 +151,8 @@ def run_gpu(spec, precision, steps, warmup, timing_steps, thermo_period=0, nvt=N
     from paper_1308_5587_amd import ljmd
 
     g = ljmd.System.from_spec(spec, precision=precision)
+    if nlist != "cell":
+        g.set_nlist(nlist)
     if nvt:
         g.set_nvt(*nvt)
     g.step(0)  # list, tuning and forces ready
@@ -415,6 +421,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-configs", action="store_true", help="skip the N=4000, KA and paper legs")
+    ap.add_argument("--size-disperse-steps", type=int, default=200)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-blocks", type=int, default=10)
     ap.add_argument("--batched-sample", type=int, default=32)
@@ -476,6 +483,22 @@ def main():
             "steps_per_rebuild": c6["steps_per_rebuild"], "kernels": c6["kernels"],
             "paper_context": PAPER_CONTEXT}
         log(f"[bench] paper benchmark N=64000 NVT fp64: {c6['value']:.4g} atom-steps/s")
+        cm = inputs.make_colloid_mixture(n_large_side=24, sigma_l=3.0)
+        sd = {}
+        for method in ("tree", "cell"):
+            r = run_gpu(cm, "fp64", args.size_disperse_steps, 20, 100, nlist=method)
+            sd[method] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                          "steps_per_rebuild": r["steps_per_rebuild"],
+                          "mean_list_length": r["mean_list_length"],
+                          "build_ms": r["kernels"]["per_build"]["nlist"],
+                          "step_kernel_ms": r["kernels"]["step_kernel_avg"],
+                          "threads_per_particle": r["threads_per_particle"]}
+            log(f"[bench] size-disperse N={cm.n} {method}: {r['value']:.4g} atom-steps/s, "
+                f"build {sd[method]['build_ms']} ms")
+        configs["size_disperse_N%d" % cm.n] = {
+            "n": cm.n, "n_large": int((cm.type == 1).sum()), "size_ratio": 3.0,
+            "steps": args.size_disperse_steps, "dtype": "f64", **sd,
+            "tree_speedup_vs_cell": sd["tree"]["value"] / sd["cell"]["value"]}
     drift = None
     if not args.no_drift:
         log("[bench] energy drift: N=2^20 over 5 tau, N=4000 over 100 tau")

@@ -209,11 +209,13 @@ def make_colloid_mixture(
     h = (np.arange(m) + 0.5) * (L / m)
     small = np.stack(np.meshgrid(h, h, h, indexing="ij"), -1).reshape(-1, 3)
     excl = 0.5 * (1.0 + sigma_l)
-    keep = np.ones(len(small), dtype=bool)
-    for c in large:
-        d = small - c
-        d -= L * np.rint(d / L)
-        keep &= (d * d).sum(1) >= excl * excl
+    # the only large centre that can be closer than excl (< spacing_l / 2) is the nearest one
+    # of the large lattice: the centre of the lattice cell holding the small site
+    if excl >= 0.5 * spacing_l:
+        raise ValueError("the large particles' spacing must exceed 1 + sigma_l")
+    c = (np.floor(small / spacing_l) + 0.5) * spacing_l
+    d = small - c
+    keep = (d * d).sum(1) >= excl * excl
     pos = np.concatenate([small[keep], large])
     pos += rng.uniform(-jitter, jitter, size=pos.shape)
     pos %= L
