@@ -122,26 +122,28 @@ __device__ __forceinline__ double coherent_load(const double *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The box of a child: a leaf's build position, or an internal node's stored box (read past
-// the non-coherent caches while boxes are still being formed, COHERENT).
-template <bool COHERENT>
-__device__ __forceinline__ void child_box(const BvhArgs &b, int c, double lo[3], double hi[3]) {
+// Each internal node stores the boxes of its two children (12 doubles: lo xyz, hi xyz of the
+// left child, then of the right one), so a walk reads one record per node it opens and tests
+// both children from it; a leaf child's box is its build position (lo = hi, exactly).
+// The box of child c: a leaf's build position, or the union of the two child boxes an internal
+// node stores (read past the non-coherent caches while boxes are still being formed).
+__device__ __forceinline__ void child_box_bu(const BvhArgs &b, int c, double lo[3], double hi[3]) {
     if (c & BVH_LEAF) {
         const double4 x = b.xb[c & ~BVH_LEAF];
         lo[0] = hi[0] = x.x;
         lo[1] = hi[1] = x.y;
         lo[2] = hi[2] = x.z;
     } else {
-        const double *bx = b.box + 6 * (size_t)c;
+        const double *bx = b.box + 12 * (size_t)c;
         for (int a = 0; a < 3; ++a) {
-            lo[a] = COHERENT ? coherent_load(bx + a) : bx[a];
-            hi[a] = COHERENT ? coherent_load(bx + 3 + a) : bx[3 + a];
+            lo[a] = fmin(coherent_load(bx + a), coherent_load(bx + 6 + a));
+            hi[a] = fmax(coherent_load(bx + 3 + a), coherent_load(bx + 9 + a));
         }
     }
 }
 
-// Boxes bottom-up: from each leaf, the second of a node's two children to arrive forms the
-// node's box from both children and climbs on; the first stops.
+// Boxes bottom-up: from each leaf, the second of a node's two children to arrive stores both
+// children's boxes in the node and climbs on; the first stops.
 __global__ void __launch_bounds__(256) k_bvh_boxes(const BvhArgs b) {
     if (!bvh_go(b)) return;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -151,13 +153,17 @@ __global__ void __launch_bounds__(256) k_bvh_boxes(const BvhArgs b) {
         __threadfence();
         if (atomicAdd(&b.flag[node], 1) == 0) return;
         __threadfence();
-        double l0[3], h0[3], l1[3], h1[3];
-        child_box<true>(b, b.left[node], l0, h0);
-        child_box<true>(b, b.right[node], l1, h1);
-        double *bx = b.box + 6 * (size_t)node;
+        double lo[3], hi[3];
+        double *bx = b.box + 12 * (size_t)node;
+        child_box_bu(b, b.left[node], lo, hi);
         for (int a = 0; a < 3; ++a) {
-            bx[a] = fmin(l0[a], l1[a]);
-            bx[3 + a] = fmax(h0[a], h1[a]);
+            bx[a] = lo[a];
+            bx[3 + a] = hi[a];
+        }
+        child_box_bu(b, b.right[node], lo, hi);
+        for (int a = 0; a < 3; ++a) {
+            bx[6 + a] = lo[a];
+            bx[9 + a] = hi[a];
         }
         node = b.parent_node[node];
     }
@@ -188,6 +194,24 @@ __device__ __forceinline__ int mi_side(double d, double L, double &out) {
     }
     out = d;
     return 0;
+}
+
+// A leaf j at (xjx, xjy, xjz) seen from particle p at xi in the image (sx, sy, sz): listed when
+// the minimum image of the pair is that image and the canonical squared distance is below rl2.
+__device__ __forceinline__ void try_leaf(const double4 &xi, double xjx, double xjy, double xjz,
+                                         int j, int sx, int sy, int sz, double rl2,
+                                         const RepParams &P, const BvhArgs &b, int p, int &count) {
+    double dx, dy, dz;
+    const int kx = mi_side(xjx - xi.x, P.L[0], dx);
+    const int ky = mi_side(xjy - xi.y, P.L[1], dy);
+    const int kz = mi_side(xjz - xi.z, P.L[2], dz);
+    if (kx != sx || ky != sy || kz != sz) return;
+    const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
+    const double r2 = (xx + yy) + zz;
+    if (r2 < rl2) {
+        if (count < b.cap) b.nlist32[slot32(p, count, b.npad, b.lshift)] = j;
+        ++count;
+    }
 }
 
 // One thread per particle: every type's tree, in every periodic image the particle's list
@@ -222,33 +246,36 @@ __global__ void __launch_bounds__(256) k_bvh_list(const BvhArgs b) {
                     for (int sz = lo_img[2]; sz <= hi_img[2]; ++sz) {
                         const double q[3] = {xq[0] + sx * P.L[0], xq[1] + sy * P.L[1],
                                              xq[2] + sz * P.L[2]};
+                        if (root & BVH_LEAF) {  // a one-particle tree
+                            const int j = root & ~BVH_LEAF;
+                            if (j != p) {
+                                const double4 xj = b.xb[j];
+                                try_leaf(xi, xj.x, xj.y, xj.z, j, sx, sy, sz, rl2, P, b, p, count);
+                            }
+                            continue;
+                        }
                         int top = 0;
                         stack[top++] = root;
                         while (top > 0) {
                             const int c = stack[--top];
-                            if (c & BVH_LEAF) {
-                                const int j = c & ~BVH_LEAF;
-                                if (j == p) continue;
-                                const double4 xj = b.xb[j];
-                                double dx, dy, dz;
-                                const int kx = mi_side(xj.x - xi.x, P.L[0], dx);
-                                const int ky = mi_side(xj.y - xi.y, P.L[1], dy);
-                                const int kz = mi_side(xj.z - xi.z, P.L[2], dz);
-                                if (kx != sx || ky != sy || kz != sz) continue;
-                                const double xx = dx * dx, yy = dy * dy, zz = dz * dz;
-                                const double r2 = (xx + yy) + zz;
-                                if (r2 < rl2) {
-                                    if (count < b.cap)
-                                        b.nlist32[slot32(p, count, b.npad, b.lshift)] = j;
-                                    ++count;
-                                }
-                                continue;
-                            }
-                            // children: the right one is pushed first so the left is walked first
-                            const int ch[2] = {b.right[c], b.left[c]};
+                            const int ch[2] = {b.left[c], b.right[c]};
+                            const double *bx = b.box + 12 * (size_t)c;
+                            double cb[12];
+#pragma unroll
+                            for (int k = 0; k < 12; ++k) cb[k] = bx[k];
+                            // leaves are tested at once, in child order; internal children are
+                            // pushed right first, so the left subtree is walked first
                             for (int u = 0; u < 2; ++u) {
-                                double lo[3], hi[3];
-                                child_box<false>(b, ch[u], lo, hi);
+                                if (!(ch[u] & BVH_LEAF)) continue;
+                                const int j = ch[u] & ~BVH_LEAF;
+                                if (j == p) continue;
+                                try_leaf(xi, cb[6 * u], cb[6 * u + 1], cb[6 * u + 2], j, sx, sy,
+                                         sz, rl2, P, b, p, count);
+                            }
+                            for (int u = 1; u >= 0; --u) {
+                                if (ch[u] & BVH_LEAF) continue;
+                                const double lo[3] = {cb[6 * u], cb[6 * u + 1], cb[6 * u + 2]};
+                                const double hi[3] = {cb[6 * u + 3], cb[6 * u + 4], cb[6 * u + 5]};
                                 if (box_dist2(q, lo, hi) <= rl2_box && top < BVH_STACK)
                                     stack[top++] = ch[u];
                             }

@@ -242,7 +242,7 @@ struct BvhArgs {
     int *left, *right;       // internal node children (node of type t at s_t + local index)
     int *parent_leaf, *parent_node;
     int *flag;               // bottom-up arrival counters (cleared by the node kernel)
-    double *box;             // 6 doubles per internal node: lo x y z, hi x y z
+    double *box;             // 12 doubles per internal node: its children's boxes (lo, hi)
     const double *rl2_table; // list radii squared per type pair (0: pair disabled)
     int *nl_count;
     int32_t *nlist32;        // 32-bit sorted-order indices, 4 per 16-byte chunk (see slot32)

@@ -290,6 +290,31 @@ __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
 
 // ---------------------------------------------------------------- rebuild: Verlet list
 
+// The replica parameters the list build reads inside its loops, held in scalar registers for
+// the whole workgroup: a parameter load in the loops would wait (vmcnt) for every list store
+// still in flight.
+struct BuildParams {
+    double L[3];
+    double rl2;  // (r_cut + skin)^2 of pair (0,0)
+    int canonical, ntypes;
+};
+
+__device__ __forceinline__ double uniform_f64(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ BuildParams build_params(const RepParams &P) {
+    BuildParams u;
+    for (int k = 0; k < 3; ++k) u.L[k] = uniform_f64(P.L[k]);
+    u.rl2 = uniform_f64(P.single_rl2);
+    u.canonical = __builtin_amdgcn_readfirstlane(P.canonical);
+    u.ntypes = __builtin_amdgcn_readfirstlane(P.ntypes);
+    return u;
+}
+
 // Candidates of one stencil cell for the particles of a wavefront's groups: each group of
 // Ln lanes takes Ln atoms of the cell at a time and appends the hits of its particle in
 // lane order. MIK selects the minimum-image form, fixed per cell: 0 none (the halo cell is
@@ -298,7 +323,7 @@ __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
 template <bool MULTI, bool STAGED, int MIK, bool SOLO>
 __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                                                 const double4 *__restrict__ st,
-                                                const double *s_rl2, const RepParams &P, int o,
+                                                const double *s_rl2, const BuildParams &P, int o,
                                                 int m, int jst, double shx, double shy,
                                                 double shz, const double4 &xi, int ti, int q,
                                                 bool active, int Ln, int lane,
@@ -346,7 +371,7 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                 dz = dz + shz;
             }
             const double r2 = r2_canon(dx, dy, dz);
-            const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.single_rl2;
+            const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.rl2;
             hv[u] = valid && (jst + tt) != q && r2 < rl2;
             ttv[u] = tt;
         }
@@ -388,7 +413,7 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
 template <bool MULTI, bool STAGED, bool SOLO>
 __device__ __forceinline__ void nlist_scan_dispatch(const RebuildArgs &a,
                                                     const double4 *__restrict__ st,
-                                                    const double *s_rl2, const RepParams &P,
+                                                    const double *s_rl2, const BuildParams &P,
                                                     int o, int m, int jst, int code,
                                                     const double4 &xi, int ti, int q, bool active,
                                                     int Ln, int lane, unsigned long long gmask,
@@ -413,7 +438,7 @@ __device__ __forceinline__ void nlist_scan_dispatch(const RebuildArgs &a,
 template <bool MULTI, bool STAGED>
 __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem &t,
                                             const BrickInfo &bi, const double4 *__restrict__ st,
-                                            const double *s_rl2, const RepParams &P,
+                                            const double *s_rl2, const BuildParams &P,
                                             int first, uint16_t *s_cnt, int &my_max,
                                             unsigned long long &my_entries) {
     const int hy = (bi.dims >> 4) & 15, hz = (bi.dims >> 8) & 15;
@@ -431,6 +456,13 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
         const int beg = __builtin_amdgcn_readfirstlane(a.cell_start[rank]);
         const int cnt = __builtin_amdgcn_readfirstlane(a.cell_start[rank + 1]) - beg;
         if (cnt == 0) continue;
+        // the cell's first atom in the staged tile: the halo cell at the brick-relative
+        // offset (1, 1, 1), or in a small box the distinct halo cell holding the cell's range
+        int hc = ((lx + 1) * hy + (ly + 1)) * hz + (lz + 1);
+        if (STAGED && P.canonical)
+            for (int h = 0; h < t.nhalo; ++h)
+                if (t.start[h] == beg && t.off[h + 1] - t.off[h] == cnt) hc = h;
+        const int own = STAGED ? __builtin_amdgcn_readfirstlane(t.off[hc]) : 0;
         int Ln = 64 / cnt;
         Ln = Ln < 1 ? 1 : (Ln > 32 ? 32 : Ln);
         const int G = 64 / Ln;
@@ -442,7 +474,7 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
             const int p = p0 + group;
             const bool active = group < G && p < cnt;
             const int q = beg + (active ? p : 0);
-            const double4 xi = a.pos_scr[q];
+            const double4 xi = STAGED ? st[own + (active ? p : 0)] : a.pos_scr[q];
             const int ti = MULTI ? (int)xi.w : 0;
             int count = 0;
             for (int s = 0; s < nst; ++s) {
@@ -544,7 +576,8 @@ k_nlist(const RebuildArgs a) {
     const int b = a.nrep > 1 ? (int)blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
     const BrickInfo bi = a.bricks[b];
     if (!rebuilds(a, bi.rep)) return;
-    const RepParams &P = a.reps[bi.rep];
+    const RepParams &P = a.reps[__builtin_amdgcn_readfirstlane(bi.rep)];
+    const BuildParams U = build_params(P);
     extern __shared__ double4 dyn_tile[];
     __shared__ TileSmem t;
     double4 *st = dyn_tile;
@@ -591,9 +624,9 @@ k_nlist(const RebuildArgs a) {
     const int first = a.cell_start[bi.first_cell];
     const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
     if (staged)
-        nlist_cells<MULTI, true>(a, t, bi, st, s_rl2, P, first, s_cnt, my_max, my_entries);
+        nlist_cells<MULTI, true>(a, t, bi, st, s_rl2, U, first, s_cnt, my_max, my_entries);
     else
-        nlist_cells<MULTI, false>(a, t, bi, st, s_rl2, P, first, s_cnt, my_max, my_entries);
+        nlist_cells<MULTI, false>(a, t, bi, st, s_rl2, U, first, s_cnt, my_max, my_entries);
     work_order(a, first, natoms, s_cnt, s_bin);
 
     // wavefront reductions of the build statistics, one atomic each per wavefront

@@ -306,7 +306,7 @@ int setup_table(ljmd_system *s) {
     return LJMD_OK;
 }
 
-// The tree method's node, box and cell arrays (n each; boxes 6 doubles per node).
+// The tree method's node, box and cell arrays (n each; 12 box doubles per node).
 int ensure_tree_arrays(ljmd_system *s) {
     if (s->d_cell_of) return LJMD_OK;
     const size_t N = (size_t)s->n;
@@ -316,7 +316,7 @@ int ensure_tree_arrays(ljmd_system *s) {
     CHK(dalloc_t(s, &s->d_bvh_pleaf, N));
     CHK(dalloc_t(s, &s->d_bvh_pnode, N));
     CHK(dalloc_t(s, &s->d_bvh_flag, N));
-    CHK(dalloc_t(s, &s->d_bvh_box, 6 * N));
+    CHK(dalloc_t(s, &s->d_bvh_box, 12 * N));
     return LJMD_OK;
 }
 
