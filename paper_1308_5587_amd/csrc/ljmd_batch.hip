@@ -51,8 +51,8 @@ constexpr int PAIR_ROWS = LJMD_MAX_TYPES * LJMD_MAX_TYPES;  // pair rows reserve
 // work order (2),
 // energy, virial and kinetic per particle (8 + 48 + 8), the block snapshot (2 x 32 + 16).
 constexpr int64_t PER_PARTICLE = 7 * 32 + 2 * 16 + 5 * 4 + 2 + 64 + 2 * 32 + 16;
-// per cell entry: rank, xyz, count, start, replica tag
-constexpr int64_t PER_CELL = 5 * 4;
+// per cell entry: rank, xyz, count, start, lower-half count, replica tag
+constexpr int64_t PER_CELL = 6 * 4;
 // per brick: BrickInfo, halo cells, tile table
 constexpr int64_t PER_BRICK = (int64_t)sizeof(BrickInfo) + HALO_MAX * (int64_t)sizeof(HaloCell) +
                               TILE_TAB * 4;
@@ -152,7 +152,7 @@ struct ljmd_batch {
         *d_rep_status = nullptr;
     int *d_prep = nullptr, *d_crep = nullptr;
     int *d_cell_rank = nullptr, *d_cell_xyz = nullptr, *d_cell_count = nullptr,
-        *d_cell_start = nullptr;
+        *d_cell_start = nullptr, *d_cell_lo = nullptr;
     BrickInfo *d_bricks = nullptr;
     HaloCell *d_halo = nullptr;
     int *d_tile_tab = nullptr;
@@ -346,6 +346,7 @@ RebuildArgs rebuild_args(ljmd_batch *b, const int *go, int go_stride, int cur) {
     a.perm = b->d_perm;
     a.cell_count = b->d_cell_count;
     a.cell_start = b->d_cell_start;
+    a.cell_lo = b->d_cell_lo;
     a.cell_rank = b->d_cell_rank;
     a.cell_xyz = b->d_cell_xyz;
     a.nl_count = b->d_count;
@@ -712,6 +713,7 @@ int ljmd_batch_create(const ljmd_batch_config *cfg, ljmd_batch **out) {
     get(&b->d_cell_xyz, C);
     get(&b->d_cell_count, C);
     get(&b->d_cell_start, C);
+    get(&b->d_cell_lo, C);
     get(&b->d_bricks, B);
     get(&b->d_halo, B * HALO_MAX);
     get(&b->d_tile_tab, B * TILE_TAB);

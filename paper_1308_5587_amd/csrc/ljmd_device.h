@@ -97,9 +97,11 @@ struct TileSmem {
     int total;
 };
 
-// Wavefront 0 reads the halo cells (lane h, h < nhalo) and scans their atom counts.
+// Wavefront 0 reads the halo cells (lane h, h < nhalo) and scans their atom counts; with
+// lo_out, also each halo cell's count of lower-z-half members (cell_lo).
 __device__ __forceinline__ void tile_setup(const BrickInfo &bi, const HaloCell *halo_b,
-                                           const int *cell_start, TileSmem &t) {
+                                           const int *cell_start, TileSmem &t,
+                                           int *lo_out = nullptr, const int *cell_lo = nullptr) {
     if (threadIdx.x < 64) {
         const int h = threadIdx.x;
         int cnt = 0;
@@ -109,6 +111,7 @@ __device__ __forceinline__ void tile_setup(const BrickInfo &bi, const HaloCell *
             cnt = cell_start[hc.rank + 1] - st;
             t.start[h] = st;
             t.shift[h] = hc.shift;
+            if (lo_out) lo_out[h] = cell_lo[hc.rank];
         }
         int v = cnt;
 #pragma unroll

@@ -143,6 +143,13 @@ __device__ __forceinline__ bool rebuilds(const RebuildArgs &a, int rep) {
     return rep >= 0 && a.reps[rep].active && a.go[rep * a.go_stride] != 0;
 }
 
+// 1 when a particle at z lies in the upper half of its cell cz: the scaled coordinate
+// z / w, the value k_bin bins by, is at least cz + 1/2 (exact: the difference of two
+// nearby doubles).
+__device__ __forceinline__ int upper_half(double z, double inv_w, int cz) {
+    return (z * inv_w - (double)cz) >= 0.5 ? 1 : 0;
+}
+
 // Cell of each particle; the slot inside its cell comes from an integer atomic counter
 // (the order is made deterministic afterwards by k_cell_gather). Particles are still in the
 // previous build's cell order, so equal cells come in runs along a wavefront: each run
@@ -150,7 +157,7 @@ __device__ __forceinline__ bool rebuilds(const RebuildArgs &a, int rep) {
 __global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     const int wl = threadIdx.x & 63;
-    int r = -1;
+    int r = -1, up = 0;
     if (q < a.n) {
         const int rep = a.prep ? a.prep[q] : 0;
         if (rebuilds(a, rep)) {
@@ -161,6 +168,7 @@ __global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
             const int cz = cell_coord(x.z * P.inv_w[2], P.nc[2]);
             const int tcell = a.typed_cells ? (int)x.w * a.typed_cells : 0;
             r = a.cell_rank[P.coff + tcell + (cx * P.nc[1] + cy) * P.nc[2] + cz];
+            if (a.cell_lo) up = upper_half(x.z, P.inv_w[2], cz);
         }
     }
     const int prev = __shfl_up(r, 1);
@@ -175,7 +183,7 @@ __global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
     base = __shfl(base, leader);
     if (r >= 0) {
         a.key[q] = r;
-        a.slot[q] = base + (wl - leader);
+        a.slot[q] = (base + (wl - leader)) | (up << 30);  // the z half rides in bit 30
     }
 }
 
@@ -239,12 +247,18 @@ __global__ void __launch_bounds__(256) k_scatter(const RebuildArgs a) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.n) return;
     if (!rebuilds(a, a.prep ? a.prep[q] : 0)) return;
-    a.perm[a.cell_start[a.key[q]] + a.slot[q]] = q;
+    // perm holds 2 q + (upper z half): particle slots are below 2^26
+    const int sl = a.slot[q];
+    a.perm[a.cell_start[a.key[q]] + (sl & 0x3FFFFFFF)] = (q << 1) | (sl >> 30);
 }
 
-// Order each cell's members by their previous sorted index (a stable counting sort) and
-// gather their state into the new order. One workgroup of 64 lanes per cell (grid-stride);
-// the rank of a member is the number of members with a smaller index.
+// Order each cell's members and gather their state into the new order. One workgroup of 64
+// lanes per cell (grid-stride). The cell method orders members by (z half, previous sorted
+// index): k_bin marks the particles whose scaled z coordinate lies in the upper half of their
+// cell, k_scatter carries the mark into perm (2 q + mark), lower-half members come first and
+// cell_lo records how many; the list build uses the split to skip, for a particle in one
+// half, the far half of the cells above or below it. The tree method's sort grid orders by
+// previous index only. The rank of a member is the number of members with a smaller key.
 __device__ __forceinline__ void gather_member(const RebuildArgs &a, int dst, int k, int c) {
     a.pos_scr[dst] = a.pos[k];
     a.vel_scr[dst] = a.vel[k];
@@ -253,37 +267,52 @@ __device__ __forceinline__ void gather_member(const RebuildArgs &a, int dst, int
 }
 
 __global__ void __launch_bounds__(64) k_cell_gather(const RebuildArgs a) {
-    __shared__ int s_in[SORT_LDS];
+    __shared__ int s_key[SORT_LDS];
+    __shared__ int s_lo;
     for (int c = blockIdx.x; c < a.ncell; c += gridDim.x) {
         if (!rebuilds(a, a.crep ? a.crep[c] : 0)) continue;  // uniform per workgroup
         const int beg = a.cell_start[c];
         const int m = a.cell_start[c + 1] - beg;
-        __syncthreads();  // s_in of the previous cell is no longer read
+        __syncthreads();  // s_key of the previous cell is no longer read
         if (m <= SORT_LDS) {
-            for (int t = threadIdx.x; t < m; t += blockDim.x) s_in[t] = a.perm[beg + t];
+            if (threadIdx.x == 0) s_lo = 0;
+            __syncthreads();
+            // the key (half, index) as one int: half in bit 30, the index below 2^26
+            for (int t = threadIdx.x; t < m; t += blockDim.x) {
+                const int pv = a.perm[beg + t];
+                s_key[t] = ((pv & 1) << 30) | (pv >> 1);
+                if (!(pv & 1)) atomicAdd(&s_lo, 1);
+            }
             __syncthreads();
             for (int t = threadIdx.x; t < m; t += blockDim.x) {
-                const int v = s_in[t];
+                const int kt = s_key[t];
                 int rank = 0;
-                for (int u = 0; u < m; ++u) rank += s_in[u] < v;
-                gather_member(a, beg + rank, v, c);
+                for (int u = 0; u < m; ++u) rank += s_key[u] < kt;
+                gather_member(a, beg + rank, kt & 0x3FFFFFFF, c);
             }
+            if (a.cell_lo && threadIdx.x == 0) a.cell_lo[c] = s_lo;
         } else {
             if (threadIdx.x == 0) {
-                // pathological occupancy: insertion sort in place by one lane
+                // pathological occupancy: insertion sort in place by one lane, on the key
+                // (half, index), which orders as the encoded value with the half bit on top
+                auto key = [](int pv) { return ((pv & 1) << 30) | (pv >> 1); };
+                int lo = 0;
+                for (int t = 0; t < m; ++t) lo += !(a.perm[beg + t] & 1);
                 for (int t = 1; t < m; ++t) {
                     const int v = a.perm[beg + t];
+                    const int kv = key(v);
                     int u = t - 1;
-                    while (u >= 0 && a.perm[beg + u] > v) {
+                    while (u >= 0 && key(a.perm[beg + u]) > kv) {
                         a.perm[beg + u + 1] = a.perm[beg + u];
                         --u;
                     }
                     a.perm[beg + u + 1] = v;
                 }
+                if (a.cell_lo) a.cell_lo[c] = lo;
             }
             __syncthreads();
             for (int t = threadIdx.x; t < m; t += blockDim.x)
-                gather_member(a, beg + t, a.perm[beg + t], c);
+                gather_member(a, beg + t, a.perm[beg + t] >> 1, c);
         }
     }
 }
@@ -297,6 +326,7 @@ struct BuildParams {
     double L[3];
     double rl2;  // (r_cut + skin)^2 of pair (0,0)
     int canonical, ntypes;
+    int narrow;  // npad < 2^24 and every list slot below 2^31 (byte offsets fit 32 bits)
 };
 
 __device__ __forceinline__ double uniform_f64(double x) {
@@ -315,25 +345,49 @@ __device__ __forceinline__ BuildParams build_params(const RepParams &P) {
     return u;
 }
 
-// Candidates of one stencil cell for the particles of a wavefront's groups: each group of
-// Ln lanes takes Ln atoms of the cell at a time and appends the hits of its particle in
-// lane order. MIK selects the minimum-image form, fixed per cell: 0 none (the halo cell is
-// in the primary image), 1 a constant shift of the halo cell's periodic image, 2 the branch
-// form (fewer than 3 cells on some axis).
+// The z shifts of a stencil column whose three cells lie in different periodic images along
+// z: the second and third cells start at tile indices b1 and b2.
+struct ColumnShift {
+    int b1, b2;
+    double shz1, shz2;
+};
+
+// Candidates of one range of tile atoms (a stencil cell, or a column of them) for the
+// particles of a wavefront's groups: each group of Ln lanes takes Ln atoms of the range at a
+// time and appends the hits of its particle in lane order, so entries follow the tile order.
+// MIK selects the minimum-image form, fixed per range: 0 none (the halo cells are in the
+// primary image), 1 a constant shift of their periodic image, 2 the branch form (fewer than
+// 3 cells on some axis).
 template <bool MULTI, bool STAGED, int MIK, bool SOLO>
 __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                                                 const double4 *__restrict__ st,
                                                 const double *s_rl2, const BuildParams &P, int o,
                                                 int m, int jst, double shx, double shy,
-                                                double shz, const double4 &xi, int ti, int q,
+                                                double shz, const ColumnShift &cz,
+                                                const double4 &xi, int ti, int q, int self,
                                                 bool active, int Ln, int lane,
                                                 unsigned long long gmask, int &count) {
     // list slots (nl_slot in closed form with the particle's part precomputed)
     const int sh = 3 + a.lshift;
     // the round stride npad << sh fits 32 bits (the host keeps npad x 8 x lanes < 2^32), so
-    // the slot is one 32 x 32 + 64-bit multiply-add
+    // the slot is one 32 x 32 + 64-bit multiply-add; for a list of less than 4 GiB with
+    // npad < 2^24 (P.narrow) it is a 24-bit multiply and 32-bit byte offsets from the list base
     const uint32_t rstride = (uint32_t)a.npad << sh;
     const uint64_t qbase = (uint64_t)q << sh;
+    const uint32_t qb32 = (uint32_t)q << sh;
+    const uint32_t lmask = (1u << sh) - 1u;
+    char *const nl_bytes = reinterpret_cast<char *>(a.nlist);
+    auto store = [&](int k, int v) {
+        if (P.narrow) {
+            const uint32_t e = __umul24((uint32_t)k >> sh, (uint32_t)a.npad);
+            const uint32_t slot = (e << sh) + qb32 + ((uint32_t)k & lmask);
+            *reinterpret_cast<uint16_t *>(nl_bytes + (slot << 1)) = (uint16_t)v;
+        } else {
+            const uint64_t slot = (uint64_t)((uint32_t)k >> sh) * rstride + qbase +
+                                  (size_t)((uint32_t)k & lmask);
+            a.nlist[slot] = (uint16_t)v;
+        }
+    };
     // BUILD_BATCH rounds of Ln candidates per iteration: their positions are read and their
     // distances tested before any append, so the LDS reads and FP64 chains of the rounds
     // overlap; the appends then run round by round, in the order of a plain loop
@@ -369,10 +423,19 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                 dx = dx + shx;  // adding 0.0 on an unshifted axis is exact
                 dy = dy + shy;
                 dz = dz + shz;
+            } else if (MIK == 3) {
+                // a column whose cells lie in different z images: the z shift of the
+                // candidate's own cell (tile index below b1: the first cell, below b2: the
+                // second, else the third)
+                const int k = o + tv;
+                dx = dx + shx;
+                dy = dy + shy;
+                dz = dz + (k < cz.b1 ? shz : (k < cz.b2 ? cz.shz1 : cz.shz2));
             }
             const double r2 = r2_canon(dx, dy, dz);
             const double rl2 = MULTI ? s_rl2[ti * P.ntypes + tj] : P.rl2;
-            hv[u] = valid && (jst + tt) != q && r2 < rl2;
+            // the particle itself: its tile index (staged) or its sorted index
+            hv[u] = valid && (STAGED ? o + tt : jst + tt) != self && r2 < rl2;
             ttv[u] = tt;
         }
 #pragma unroll
@@ -381,11 +444,7 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
             if (SOLO) {
                 // one lane per particle: its hits are appended in order, no group prefix
                 if (hit) {
-                    if (count < a.cap) {
-                        const uint64_t slot = (uint64_t)((uint32_t)count >> sh) * rstride +
-                                              qbase + (size_t)(count & ((1 << sh) - 1));
-                        a.nlist[slot] = (uint16_t)(o + ttv[u]);
-                    }
+                    if (count < a.cap) store(count, o + ttv[u]);
                     ++count;
                 }
                 continue;
@@ -397,72 +456,109 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                 const int k = count + (int)__builtin_amdgcn_mbcnt_hi(
                                           (unsigned)(bal >> 32),
                                           __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-                if (k < a.cap) {
-                    const uint64_t slot = (uint64_t)((uint32_t)k >> sh) * rstride + qbase +
-                                          (size_t)(k & ((1 << sh) - 1));
-                    a.nlist[slot] = (uint16_t)(o + ttv[u]);
-                }
+                if (k < a.cap) store(k, o + ttv[u]);
             }
             count += __popcll(bal);
         }
     }
 }
 
-// The minimum-image form of a stencil cell: branch form for small boxes, else the halo cell's
-// shift code (21: no shift on any axis).
+// The minimum-image form of a range: branch form for small boxes, else the halo cells' shift
+// code (21: no shift on any axis), or for a column across the box's z boundary the shift
+// code of its first cell and the z shifts of the others (cz.b1 >= 0).
 template <bool MULTI, bool STAGED, bool SOLO>
 __device__ __forceinline__ void nlist_scan_dispatch(const RebuildArgs &a,
                                                     const double4 *__restrict__ st,
                                                     const double *s_rl2, const BuildParams &P,
                                                     int o, int m, int jst, int code,
-                                                    const double4 &xi, int ti, int q, bool active,
-                                                    int Ln, int lane, unsigned long long gmask,
+                                                    const ColumnShift &cz, const double4 &xi,
+                                                    int ti, int q, int self, bool active, int Ln,
+                                                    int lane, unsigned long long gmask,
                                                     int &count) {
     if (P.canonical) {
-        nlist_scan_cell<MULTI, STAGED, 2, SOLO>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0, xi, ti,
-                                                q, active, Ln, lane, gmask, count);
-    } else if (code != 21) {
-        const double shx = (double)((code & 3) - 1) * P.L[0];
-        const double shy = (double)(((code >> 2) & 3) - 1) * P.L[1];
-        const double shz = (double)(((code >> 4) & 3) - 1) * P.L[2];
-        nlist_scan_cell<MULTI, STAGED, 1, SOLO>(a, st, s_rl2, P, o, m, jst, shx, shy, shz, xi, ti,
-                                                q, active, Ln, lane, gmask, count);
-    } else {
-        nlist_scan_cell<MULTI, STAGED, 0, SOLO>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0, xi, ti,
-                                                q, active, Ln, lane, gmask, count);
+        nlist_scan_cell<MULTI, STAGED, 2, SOLO>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0, cz, xi,
+                                                ti, q, self, active, Ln, lane, gmask, count);
+        return;
     }
+    const double shx = (double)((code & 3) - 1) * P.L[0];
+    const double shy = (double)(((code >> 2) & 3) - 1) * P.L[1];
+    const double shz = (double)(((code >> 4) & 3) - 1) * P.L[2];
+    if (cz.b1 >= 0)
+        nlist_scan_cell<MULTI, STAGED, 3, SOLO>(a, st, s_rl2, P, o, m, jst, shx, shy, shz, cz, xi,
+                                                ti, q, self, active, Ln, lane, gmask, count);
+    else if (code != 21)
+        nlist_scan_cell<MULTI, STAGED, 1, SOLO>(a, st, s_rl2, P, o, m, jst, shx, shy, shz, cz, xi,
+                                                ti, q, self, active, Ln, lane, gmask, count);
+    else
+        nlist_scan_cell<MULTI, STAGED, 0, SOLO>(a, st, s_rl2, P, o, m, jst, 0.0, 0.0, 0.0, cz, xi,
+                                                ti, q, self, active, Ln, lane, gmask, count);
 }
 
-// The cells of one brick, one wavefront per cell; STAGED selects candidate positions from
-// the LDS tile or, for a tile larger than the LDS allocation, from global memory.
+template <bool MULTI, bool STAGED>
+__device__ __forceinline__ void nlist_scan(const RebuildArgs &a, const double4 *__restrict__ st,
+                                           const double *s_rl2, const BuildParams &P, int o,
+                                           int m, int jst, int code, const ColumnShift &cz,
+                                           const double4 &xi, int ti, int q, int self,
+                                           bool active, int Ln, int lane,
+                                           unsigned long long gmask, int &count) {
+    if (Ln == 1)
+        nlist_scan_dispatch<MULTI, STAGED, true>(a, st, s_rl2, P, o, m, jst, code, cz, xi, ti, q,
+                                                 self, active, Ln, lane, gmask, count);
+    else
+        nlist_scan_dispatch<MULTI, STAGED, false>(a, st, s_rl2, P, o, m, jst, code, cz, xi, ti,
+                                                  q, self, active, Ln, lane, gmask, count);
+}
+
+// The cells of one brick, one wavefront per work item; STAGED selects candidate positions
+// from the LDS tile or, for a tile larger than the LDS allocation, from global memory. With
+// the z-half split (s_lo: each halo cell's lower-half count) a work item is one half of a
+// cell: its particles need, of the stencil cells below them, only the upper half when they
+// are in the upper half, and of the cells above them only the lower half when they are in
+// the lower half (the far half lies beyond a cell width, at least the list radius, on z).
+// Without it (boxes with fewer than three cells on an axis) an item is a whole cell.
 template <bool MULTI, bool STAGED>
 __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem &t,
-                                            const BrickInfo &bi, const double4 *__restrict__ st,
+                                            const int *s_lo, const BrickInfo &bi,
+                                            const double4 *__restrict__ st,
                                             const double *s_rl2, const BuildParams &P,
                                             int first, uint16_t *s_cnt, int &my_max,
                                             unsigned long long &my_entries) {
     const int hy = (bi.dims >> 4) & 15, hz = (bi.dims >> 8) & 15;
     const int fpk = a.cell_xyz[bi.first_cell];
     const int wl = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    // the wavefront index is uniform: so are the item, its cell and every range bound below
+    // (scalar loop control)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwave = blockDim.x >> 6;
     const int nst = P.canonical ? t.nhalo : 27;
-    for (int ci = wave; ci < bi.ncell; ci += nwave) {
+    // split cells in halves only where whole cells would leave wavefronts idle (bricks of
+    // fewer cells than wavefronts): each range then costs a fixed setup as well, and halves
+    // double the ranges of an item's particles
+    const bool split = s_lo != nullptr && !P.canonical && bi.ncell < nwave;
+    const int nitem = split ? 2 * bi.ncell : bi.ncell;
+    for (int it = wave; it < nitem; it += nwave) {
+        const int ci = split ? it >> 1 : it;
+        const int half = split ? (it & 1) : -1;
         const int rank = bi.first_cell + ci;
         const int pk = a.cell_xyz[rank];
         const int lx = (pk & 1023) - (fpk & 1023);
         const int ly = ((pk >> 10) & 1023) - ((fpk >> 10) & 1023);
         const int lz = ((pk >> 20) & 1023) - ((fpk >> 20) & 1023);
-        const int beg = __builtin_amdgcn_readfirstlane(a.cell_start[rank]);
-        const int cnt = __builtin_amdgcn_readfirstlane(a.cell_start[rank + 1]) - beg;
-        if (cnt == 0) continue;
-        // the cell's first atom in the staged tile: the halo cell at the brick-relative
-        // offset (1, 1, 1), or in a small box the distinct halo cell holding the cell's range
+        const int cbeg = __builtin_amdgcn_readfirstlane(a.cell_start[rank]);
+        const int ccnt = __builtin_amdgcn_readfirstlane(a.cell_start[rank + 1]) - cbeg;
+        // the cell as a halo cell: at the brick-relative offset (1, 1, 1) of its stencil, or
+        // in a small box the distinct halo cell holding the cell's range
         int hc = ((lx + 1) * hy + (ly + 1)) * hz + (lz + 1);
-        if (STAGED && P.canonical)
+        if (P.canonical)
             for (int h = 0; h < t.nhalo; ++h)
-                if (t.start[h] == beg && t.off[h + 1] - t.off[h] == cnt) hc = h;
-        const int own = STAGED ? __builtin_amdgcn_readfirstlane(t.off[hc]) : 0;
+                if (t.start[h] == cbeg && t.off[h + 1] - t.off[h] == ccnt) hc = h;
+        const int clo = split ? __builtin_amdgcn_readfirstlane(s_lo[hc]) : 0;
+        // the item's particles: the cell's lower-half members, its upper-half ones, or all
+        const int pb = half == 1 ? clo : 0;
+        const int cnt = half == 0 ? clo : ccnt - pb;
+        if (cnt == 0) continue;
+        const int beg = cbeg + pb;
+        const int own = STAGED ? __builtin_amdgcn_readfirstlane(t.off[hc]) + pb : 0;
         int Ln = 64 / cnt;
         Ln = Ln < 1 ? 1 : (Ln > 32 ? 32 : Ln);
         const int G = 64 / Ln;
@@ -476,23 +572,59 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
             const int q = beg + (active ? p : 0);
             const double4 xi = STAGED ? st[own + (active ? p : 0)] : a.pos_scr[q];
             const int ti = MULTI ? (int)xi.w : 0;
+            const int self = STAGED ? own + (active ? p : 0) : q;
             int count = 0;
-            for (int s = 0; s < nst; ++s) {
-                const int h = P.canonical
-                                  ? s
-                                  : ((lx + s / 9) * hy + (ly + (s / 3) % 3)) * hz + (lz + s % 3);
-                // the stencil cell is the same for every lane of the wavefront: keep its
-                // bounds in scalar registers (uniform loop control, no per-lane masks)
-                const int o = __builtin_amdgcn_readfirstlane(t.off[h]);
-                const int m = __builtin_amdgcn_readfirstlane(t.off[h + 1]) - o;
-                const int jst = __builtin_amdgcn_readfirstlane(t.start[h]);
-                const int code = __builtin_amdgcn_readfirstlane(t.shift[h]);
-                if (Ln == 1)
-                    nlist_scan_dispatch<MULTI, STAGED, true>(a, st, s_rl2, P, o, m, jst, code, xi,
-                                                             ti, q, active, Ln, lane, gmask, count);
-                else
-                    nlist_scan_dispatch<MULTI, STAGED, false>(a, st, s_rl2, P, o, m, jst, code, xi,
-                                                              ti, q, active, Ln, lane, gmask, count);
+            if (STAGED && !P.canonical) {
+                // the stencil by columns (dx, dy): a column's three cells (z below, level,
+                // above) are consecutive in the tile, and so is the part of them the item
+                // needs, so a column is one range (same entry order as cell by cell); across
+                // the box's z boundary its cells differ in their z image only
+                for (int c = 0; c < 9; ++c) {
+                    const int h0 = ((lx + c / 3) * hy + (ly + c % 3)) * hz + lz;
+                    const int code = __builtin_amdgcn_readfirstlane(t.shift[h0]);
+                    const int code1 = __builtin_amdgcn_readfirstlane(t.shift[h0 + 1]);
+                    const int code2 = __builtin_amdgcn_readfirstlane(t.shift[h0 + 2]);
+                    ColumnShift cz{-1, -1, 0.0, 0.0};
+                    if (code != code1 || code != code2) {
+                        cz.b1 = __builtin_amdgcn_readfirstlane(t.off[h0 + 1]);
+                        cz.b2 = __builtin_amdgcn_readfirstlane(t.off[h0 + 2]);
+                        cz.shz1 = (double)(((code1 >> 4) & 3) - 1) * P.L[2];
+                        cz.shz2 = (double)(((code2 >> 4) & 3) - 1) * P.L[2];
+                    }
+                    int o = __builtin_amdgcn_readfirstlane(t.off[h0]);
+                    int e = __builtin_amdgcn_readfirstlane(t.off[h0 + 3]);
+                    if (half == 1) o += __builtin_amdgcn_readfirstlane(s_lo[h0]);
+                    if (half == 0)
+                        e = __builtin_amdgcn_readfirstlane(t.off[h0 + 2]) +
+                            __builtin_amdgcn_readfirstlane(s_lo[h0 + 2]);
+                    nlist_scan<MULTI, STAGED>(a, st, s_rl2, P, o, e - o, 0, code, cz, xi, ti, q,
+                                              self, active, Ln, lane, gmask, count);
+                }
+            } else {
+                for (int s = 0; s < nst; ++s) {
+                    const int h =
+                        P.canonical ? s
+                                    : ((lx + s / 9) * hy + (ly + (s / 3) % 3)) * hz + (lz + s % 3);
+                    // the stencil cell is the same for every lane of the wavefront: keep its
+                    // bounds in scalar registers (uniform loop control, no per-lane masks)
+                    int o = __builtin_amdgcn_readfirstlane(t.off[h]);
+                    int m = __builtin_amdgcn_readfirstlane(t.off[h + 1]) - o;
+                    int jst = __builtin_amdgcn_readfirstlane(t.start[h]);
+                    const int code = __builtin_amdgcn_readfirstlane(t.shift[h]);
+                    if (split && s % 3 != 1) {
+                        const int lo_h = __builtin_amdgcn_readfirstlane(s_lo[h]);
+                        if (half == 0 && s % 3 == 2) {
+                            m = lo_h;  // the cell above: its lower half
+                        } else if (half == 1 && s % 3 == 0) {
+                            o += lo_h;  // the cell below: its upper half
+                            jst += lo_h;
+                            m -= lo_h;
+                        }
+                    }
+                    const ColumnShift none{-1, -1, 0.0, 0.0};
+                    nlist_scan<MULTI, STAGED>(a, st, s_rl2, P, o, m, jst, code, none, xi, ti, q,
+                                              self, active, Ln, lane, gmask, count);
+                }
             }
             if (active && lane == 0) {
                 a.nl_count[q] = count;
@@ -577,7 +709,10 @@ k_nlist(const RebuildArgs a) {
     const BrickInfo bi = a.bricks[b];
     if (!rebuilds(a, bi.rep)) return;
     const RepParams &P = a.reps[__builtin_amdgcn_readfirstlane(bi.rep)];
-    const BuildParams U = build_params(P);
+    BuildParams U = build_params(P);
+    // every slot of an entry k < cap is below npad x (cap rounded up to a whole round)
+    U.narrow = a.npad < (1 << 24) &&
+               (uint64_t)a.npad * (uint64_t)(a.cap + (8 << a.lshift)) <= 0x7FFFFFFFull;
     extern __shared__ double4 dyn_tile[];
     __shared__ TileSmem t;
     double4 *st = dyn_tile;
@@ -586,7 +721,9 @@ k_nlist(const RebuildArgs a) {
         for (int k = threadIdx.x; k < P.ntypes * P.ntypes; k += blockDim.x)
             s_rl2[k] = a.rl2_table[P.pair_off + k];
     if (b == P.boff && threadIdx.x == 0) atomicAdd(&a.st->builds, 1ull);
-    tile_setup(bi, a.halo + (size_t)b * HALO_MAX, a.cell_start, t);
+    __shared__ int s_lo[HALO_MAX];
+    tile_setup(bi, a.halo + (size_t)b * HALO_MAX, a.cell_start, t, a.cell_lo ? s_lo : nullptr,
+               a.cell_lo);
     tile_save(t, a.tile_tab + (size_t)b * TILE_TAB);
     // the permuted state of the brick's particles becomes the main state and the new build
     // point (coalesced copy; tile staging below reads pos_scr, not pos)
@@ -624,9 +761,11 @@ k_nlist(const RebuildArgs a) {
     const int first = a.cell_start[bi.first_cell];
     const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
     if (staged)
-        nlist_cells<MULTI, true>(a, t, bi, st, s_rl2, U, first, s_cnt, my_max, my_entries);
+        nlist_cells<MULTI, true>(a, t, a.cell_lo ? s_lo : nullptr, bi, st, s_rl2, U, first, s_cnt,
+                                 my_max, my_entries);
     else
-        nlist_cells<MULTI, false>(a, t, bi, st, s_rl2, U, first, s_cnt, my_max, my_entries);
+        nlist_cells<MULTI, false>(a, t, a.cell_lo ? s_lo : nullptr, bi, st, s_rl2, U, first,
+                                  s_cnt, my_max, my_entries);
     work_order(a, first, natoms, s_cnt, s_bin);
 
     // wavefront reductions of the build statistics, one atomic each per wavefront

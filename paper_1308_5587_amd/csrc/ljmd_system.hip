@@ -70,7 +70,7 @@ struct ljmd_system {
     int *d_one = nullptr;  // constant 1: the go word of an unconditional rebuild
     int ncell = 0, ncell_alloc = 0;
     int *d_cell_rank = nullptr, *d_cell_xyz = nullptr, *d_cell_count = nullptr,
-        *d_cell_start = nullptr;
+        *d_cell_start = nullptr, *d_cell_lo = nullptr;
     BrickInfo *d_bricks = nullptr;
     HaloCell *d_halo = nullptr;
     int *d_tile_tab = nullptr;
@@ -231,12 +231,15 @@ int setup_table(ljmd_system *s) {
         dfree(s, s->d_cell_xyz);
         dfree(s, s->d_cell_count);
         dfree(s, s->d_cell_start);
-        s->d_cell_rank = s->d_cell_xyz = s->d_cell_count = s->d_cell_start = nullptr;
+        dfree(s, s->d_cell_lo);
+        s->d_cell_rank = s->d_cell_xyz = s->d_cell_count = s->d_cell_start = s->d_cell_lo =
+            nullptr;
         s->ncell_alloc = 0;
         CHK(dalloc_t(s, &s->d_cell_rank, ncell + 1));
         CHK(dalloc_t(s, &s->d_cell_xyz, ncell + 1));
         CHK(dalloc_t(s, &s->d_cell_count, ncell + 1));
         CHK(dalloc_t(s, &s->d_cell_start, ncell + 1));
+        CHK(dalloc_t(s, &s->d_cell_lo, ncell + 1));
         s->ncell_alloc = ncell + 1;
     }
     if (g.nbrick > 0 && g.nbrick > s->nbrick_alloc) {
@@ -399,6 +402,7 @@ RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
     const bool tree = s->nlist_method == LJMD_NLIST_TREE;
     a.typed_cells = tree ? s->ncs : 0;
     a.cell_of = tree ? s->d_cell_of : nullptr;
+    a.cell_lo = tree ? nullptr : s->d_cell_lo;
     return a;
 }
 
