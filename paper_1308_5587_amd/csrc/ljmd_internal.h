@@ -211,6 +211,7 @@ struct RebuildArgs {
     int *cell_start;         // ncell + 1 entries per replica
     int *cell_lo;            // per cell: members in the lower z half of the cell (cell method;
                              // null for the tree method's sort grid)
+    int split_halves;        // list build items may be half cells (bricks of few cells)
     const int *cell_rank;    // per replica: local linear cell index -> global cell index
     const int *cell_xyz;     // global cell -> packed local (cx | cy << 10 | cz << 20)
     int *nl_count;

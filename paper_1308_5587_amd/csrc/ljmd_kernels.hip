@@ -532,9 +532,11 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
     const int nwave = blockDim.x >> 6;
     const int nst = P.canonical ? t.nhalo : 27;
     // split cells in halves only where whole cells would leave wavefronts idle (bricks of
-    // fewer cells than wavefronts): each range then costs a fixed setup as well, and halves
-    // double the ranges of an item's particles
-    const bool split = s_lo != nullptr && !P.canonical && bi.ncell < nwave;
+    // fewer cells than wavefronts) and the caller allows it (split_halves): halves double the
+    // ranges of an item's particles, and each range costs a fixed setup. The list is the
+    // same either way: a split only skips atoms beyond the list radius, and entries keep the
+    // tile order within each column
+    const bool split = s_lo != nullptr && a.split_halves && !P.canonical && bi.ncell < nwave;
     const int nitem = split ? 2 * bi.ncell : bi.ncell;
     for (int it = wave; it < nitem; it += nwave) {
         const int ci = split ? it >> 1 : it;

@@ -403,6 +403,9 @@ RebuildArgs rebuild_args(ljmd_system *s, const int *go, int cur) {
     a.typed_cells = tree ? s->ncs : 0;
     a.cell_of = tree ? s->d_cell_of : nullptr;
     a.cell_lo = tree ? nullptr : s->d_cell_lo;
+    // half-cell work items for bricks of fewer cells than wavefronts (the batch keeps whole
+    // cells: there, over many small replicas at once, halves measured slower)
+    a.split_halves = 1;
     return a;
 }
 
@@ -1023,6 +1026,7 @@ int ljmd_system_create(const ljmd_config *cfg, int64_t n, const double *pos, con
                 hipSuccess &&
             v > 0)
             s->lds_limit = (size_t)v;
+
     }
     s->stream = (hipStream_t)cfg->stream;
     s->mem.alloc = cfg->alloc;
