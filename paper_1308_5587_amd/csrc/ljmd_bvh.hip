@@ -4,8 +4,10 @@
 //
 // After the sort of a rebuild (typed sort grid: the particles of each type are contiguous and
 // in Morton order of fine cells), every type gets a binary radix tree over its particles built
-// by the Karras construction on the unique sorted keys (cell << 32 | index); node boxes are
-// formed bottom-up (the second child to finish forms its parent's box); then each particle
+// by the Karras construction on the unique sorted keys (cell << 32 | index); every internal
+// node then stores the boxes of its two children, each the bounding box of the child's
+// contiguous leaf range, reduced from per-64 and per-4096-leaf box tables (no atomics and no
+// device-wide fences: each node's boxes are formed independently); then each particle
 // walks every type's tree with its list radius for that type pair and appends, as 32-bit sorted
 // indices, the particles j with r^2 < (r_cut + skin)^2 in the canonical FP64 arithmetic. The
 // walk order is fixed by the tree, so the list order is deterministic.
@@ -73,14 +75,8 @@ __global__ void __launch_bounds__(256) k_bvh_nodes(const BvhArgs b) {
     bvh_type_range(b, g, s, e);
     const int nt = e - s;
     const int i = g - s;
-    if (nt == 1) {
-        b.parent_leaf[s] = -1;
-        return;
-    }
-    if (i >= nt - 1) return;
+    if (i >= nt - 1) return;  // a one-particle type has no internal node
     const int node = s + i;
-    b.flag[node] = 0;
-    if (i == 0) b.parent_node[node] = -1;
     const int dr = bvh_delta(b, s, nt, i, i + 1), dl = bvh_delta(b, s, nt, i, i - 1);
     const int d = dr > dl ? 1 : -1;
     const int dmin = d > 0 ? dl : dr;
@@ -99,74 +95,120 @@ __global__ void __launch_bounds__(256) k_bvh_nodes(const BvhArgs b) {
     } while (t > 1);
     const int gamma = i + sp * d + (d < 0 ? -1 : 0);
     const int lo = i < j ? i : j, hi = i < j ? j : i;
-    int left, right;
-    if (lo == gamma) {
-        left = (s + gamma) | BVH_LEAF;
-        b.parent_leaf[s + gamma] = node;
-    } else {
-        left = s + gamma;
-        b.parent_node[s + gamma] = node;
-    }
-    if (hi == gamma + 1) {
-        right = (s + gamma + 1) | BVH_LEAF;
-        b.parent_leaf[s + gamma + 1] = node;
-    } else {
-        right = s + gamma + 1;
-        b.parent_node[s + gamma + 1] = node;
-    }
-    b.left[node] = left;
-    b.right[node] = right;
+    b.left[node] = lo == gamma ? ((s + gamma) | BVH_LEAF) : s + gamma;
+    b.right[node] = hi == gamma + 1 ? ((s + gamma + 1) | BVH_LEAF) : s + gamma + 1;
+    b.rlo[node] = s + lo;
+    b.rsplit[node] = s + gamma;
+    b.rhi[node] = s + hi;
 }
 
-__device__ __forceinline__ double coherent_load(const double *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Box tables over the build positions in sorted order: blk[k] bounds leaves [64k, 64k + 64)
+// (one wavefront per block, shuffle reductions), sblk[k] bounds leaves [4096k, 4096k + 4096)
+// (one wavefront per 64 blocks). A block may straddle two types' ranges; a node's range query
+// uses only the blocks that lie inside it.
+__device__ __forceinline__ void wave_minmax(double lo[3], double hi[3]) {
+    for (int o = 32; o > 0; o >>= 1)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], o));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], o));
+        }
+}
+
+__global__ void __launch_bounds__(256) k_bvh_blocks(const BvhArgs b) {
+    if (!bvh_go(b)) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = g >> 6;
+    if (k >= (b.n + 63) / 64) return;  // whole wavefronts: 64 divides the workgroup
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (g < b.n) {
+        const double4 x = b.xb[g];
+        lo[0] = hi[0] = x.x;
+        lo[1] = hi[1] = x.y;
+        lo[2] = hi[2] = x.z;
+    }
+    wave_minmax(lo, hi);
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) {
+            b.blk[6 * (size_t)k + a] = lo[a];
+            b.blk[6 * (size_t)k + 3 + a] = hi[a];
+        }
+}
+
+__global__ void __launch_bounds__(256) k_bvh_sblocks(const BvhArgs b) {
+    if (!bvh_go(b)) return;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nb = (b.n + 63) / 64;
+    const int k = g >> 6;
+    if (k >= (b.n + 4095) / 4096) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (g < nb)
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = b.blk[6 * (size_t)g + a];
+            hi[a] = b.blk[6 * (size_t)g + 3 + a];
+        }
+    wave_minmax(lo, hi);
+    if ((threadIdx.x & 63) == 0)
+        for (int a = 0; a < 3; ++a) {
+            b.sblk[6 * (size_t)k + a] = lo[a];
+            b.sblk[6 * (size_t)k + 3 + a] = hi[a];
+        }
+}
+
+// The bounding box of the build positions of sorted leaves [i, e]: single leaves up to a block
+// boundary, whole blocks up to a 4096 boundary, whole 4096-blocks, then blocks and leaves
+// again (at most 63 + 63 + n/4096 + 63 + 63 reads). Minimum and maximum are exact, so this is
+// the box of the range itself.
+__device__ __forceinline__ void range_box(const BvhArgs &b, int i, int e, double *out) {
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    auto leaf = [&](int k) {
+        const double4 x = b.xb[k];
+        const double c[3] = {x.x, x.y, x.z};
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], c[a]);
+            hi[a] = fmax(hi[a], c[a]);
+        }
+    };
+    auto box = [&](const double *t) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], t[a]);
+            hi[a] = fmax(hi[a], t[3 + a]);
+        }
+    };
+    while (i <= e && (i & 63)) leaf(i++);
+    while (i + 63 <= e && (i & 4095)) {
+        box(b.blk + 6 * (size_t)(i >> 6));
+        i += 64;
+    }
+    while (i + 4095 <= e) {
+        box(b.sblk + 6 * (size_t)(i >> 12));
+        i += 4096;
+    }
+    while (i + 63 <= e) {
+        box(b.blk + 6 * (size_t)(i >> 6));
+        i += 64;
+    }
+    while (i <= e) leaf(i++);
+    for (int a = 0; a < 3; ++a) {
+        out[a] = lo[a];
+        out[3 + a] = hi[a];
+    }
 }
 
 // Each internal node stores the boxes of its two children (12 doubles: lo xyz, hi xyz of the
 // left child, then of the right one), so a walk reads one record per node it opens and tests
-// both children from it; a leaf child's box is its build position (lo = hi, exactly).
-// The box of child c: a leaf's build position, or the union of the two child boxes an internal
-// node stores (read past the non-coherent caches while boxes are still being formed).
-__device__ __forceinline__ void child_box_bu(const BvhArgs &b, int c, double lo[3], double hi[3]) {
-    if (c & BVH_LEAF) {
-        const double4 x = b.xb[c & ~BVH_LEAF];
-        lo[0] = hi[0] = x.x;
-        lo[1] = hi[1] = x.y;
-        lo[2] = hi[2] = x.z;
-    } else {
-        const double *bx = b.box + 12 * (size_t)c;
-        for (int a = 0; a < 3; ++a) {
-            lo[a] = fmin(coherent_load(bx + a), coherent_load(bx + 6 + a));
-            hi[a] = fmax(coherent_load(bx + 3 + a), coherent_load(bx + 9 + a));
-        }
-    }
-}
-
-// Boxes bottom-up: from each leaf, the second of a node's two children to arrive stores both
-// children's boxes in the node and climbs on; the first stops.
+// both children from it. A child's box is that of its leaf range: [rlo, rsplit] on the left,
+// [rsplit + 1, rhi] on the right (a leaf child's box is its build position, lo = hi).
 __global__ void __launch_bounds__(256) k_bvh_boxes(const BvhArgs b) {
     if (!bvh_go(b)) return;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= b.n) return;
-    int node = b.parent_leaf[g];
-    while (node >= 0) {
-        __threadfence();
-        if (atomicAdd(&b.flag[node], 1) == 0) return;
-        __threadfence();
-        double lo[3], hi[3];
-        double *bx = b.box + 12 * (size_t)node;
-        child_box_bu(b, b.left[node], lo, hi);
-        for (int a = 0; a < 3; ++a) {
-            bx[a] = lo[a];
-            bx[3 + a] = hi[a];
-        }
-        child_box_bu(b, b.right[node], lo, hi);
-        for (int a = 0; a < 3; ++a) {
-            bx[6 + a] = lo[a];
-            bx[9 + a] = hi[a];
-        }
-        node = b.parent_node[node];
-    }
+    int s, e;
+    bvh_type_range(b, g, s, e);
+    if (g - s >= e - s - 1) return;  // the type's last leaf index has no internal node
+    double *bx = b.box + 12 * (size_t)g;
+    const int sp = b.rsplit[g];
+    range_box(b, b.rlo[g], sp, bx);
+    range_box(b, sp + 1, b.rhi[g], bx + 6);
 }
 
 // Squared distance from q to a box (0 inside).
@@ -304,8 +346,11 @@ hipError_t launch_rebuild_bvh(hipStream_t s, const RebuildArgs &a, const BvhArgs
     hipError_t e = launch_sort_cells(s, a, ev);
     if (e != hipSuccess) return e;
     const int g = (b.n + 255) / 256;
+    const int nb = (b.n + 63) / 64;
     hipLaunchKernelGGL(k_bvh_copy, dim3(g), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_bvh_nodes, dim3(g), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bvh_blocks, dim3((nb + 3) / 4), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bvh_sblocks, dim3(((b.n + 4095) / 4096 + 3) / 4), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_bvh_boxes, dim3(g), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_bvh_list, dim3(g), dim3(256), 0, s, b);
     if (ev) (void)hipEventRecord(ev[5], s);

@@ -231,8 +231,8 @@ struct RebuildArgs {
 };
 
 // Tree (BVH) neighbour lists, one tree per particle type over the type's particles in their
-// sorted order: the Karras construction on the keys (cell << 32 | index), boxes bottom-up,
-// and one traversal per particle and tree.
+// sorted order: the Karras construction on the keys (cell << 32 | index), the children's boxes
+// of every node from range reductions over box tables, and one traversal per particle and tree.
 constexpr int BVH_LEAF = 1 << 30;   // child code: a leaf (particle index | BVH_LEAF)
 constexpr int BVH_STACK = 64;       // traversal stack (tree depth is at most the 64 key bits)
 struct BvhArgs {
@@ -243,8 +243,9 @@ struct BvhArgs {
     const int *cell_start;   // typed cells: type t is [cell_start[t ncs], cell_start[(t+1) ncs])
     const int *cell_of;
     int *left, *right;       // internal node children (node of type t at s_t + local index)
-    int *parent_leaf, *parent_node;
-    int *flag;               // bottom-up arrival counters (cleared by the node kernel)
+    int *rlo, *rsplit, *rhi; // internal node's leaves [rlo, rhi]; the left child's end rsplit
+    double *blk;             // per 64 leaves (sorted order): their box, lo x y z, hi x y z
+    double *sblk;            // per 4096 leaves: their box
     double *box;             // 12 doubles per internal node: its children's boxes (lo, hi)
     const double *rl2_table; // list radii squared per type pair (0: pair disabled)
     int *nl_count;

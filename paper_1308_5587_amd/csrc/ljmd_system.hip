@@ -94,8 +94,8 @@ struct ljmd_system {
     int nlist_method = LJMD_NLIST_CELL;
     int ncs = 0;
     int *d_cell_of = nullptr, *d_bvh_left = nullptr, *d_bvh_right = nullptr,
-        *d_bvh_pleaf = nullptr, *d_bvh_pnode = nullptr, *d_bvh_flag = nullptr;
-    double *d_bvh_box = nullptr;
+        *d_bvh_rlo = nullptr, *d_bvh_rsplit = nullptr, *d_bvh_rhi = nullptr;
+    double *d_bvh_box = nullptr, *d_bvh_blk = nullptr, *d_bvh_sblk = nullptr;
     int32_t *d_nlist32 = nullptr;
     size_t nlist32_alloc = 0;
     // NVT thermostat: device scalars (TH_*), their snapshot, kinetic-energy partials
@@ -309,17 +309,20 @@ int setup_table(ljmd_system *s) {
     return LJMD_OK;
 }
 
-// The tree method's node, box and cell arrays (n each; 12 box doubles per node).
+// The tree method's node, box and cell arrays (n each; 12 box doubles per node; 6 per block of
+// 64 and of 4096 leaves).
 int ensure_tree_arrays(ljmd_system *s) {
     if (s->d_cell_of) return LJMD_OK;
     const size_t N = (size_t)s->n;
     CHK(dalloc_t(s, &s->d_cell_of, N));
     CHK(dalloc_t(s, &s->d_bvh_left, N));
     CHK(dalloc_t(s, &s->d_bvh_right, N));
-    CHK(dalloc_t(s, &s->d_bvh_pleaf, N));
-    CHK(dalloc_t(s, &s->d_bvh_pnode, N));
-    CHK(dalloc_t(s, &s->d_bvh_flag, N));
+    CHK(dalloc_t(s, &s->d_bvh_rlo, N));
+    CHK(dalloc_t(s, &s->d_bvh_rsplit, N));
+    CHK(dalloc_t(s, &s->d_bvh_rhi, N));
     CHK(dalloc_t(s, &s->d_bvh_box, 12 * N));
+    CHK(dalloc_t(s, &s->d_bvh_blk, 6 * ((N + 63) / 64)));
+    CHK(dalloc_t(s, &s->d_bvh_sblk, 6 * ((N + 4095) / 4096)));
     return LJMD_OK;
 }
 
@@ -424,9 +427,11 @@ BvhArgs bvh_args(ljmd_system *s, const int *go, int cur) {
     b.cell_of = s->d_cell_of;
     b.left = s->d_bvh_left;
     b.right = s->d_bvh_right;
-    b.parent_leaf = s->d_bvh_pleaf;
-    b.parent_node = s->d_bvh_pnode;
-    b.flag = s->d_bvh_flag;
+    b.rlo = s->d_bvh_rlo;
+    b.rsplit = s->d_bvh_rsplit;
+    b.rhi = s->d_bvh_rhi;
+    b.blk = s->d_bvh_blk;
+    b.sblk = s->d_bvh_sblk;
     b.box = s->d_bvh_box;
     b.rl2_table = s->d_rl2;
     b.nl_count = s->d_count;
