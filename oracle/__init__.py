@@ -101,6 +101,7 @@ def _load():
         lib.oracle_get_thermostat.argtypes = [C.c_void_p, dp, dp, dp]
         lib.oracle_set_thermostat.argtypes = [C.c_void_p, C.c_double, C.c_double]
         lib.oracle_negate_velocities.argtypes = [C.c_void_p]
+        lib.oracle_set_shift_mode.argtypes = [C.c_void_p, C.c_int32]
         _lib = lib
     return _lib
 
@@ -214,6 +215,13 @@ class OracleSystem:
         p[:len(params)] = params
         _check(self._lib.oracle_set_pair_style(self._h, a, b, self.STYLES[style], _dp(p),
                                                float(rc)))
+
+    SHIFTS = {"energy": 0, "force": 1}
+
+    def set_shift_mode(self, mode):
+        """'energy': the energy is shifted to 0 at r_cut, the force is not (the default);
+        'force': the force is shifted too (shifted-force form, both vanish at r_cut)."""
+        _check(self._lib.oracle_set_shift_mode(self._h, self.SHIFTS[mode]))
 
     def set_nvt(self, kT, tau):
         """NVT (Nose-Hoover, symmetric splitting) at kT with time constant tau; tau may be

@@ -38,6 +38,11 @@
  *                 Gaussian(eps, sigma): u = eps exp(-r^2 / (2 s^2)); f = eps / s^2 exp(-r^2 / (2 s^2))
  *                 Yukawa(eps, kappa): u = eps exp(-kappa r) / r; f = eps exp(-kappa r) (1 + kappa r) / r^3
  *               WCA is the LJ form cut at 2^(1/6) sigma (the shift then is +eps).
+ *   shifted     (an option per system, for tighter energy conservation): the force is
+ *   force       shifted as well, so that both vanish at r_cut. With F(r) = f(r) r the
+ *               pair force magnitude (positive when repulsive) and F_c = F(r_cut):
+ *                 u_sf(r) = u(r) - u(r_cut) + (r - r_cut) F_c,  f_sf(r) = f(r) - F_c / r,
+ *               so that F_sf = F - F_c = -du_sf/dr, and u_sf(r_cut) = F_sf(r_cut) = 0.
  *   NVT         (the integrator of the paper's MD listing, built on the Martyna-Tobias-
  *               Klein method, Section "Capabilities"): one Nose-Hoover thermostat
  *               variable xi with "position" eta and mass Q = N_f kT tau^2, N_f = 3N - 3.
@@ -90,6 +95,7 @@ typedef struct {
     /* NVT thermostat (nvt = 0: NVE) */
     int nvt;
     double kT, invQ, xi, eta;
+    int shift_force;         /* 1: shifted force (see the header), 0: shifted energy only */
 } orc_sys;
 
 /* ---------------------------------------------------------------- basic definitions */
@@ -306,6 +312,15 @@ int oracle_set_pair_style(orc_sys *s, int32_t a, int32_t b, int32_t style, const
     return ORC_OK;
 }
 
+/* mode 0: energy shifted to 0 at r_cut, force not shifted; mode 1: shifted force */
+int oracle_set_shift_mode(orc_sys *s, int32_t mode)
+{
+    if (!s || (mode != 0 && mode != 1)) return ORC_EINVAL;
+    s->shift_force = mode;
+    s->force_valid = 0;
+    return ORC_OK;
+}
+
 static int check_ready(const orc_sys *s)
 {
     for (int k = 0; k < s->ntypes * s->ntypes; ++k)
@@ -429,15 +444,24 @@ static int compute_forces(orc_sys *s)
         int k = pair_index(s, s->type[i], s->type[j]);
         double rcut2 = s->rc[k] * s->rc[k];
         if (!(r2 < rcut2)) continue;
-        double ff, u;
+        double ff, u, ffc;
         if (s->style[k] == ORC_LJ) {
             ff = lj_force_factor(s->eps[k], s->sig[k], r2);
             u = lj_energy(s->eps[k], s->sig[k], r2) -
                 lj_energy(s->eps[k], s->sig[k], rcut2);
+            ffc = lj_force_factor(s->eps[k], s->sig[k], rcut2);
         } else {
             const double *p = s->par + 4 * k;
             ff = form_force_factor(s->style[k], p, r2);
             u = form_energy(s->style[k], p, r2) - form_energy(s->style[k], p, rcut2);
+            ffc = form_force_factor(s->style[k], p, rcut2);
+        }
+        if (s->shift_force) {
+            /* F_c = f(r_cut) r_cut; u_sf = u + (r - r_cut) F_c; f_sf = f - F_c / r */
+            double r = sqrt(r2);
+            double fc = ffc * s->rc[k];
+            u = u + (r - s->rc[k]) * fc;
+            ff = ff - fc / r;
         }
         double rij[3] = {-d[0], -d[1], -d[2]};  /* x_i - x_j */
         for (int a = 0; a < 3; ++a) {

@@ -116,15 +116,17 @@ def _form(style, p, r):
     return 4 * eps * (x6 * x6 - x6), 24 * eps * (2 * x6 * x6 - x6) / r
 
 
-def brute_fuw_style(box, pos, style, params, rc):
+def brute_fuw_style(box, pos, style, params, rc, shift_force=False):
     """Forces, total energy and virial of one pair form (single type), truncated at rc and
-    energy-shifted there, over every pair (i < j) within rc."""
+    energy-shifted there (with shift_force, force-shifted as well: the pair force less its
+    value at rc, and the energy less the matching linear term), over every pair (i < j)
+    within rc."""
     pos = np.asarray(pos, dtype=np.float64)
     n = pos.shape[0]
     F = np.zeros((n, 3))
     U = 0.0
     W = np.zeros(6)
-    u_c, _ = _form(style, params, np.array([rc]))
+    u_c, f_c = _form(style, params, np.array([rc]))
     for i in range(n - 1):
         d = np.stack([_min_image(pos[i + 1:, a] - pos[i, a], box[a]) for a in range(3)], 1)
         r = np.sqrt((d * d).sum(1))
@@ -132,7 +134,12 @@ def brute_fuw_style(box, pos, style, params, rc):
         d, r = d[inside], r[inside]
         j = np.nonzero(inside)[0] + i + 1
         u, mdu = _form(style, params, r)
-        U += float((u - u_c[0]).sum())
+        u = u - u_c[0]
+        if shift_force:
+            # the force (-du/dr) less its value at rc; the energy whose derivative that is
+            mdu = mdu - f_c[0]
+            u = u + (r - rc) * f_c[0]
+        U += float(u.sum())
         fij = (mdu / r)[:, None] * (-d)  # on i, along x_i - x_j
         F[i] += fij.sum(0)
         np.add.at(F, j, -fij)

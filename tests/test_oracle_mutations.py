@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle_md.c")
 PIN_TESTS = ["tests/test_oracle_invariants.py", "tests/test_oracle_vs_brute.py",
              "tests/test_six_particle.py", "tests/test_oracle_nvt.py",
-             "tests/test_oracle_styles.py"]
+             "tests/test_oracle_styles.py", "tests/test_oracle_shift.py"]
 
 MUTANTS = {
     "drop_energy_shift": ("lj_energy(s->eps[k], s->sig[k], r2) -\n                lj_energy(",
@@ -45,6 +45,10 @@ MUTANTS = {
     "yukawa_force_sign": ("(1.0 + p[1] * r) / (r2 * r)", "(1.0 - p[1] * r) / (r2 * r)"),
     "form_energy_shift_dropped": ("u = form_energy(s->style[k], p, r2) - form_energy(",
                                   "u = form_energy(s->style[k], p, r2) - 0.0 * form_energy("),
+    # shifted force
+    "shift_force_linear_term_sign": ("u = u + (r - s->rc[k]) * fc;", "u = u - (r - s->rc[k]) * fc;"),
+    "shift_force_not_over_r": ("ff = ff - fc / r;", "ff = ff - fc;"),
+    "shift_force_cut_force_unscaled": ("double fc = ffc * s->rc[k];", "double fc = ffc;"),
     "nvt_end_half_step_dropped": ("if (s->nvt) thermostat_half(s);\n        s->steps += 1;",
                                   "s->steps += 1;"),
 }
