@@ -212,6 +212,19 @@ int ljmd_set_state(ljmd_system *sys, const double *pos, const double *vel, const
 #define LJMD_NLIST_TREE 1
 int ljmd_set_nlist(ljmd_system *sys, int32_t method);
 
+/* How every pair form of the system is truncated at its r_cut:
+ *   LJMD_SHIFT_ENERGY  (default) the energy is shifted to 0 at r_cut, the force is not (it
+ *                      jumps to 0 there), as the paper's LJ pair force does by default.
+ *   LJMD_SHIFT_FORCE   shifted force, for tighter energy conservation: with F(r) the pair
+ *                      force magnitude (positive when repulsive) and F_c = F(r_cut), the
+ *                      force is F(r) - F_c and the energy u(r) - u(r_cut) + (r - r_cut) F_c,
+ *                      so both vanish at r_cut and the force stays -du/dr.
+ * Applies to the LJ form and to every form of ljmd_pair_set; the next step or read uses it.
+ * Errors: INVAL (unknown mode; the tree lists with the shifted force, at the next step). */
+#define LJMD_SHIFT_ENERGY 0
+#define LJMD_SHIFT_FORCE 1
+int ljmd_set_pair_shift(ljmd_system *sys, int32_t mode);
+
 /* The current neighbour list as unordered tag pairs (i < j), 2 x count int32, sorted by
  * (i, j); pairs = NULL only returns the count. build_pos (n x 3, tag order, nullable)
  * receives the positions the list was built from. */

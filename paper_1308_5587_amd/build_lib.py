@@ -12,8 +12,9 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libljmd.so")
 SOURCES = ["ljmd_kernels.hip", "ljmd_force_lj.hip", "ljmd_force_mie.hip", "ljmd_force_gauss.hip",
-           "ljmd_force_yukawa.hip", "ljmd_force_glist.hip", "ljmd_bvh.hip", "ljmd_host.hip",
-           "ljmd_system.hip", "ljmd_batch.hip"]
+           "ljmd_force_yukawa.hip", "ljmd_force_lj_sf.hip", "ljmd_force_mie_sf.hip",
+           "ljmd_force_gauss_sf.hip", "ljmd_force_yukawa_sf.hip", "ljmd_force_glist.hip",
+           "ljmd_bvh.hip", "ljmd_host.hip", "ljmd_system.hip", "ljmd_batch.hip"]
 
 # -ffp-contract=off: the distance arithmetic must not be fused (explicit fma elsewhere).
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.

@@ -47,8 +47,9 @@ struct Acc<PREC_MIXED> {
 //           f = lj1 exp(lj2 r^2), u = lj3 exp(lj2 r^2) - shift
 //   Yukawa  lj1 = eps, lj2 = kappa: f = eps exp(-kappa r) (1 + kappa r) / r^3,
 //           u = eps exp(-kappa r) / r - shift
-template <int STYLE, bool ENERGY>
+template <int FORM, bool ENERGY>
 __device__ __forceinline__ double form64(const PairCoef &c, double r2, double &u) {
+    constexpr int STYLE = FORM & 7;
     if (STYLE == STYLE_LJ) {
         const double r2i = rcp64(r2);
         const double r6i = r2i * r2i * r2i;
@@ -73,8 +74,9 @@ __device__ __forceinline__ double form64(const PairCoef &c, double r2, double &u
 }
 
 // The same in FP32 (the mixed path); the energy shift is applied in FP64 by the caller.
-template <int STYLE, bool ENERGY>
+template <int FORM, bool ENERGY>
 __device__ __forceinline__ float form32(const PairCoef &c, float r2, float &u) {
+    constexpr int STYLE = FORM & 7;
     if (STYLE == STYLE_LJ) {
         const float r2i = __builtin_amdgcn_rcpf(r2);
         const float r6i = r2i * r2i * r2i;
@@ -100,7 +102,9 @@ __device__ __forceinline__ float form32(const PairCoef &c, float r2, float &u) {
 }
 
 // One pair inside the cutoff: add the force on i (and, with ENERGY, half the pair energy and
-// virial) for the displacement d = x_j - x_i with r2 = |d|^2.
+// virial) for the displacement d = x_j - x_i with r2 = |d|^2. With STYLE_SF in STYLE, the
+// shifted-force variant: f - F(r_cut) / r, and u + r F(r_cut) (the shift holds the constant
+// part, u(r_cut) + r_cut F(r_cut)), so that both vanish at r_cut.
 template <int STYLE, int PREC, bool ENERGY>
 __device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double dy, double dz,
                                           double r2, Acc<PREC> &acc, double &ue, double &w0,
@@ -108,7 +112,12 @@ __device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double d
                                           double &w5) {
     if (PREC == PREC_FP64) {
         double u = 0.0;
-        const double ff = form64<STYLE, ENERGY>(c, r2, u);
+        double ff = form64<STYLE, ENERGY>(c, r2, u);
+        if (STYLE & STYLE_SF) {
+            const double r = __builtin_sqrt(r2);
+            ff = __builtin_fma(-c.fcut, rcp64(r), ff);
+            if (ENERGY) u = __builtin_fma(c.fcut, r, u);
+        }
         // force on i is ff * (x_i - x_j) = -ff * d
         acc.fx = __builtin_fma(-ff, dx, acc.fx);
         acc.fy = __builtin_fma(-ff, dy, acc.fy);
@@ -128,12 +137,17 @@ __device__ __forceinline__ void pair_term(const PairCoef &c, double dx, double d
         const float fdx = (float)dx, fdy = (float)dy, fdz = (float)dz;
         const float fr2 = (float)r2;
         float up = 0.0f;
-        const float ff = form32<STYLE, ENERGY>(c, fr2, up);
+        float ff = form32<STYLE, ENERGY>(c, fr2, up);
+        float fr = 0.0f;
+        if (STYLE & STYLE_SF) {
+            fr = __builtin_sqrtf(fr2);
+            ff = __builtin_fmaf(-(float)c.fcut, __builtin_amdgcn_rcpf(fr), ff);
+        }
         acc.fx = __builtin_fmaf(-ff, fdx, acc.fx);
         acc.fy = __builtin_fmaf(-ff, fdy, acc.fy);
         acc.fz = __builtin_fmaf(-ff, fdz, acc.fz);
         if (ENERGY) {
-            ue += 0.5 * ((double)up - c.shift);
+            ue += 0.5 * ((double)up - c.shift + ((STYLE & STYLE_SF) ? c.fcut * (double)fr : 0.0));
             const double hf = 0.5 * (double)ff;
             w0 = __builtin_fma(hf * (double)fdx, (double)fdx, w0);
             w1 = __builtin_fma(hf * (double)fdx, (double)fdy, w1);

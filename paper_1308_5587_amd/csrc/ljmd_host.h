@@ -61,6 +61,10 @@ void make_pair_table(int ntypes, const double *eps, const double *sig, const dou
 // 4 per pair: (eps, sigma, n, m), (eps, sigma), (eps, kappa).
 void make_form_table(int ntypes, int style, const double *par, const double *rc, double skin,
                      PairTable *out);
+// The shifted-force variant of a table (style one of STYLE_LJ .. STYLE_YUKAWA): per pair,
+// fcut = F(r_cut) (the force factor at r_cut times r_cut) and the shift raised by r_cut fcut,
+// so that the kernels' f - fcut / r and u + r fcut - shift vanish at r_cut.
+void apply_force_shift(int style, const double *rc, PairTable *pt);
 
 // Cell grid, bricks and halos of one replica, with replica-local cell indices.
 struct ReplicaGrid {

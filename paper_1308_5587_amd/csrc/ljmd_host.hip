@@ -128,6 +128,30 @@ void make_form_table(int nt, int style, const double *par, const double *rc, dou
     }
 }
 
+void apply_force_shift(int style, const double *rc, PairTable *pt) {
+    for (size_t k = 0; k < pt->coef.size(); ++k) {
+        PairCoef &c = pt->coef[k];
+        const double r = rc[k];
+        if (!(r > 0.0)) continue;
+        const double r2 = c.rc2;
+        double f;  // the force factor at r_cut, as the kernels evaluate it
+        if (style == STYLE_LJ) {
+            const double r2i = 1.0 / r2;
+            const double r6i = r2i * r2i * r2i;
+            f = r2i * r6i * (c.lj1 * r6i - c.lj2);
+        } else if (style == STYLE_MIE) {
+            const double lr = std::log(r2);
+            f = (c.lj1 * std::exp(-c.lj3 * lr) - c.lj2 * std::exp(-c.lj4 * lr)) / r2;
+        } else if (style == STYLE_GAUSS) {
+            f = c.lj1 * std::exp(c.lj2 * r2);
+        } else {
+            f = c.lj1 * std::exp(-c.lj2 * r) * (1.0 + c.lj2 * r) / (r2 * r);
+        }
+        c.fcut = f * r;
+        c.shift += r * c.fcut;
+    }
+}
+
 // ------------------------------------------------------------------ cell grid and bricks
 
 static uint64_t spread3(uint64_t v) {  // 10-bit value -> every third bit

@@ -17,8 +17,9 @@ struct PairCoef {
     double lj2;    // 24 eps sig^6
     double lj3;    // 4 eps sig^12    energy: u = r^-6 (lj3 r^-6 - lj4) - shift
     double lj4;    // 4 eps sig^6
-    double shift;  // 4 eps ((sig/r_cut)^12 - (sig/r_cut)^6), the energy at r_cut
-    double pad;
+    double shift;  // 4 eps ((sig/r_cut)^12 - (sig/r_cut)^6), the energy at r_cut (shifted
+                   // force: that plus r_cut fcut)
+    double fcut;   // shifted force only: F(r_cut), the pair force magnitude at the cutoff
 };
 // (the other forms keep their coefficients in lj1..lj4 too: see form64 in ljmd_force.h)
 
@@ -108,6 +109,9 @@ enum { MODE_EVAL = 0, MODE_FUSED = 1, MODE_FINAL = 2 };
 // Pair forms (one per system; the batch uses LJ). The PairCoef fields lj1..lj4 hold each
 // form's coefficients (see form64 in ljmd_force.h).
 enum { STYLE_LJ = 0, STYLE_MIE = 1, STYLE_GAUSS = 2, STYLE_YUKAWA = 3, STYLE_COUNT = 4 };
+// Flag on a style: its shifted-force variant (force less F(r_cut), energy less the matching
+// linear term; PairCoef::fcut).
+constexpr int STYLE_SF = 8;
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };
 
 constexpr int LJMD_MAX_TYPES_DEV = 16; // equals LJMD_MAX_TYPES of the public header
@@ -270,6 +274,15 @@ hipError_t launch_force_gauss(hipStream_t s, const ForceArgs &a, int prec, int t
                               bool energy, int block);
 hipError_t launch_force_yukawa(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
                                bool energy, int block);
+// the shifted-force variants (STYLE_SF)
+hipError_t launch_force_lj_sf(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                              bool energy, int block);
+hipError_t launch_force_mie_sf(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                               bool energy, int block);
+hipError_t launch_force_gauss_sf(hipStream_t s, const ForceArgs &a, int prec, int tpp, int mode,
+                                 bool energy, int block);
+hipError_t launch_force_yukawa_sf(hipStream_t s, const ForceArgs &a, int prec, int tpp,
+                                  int mode, bool energy, int block);
 hipError_t launch_rebuild(hipStream_t s, const RebuildArgs &a, hipEvent_t *ev = nullptr);
 // The sort of launch_rebuild (bin, scan, scatter, gather) over the typed sort grid, then the
 // tree build and traversal; ev as for launch_rebuild (the tree kernels in the last slot).

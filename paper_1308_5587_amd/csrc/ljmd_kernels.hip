@@ -126,6 +126,13 @@ hipError_t launch_force(hipStream_t s, const ForceArgs &a, int prec, int tpp, in
         case STYLE_MIE: return launch_force_mie(s, a, prec, tpp, mode, energy, block);
         case STYLE_GAUSS: return launch_force_gauss(s, a, prec, tpp, mode, energy, block);
         case STYLE_YUKAWA: return launch_force_yukawa(s, a, prec, tpp, mode, energy, block);
+        case STYLE_LJ | STYLE_SF: return launch_force_lj_sf(s, a, prec, tpp, mode, energy, block);
+        case STYLE_MIE | STYLE_SF:
+            return launch_force_mie_sf(s, a, prec, tpp, mode, energy, block);
+        case STYLE_GAUSS | STYLE_SF:
+            return launch_force_gauss_sf(s, a, prec, tpp, mode, energy, block);
+        case STYLE_YUKAWA | STYLE_SF:
+            return launch_force_yukawa_sf(s, a, prec, tpp, mode, energy, block);
         default: return hipErrorInvalidValue;
     }
 }

@@ -55,6 +55,7 @@ struct ljmd_system {
     std::vector<char> is_set;
     // pair form of the system (all set pairs share it) and each pair's form parameters
     int style = STYLE_LJ;
+    int shift_force = 0;  // LJMD_SHIFT_FORCE: the shifted-force variant of the form
     std::vector<int> pform;       // form of each set pair
     std::vector<double> par;      // 4 per pair
     std::vector<int32_t> h_type;
@@ -217,10 +218,12 @@ int setup_table(ljmd_system *s) {
         make_pair_table(nt, s->eps.data(), s->sig.data(), s->rc.data(), s->cfg.skin, &pt);
     else
         make_form_table(nt, s->style, s->par.data(), s->rc.data(), s->cfg.skin, &pt);
+    if (s->shift_force) apply_force_shift(s->style, s->rc.data(), &pt);
     ReplicaGrid g;
     if (s->nlist_method == LJMD_NLIST_TREE) {
-        if (s->style != STYLE_LJ)
-            return set_err(LJMD_E_INVAL, "tree neighbour lists evaluate the LJ form only");
+        if (s->style != STYLE_LJ || s->shift_force)
+            return set_err(LJMD_E_INVAL,
+                           "tree neighbour lists evaluate the LJ form with the energy shift only");
         CHK(make_sort_grid(s, pt.rl_max, &g));
     } else {
         CHK(make_grid(s->L, pt.rl_max, &g, s->n, tile_limit_for(nt, s->lds_limit)));
@@ -516,7 +519,8 @@ hipError_t launch_forces(ljmd_system *s, hipStream_t st, const ForceArgs &fa, in
                          bool energy) {
     if (s->nlist_method == LJMD_NLIST_TREE)
         return launch_force_glist(st, fa, precision(s), s->tpp, mode, energy, s->block);
-    return launch_force(st, fa, precision(s), s->tpp, mode, energy, s->block, s->style);
+    return launch_force(st, fa, precision(s), s->tpp, mode, energy, s->block,
+                        s->style | (s->shift_force ? STYLE_SF : 0));
 }
 
 int enqueue_eval(ljmd_system *s, bool energy) {
@@ -1392,6 +1396,19 @@ int ljmd_negate_velocities(ljmd_system *s) {
     CHK(launch_chk(launch_negate_vel(s->stream, s->d_vel, 0, s->n), "negate"));
     HIPCHK(hipStreamSynchronize(s->stream));
     s->nvt_ready = false;
+    return LJMD_OK;
+}
+
+int ljmd_set_pair_shift(ljmd_system *s, int32_t mode) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (mode != LJMD_SHIFT_ENERGY && mode != LJMD_SHIFT_FORCE)
+        return set_err(LJMD_E_INVAL, "unknown shift mode %d", mode);
+    if ((mode == LJMD_SHIFT_FORCE) == (s->shift_force != 0)) return LJMD_OK;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->shift_force = mode == LJMD_SHIFT_FORCE;
+    s->table_dirty = true;  // coefficients change; the list radii do not
+    s->force_valid = false;
+    drop_graphs(s);
     return LJMD_OK;
 }
 

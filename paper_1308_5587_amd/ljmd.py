@@ -96,7 +96,7 @@ EXPORTED = [
     "ljmd_step",
     "ljmd_get_forces", "ljmd_get_energy", "ljmd_get_virial", "ljmd_get_per_particle",
     "ljmd_get_state", "ljmd_set_state", "ljmd_get_neighbor_pairs", "ljmd_get_neighbor_list",
-    "ljmd_get_stats", "ljmd_set_nlist", "ljmd_set_nvt", "ljmd_set_nve", "ljmd_get_thermostat",
+    "ljmd_get_stats", "ljmd_set_nlist", "ljmd_set_pair_shift", "ljmd_set_nvt", "ljmd_set_nve", "ljmd_get_thermostat",
     "ljmd_set_thermostat", "ljmd_negate_velocities",
     "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_kernel_durations", "ljmd_last_error", "ljmd_version",
     "ljmd_batch_create", "ljmd_batch_destroy", "ljmd_batch_footprint", "ljmd_batch_admit",
@@ -132,6 +132,7 @@ def load(path: str = LIB_PATH):
         "ljmd_get_neighbor_list": ([vp, ip, lp, ip, dp], C.c_int),
         "ljmd_get_stats": ([vp, C.POINTER(LjmdStats)], C.c_int),
         "ljmd_set_nlist": ([vp, C.c_int32], C.c_int),
+        "ljmd_set_pair_shift": ([vp, C.c_int32], C.c_int),
         "ljmd_set_nvt": ([vp, C.c_double, C.c_double], C.c_int),
         "ljmd_set_nve": ([vp], C.c_int),
         "ljmd_get_thermostat": ([vp, dp, dp, dp], C.c_int),
@@ -343,6 +344,13 @@ class System:
     def set_nlist(self, method):
         """Neighbour-list method: 'cell' (default) or 'tree' (one BVH per type)."""
         _check(self._lib.ljmd_set_nlist(self._h, self.NLIST_METHODS[method]))
+
+    SHIFT_MODES = {"energy": 0, "force": 1}
+
+    def set_pair_shift(self, mode):
+        """Truncation of every pair form at r_cut: 'energy' (default; energy shifted to 0,
+        force not) or 'force' (shifted force: both vanish at r_cut)."""
+        _check(self._lib.ljmd_set_pair_shift(self._h, self.SHIFT_MODES[mode]))
 
     def set_nvt(self, kT, tau):
         """NVT at kT with thermostat time constant tau (float('inf'): zero coupling)."""

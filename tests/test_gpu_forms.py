@@ -103,3 +103,51 @@ def test_one_form_per_system(ljmd_mod):
         g.pair_set(1, 1, "mie", (1.0, 1.0, 6.0, 12.0), 2.5)  # n <= m
     with pytest.raises(ljmd_mod.LjmdError):
         g.pair_set(1, 1, "wca", (1.0, 1.0), 2.5)  # WCA takes its own cut
+
+
+SF_FORMS = [("lj", (1.0, 1.0), 2.5), ("mie", (1.0, 1.0, 14.0, 7.0), 2.5),
+            ("gauss", (3.0, 1.0), 2.8), ("yukawa", (2.0, 1.2), 2.6)]
+
+
+@pytest.mark.parametrize("form,params,rc", SF_FORMS)
+def test_shifted_force(ljmd_mod, oracle_mod, form, params, rc):
+    print_case(f"shifted force, pair form {form}")
+    s = gen.make_lj_fluid(4000, rho=0.8442 if form != "gauss" else 0.5, T=1.2, seed=4)
+    o = oracle_mod.OracleSystem(s.box, s.pos, s.vel, s.type, 1, [])
+    o.set_pair_style(0, 0, form, params, rc)
+    o.set_shift_mode("force")
+    g = ljmd_mod.System(s.box, s.pos, s.vel, s.type, 1, [])
+    g.pair_set(0, 0, form, params, rc)
+    g.set_pair_shift("force")
+    _check(o, g, 1e-10)
+    m = ljmd_mod.System(s.box, s.pos, s.vel, s.type, 1, [], precision="mixed")
+    m.pair_set(0, 0, form, params, rc)
+    m.set_pair_shift("force")
+    _check(o, m, 1e-5)
+    o.step(30)
+    g.step(30)
+    po_, vo, io, _ = o.state()
+    pg, vg, ig, _ = g.state()
+    assert np.abs(unwrapped(pg, ig, s.box) - unwrapped(po_, io, s.box)).max() < 1e-9
+    assert np.abs(vg - vo).max() < 1e-9
+    _check(o, g, 1e-8)
+    # back to the energy shift: the plain form again
+    g.set_pair_shift("energy")
+    o.set_shift_mode("energy")
+    _check(o, g, 1e-10)
+
+
+def test_shifted_force_errors(ljmd_mod):
+    print_case("shifted force: unknown mode, tree lists refused")
+    s = gen.make_lj_fluid(500, rho=0.8, T=1.0, seed=2)
+    g = ljmd_mod.System(s.box, s.pos, s.vel, s.type, 1, [(0, 0, 1.0, 1.0, 2.5)])
+    with pytest.raises(ljmd_mod.LjmdError) as e:
+        ljmd_mod._check(g._lib.ljmd_set_pair_shift(g._h, 2))
+    assert e.value.code == ljmd_mod.LJMD_E_INVAL
+    with pytest.raises(KeyError):
+        g.set_pair_shift("smooth")
+    g.set_pair_shift("force")
+    g.set_nlist("tree")
+    with pytest.raises(ljmd_mod.LjmdError) as e:
+        g.step(1)
+    assert e.value.code == ljmd_mod.LJMD_E_INVAL
