@@ -194,10 +194,10 @@ __device__ __forceinline__ void range_box(const BvhArgs &b, int i, int e, double
     }
 }
 
-// Each internal node stores the boxes of its two children (12 doubles: lo xyz, hi xyz of the
-// left child, then of the right one), so a walk reads one record per node it opens and tests
-// both children from it. A child's box is that of its leaf range: [rlo, rsplit] on the left,
-// [rsplit + 1, rhi] on the right (a leaf child's box is its build position, lo = hi).
+// Each internal node's record (BvhNode): per child, a leaf's exact build position or an
+// internal child's box rounded outwards to FP32, the box of its leaf range [rlo, rsplit] on
+// the left and [rsplit + 1, rhi] on the right; then the child codes. A walk reads one 64-byte
+// record per node it opens and tests both children from it.
 __global__ void __launch_bounds__(256) k_bvh_boxes(const BvhArgs b) {
     if (!bvh_go(b)) return;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -205,10 +205,29 @@ __global__ void __launch_bounds__(256) k_bvh_boxes(const BvhArgs b) {
     int s, e;
     bvh_type_range(b, g, s, e);
     if (g - s >= e - s - 1) return;  // the type's last leaf index has no internal node
-    double *bx = b.box + 12 * (size_t)g;
+    BvhNode nd;
+    nd.left = b.left[g];
+    nd.right = b.right[g];
+    nd.pad[0] = nd.pad[1] = 0;
     const int sp = b.rsplit[g];
-    range_box(b, b.rlo[g], sp, bx);
-    range_box(b, sp + 1, b.rhi[g], bx + 6);
+    const int code[2] = {nd.left, nd.right};
+    const int lo[2] = {b.rlo[g], sp + 1}, hi[2] = {sp, b.rhi[g]};
+    for (int u = 0; u < 2; ++u) {
+        if (code[u] & BVH_LEAF) {
+            const double4 x = b.xb[code[u] & ~BVH_LEAF];
+            nd.child[u].pos[0] = x.x;
+            nd.child[u].pos[1] = x.y;
+            nd.child[u].pos[2] = x.z;
+        } else {
+            double bx[6];
+            range_box(b, lo[u], hi[u], bx);
+            for (int a = 0; a < 3; ++a) {
+                nd.child[u].box[a] = __double2float_rd(bx[a]);
+                nd.child[u].box[3 + a] = __double2float_ru(bx[3 + a]);
+            }
+        }
+    }
+    b.node[g] = nd;
 }
 
 // Squared distance from q to a box (0 inside).
@@ -296,30 +315,38 @@ __global__ void __launch_bounds__(256) k_bvh_list(const BvhArgs b) {
                             }
                             continue;
                         }
+                        // the next node to open is kept in a register: a descent needs no stack
+                        // round trip; the right child waits on the stack while the left
+                        // subtree is walked (the same depth-first order as pushing both)
                         int top = 0;
-                        stack[top++] = root;
-                        while (top > 0) {
-                            const int c = stack[--top];
-                            const int ch[2] = {b.left[c], b.right[c]};
-                            const double *bx = b.box + 12 * (size_t)c;
-                            double cb[12];
-#pragma unroll
-                            for (int k = 0; k < 12; ++k) cb[k] = bx[k];
-                            // leaves are tested at once, in child order; internal children are
-                            // pushed right first, so the left subtree is walked first
+                        int c = root;
+                        while (true) {
+                            if (c < 0) {
+                                if (top == 0) break;
+                                c = stack[--top];
+                            }
+                            const BvhNode nd = b.node[c];
+                            const int ch[2] = {nd.left, nd.right};
+                            // leaves are tested at once, in child order
                             for (int u = 0; u < 2; ++u) {
                                 if (!(ch[u] & BVH_LEAF)) continue;
                                 const int j = ch[u] & ~BVH_LEAF;
                                 if (j == p) continue;
-                                try_leaf(xi, cb[6 * u], cb[6 * u + 1], cb[6 * u + 2], j, sx, sy,
-                                         sz, rl2, P, b, p, count);
+                                try_leaf(xi, nd.child[u].pos[0], nd.child[u].pos[1],
+                                         nd.child[u].pos[2], j, sx, sy, sz, rl2, P, b, p, count);
                             }
-                            for (int u = 1; u >= 0; --u) {
-                                if (ch[u] & BVH_LEAF) continue;
-                                const double lo[3] = {cb[6 * u], cb[6 * u + 1], cb[6 * u + 2]};
-                                const double hi[3] = {cb[6 * u + 3], cb[6 * u + 4], cb[6 * u + 5]};
-                                if (box_dist2(q, lo, hi) <= rl2_box && top < BVH_STACK)
-                                    stack[top++] = ch[u];
+                            bool go[2];
+                            for (int u = 0; u < 2; ++u) {
+                                const float *f = nd.child[u].box;
+                                const double lo[3] = {(double)f[0], (double)f[1], (double)f[2]};
+                                const double hi[3] = {(double)f[3], (double)f[4], (double)f[5]};
+                                go[u] = !(ch[u] & BVH_LEAF) && box_dist2(q, lo, hi) <= rl2_box;
+                            }
+                            if (go[0]) {
+                                if (go[1] && top < BVH_STACK) stack[top++] = ch[1];
+                                c = ch[0];
+                            } else {
+                                c = go[1] ? ch[1] : -1;
                             }
                         }
                     }

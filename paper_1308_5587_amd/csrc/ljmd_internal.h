@@ -238,6 +238,18 @@ struct RebuildArgs {
 // sorted order: the Karras construction on the keys (cell << 32 | index), the children's boxes
 // of every node from range reductions over box tables, and one traversal per particle and tree.
 constexpr int BVH_LEAF = 1 << 30;   // child code: a leaf (particle index | BVH_LEAF)
+// A tree node as a walk reads it, one 64-byte record per internal node: per child 24 bytes,
+// the exact build position (3 doubles) of a leaf child or the box of an internal child in
+// FP32 rounded outwards (lo x y z, hi x y z: the box only ever grows, so a walk never skips a
+// neighbour), then the two child codes.
+struct alignas(64) BvhNode {
+    union {
+        double pos[3];
+        float box[6];
+    } child[2];
+    int left, right;
+    int pad[2];
+};
 constexpr int BVH_STACK = 64;       // traversal stack (tree depth is at most the 64 key bits)
 struct BvhArgs {
     const RepParams *reps;
@@ -250,7 +262,7 @@ struct BvhArgs {
     int *rlo, *rsplit, *rhi; // internal node's leaves [rlo, rhi]; the left child's end rsplit
     double *blk;             // per 64 leaves (sorted order): their box, lo x y z, hi x y z
     double *sblk;            // per 4096 leaves: their box
-    double *box;             // 12 doubles per internal node: its children's boxes (lo, hi)
+    BvhNode *node;           // per internal node: what a walk reads
     const double *rl2_table; // list radii squared per type pair (0: pair disabled)
     int *nl_count;
     int32_t *nlist32;        // 32-bit sorted-order indices, 4 per 16-byte chunk (see slot32)

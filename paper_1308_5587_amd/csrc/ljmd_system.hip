@@ -96,7 +96,8 @@ struct ljmd_system {
     int ncs = 0;
     int *d_cell_of = nullptr, *d_bvh_left = nullptr, *d_bvh_right = nullptr,
         *d_bvh_rlo = nullptr, *d_bvh_rsplit = nullptr, *d_bvh_rhi = nullptr;
-    double *d_bvh_box = nullptr, *d_bvh_blk = nullptr, *d_bvh_sblk = nullptr;
+    BvhNode *d_bvh_node = nullptr;
+    double *d_bvh_blk = nullptr, *d_bvh_sblk = nullptr;
     int32_t *d_nlist32 = nullptr;
     size_t nlist32_alloc = 0;
     // NVT thermostat: device scalars (TH_*), their snapshot, kinetic-energy partials
@@ -312,8 +313,8 @@ int setup_table(ljmd_system *s) {
     return LJMD_OK;
 }
 
-// The tree method's node, box and cell arrays (n each; 12 box doubles per node; 6 per block of
-// 64 and of 4096 leaves).
+// The tree method's node, record and cell arrays (n each; 6 box doubles per block of 64 and
+// of 4096 leaves).
 int ensure_tree_arrays(ljmd_system *s) {
     if (s->d_cell_of) return LJMD_OK;
     const size_t N = (size_t)s->n;
@@ -323,7 +324,7 @@ int ensure_tree_arrays(ljmd_system *s) {
     CHK(dalloc_t(s, &s->d_bvh_rlo, N));
     CHK(dalloc_t(s, &s->d_bvh_rsplit, N));
     CHK(dalloc_t(s, &s->d_bvh_rhi, N));
-    CHK(dalloc_t(s, &s->d_bvh_box, 12 * N));
+    CHK(dalloc_t(s, &s->d_bvh_node, N));
     CHK(dalloc_t(s, &s->d_bvh_blk, 6 * ((N + 63) / 64)));
     CHK(dalloc_t(s, &s->d_bvh_sblk, 6 * ((N + 4095) / 4096)));
     return LJMD_OK;
@@ -435,7 +436,7 @@ BvhArgs bvh_args(ljmd_system *s, const int *go, int cur) {
     b.rhi = s->d_bvh_rhi;
     b.blk = s->d_bvh_blk;
     b.sblk = s->d_bvh_sblk;
-    b.box = s->d_bvh_box;
+    b.node = s->d_bvh_node;
     b.rl2_table = s->d_rl2;
     b.nl_count = s->d_count;
     b.nlist32 = s->d_nlist32;
