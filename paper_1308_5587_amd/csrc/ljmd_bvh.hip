@@ -280,7 +280,20 @@ __device__ __forceinline__ void try_leaf(const double4 &xi, double xjx, double x
 __global__ void __launch_bounds__(256) k_bvh_list(const BvhArgs b) {
     if (!bvh_go(b)) return;
     const RepParams &P = b.reps[0];
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // thread g takes the g-th particle of the types' ranges in type_order
+    int p = b.n;
+    {
+        int g = blockIdx.x * blockDim.x + threadIdx.x;
+        for (int k = 0; k < b.ntypes; ++k) {
+            const int t = b.type_order[k];
+            const int s = b.cell_start[t * b.ncs], e = b.cell_start[(t + 1) * b.ncs];
+            if (g < e - s) {
+                p = s + g;
+                break;
+            }
+            g -= e - s;
+        }
+    }
     int count = 0;
     if (p < b.n) {
         const double4 xi = b.xb[p];

@@ -268,6 +268,9 @@ struct BvhArgs {
     int32_t *nlist32;        // 32-bit sorted-order indices, 4 per 16-byte chunk (see slot32)
     DevStatus *st;
     int n, ntypes, ncs, npad, cap, lshift;
+    // the order in which the walk kernel's threads take the types' particle ranges: the
+    // types with the widest list radii (the longest walks) first, so they do not form a tail
+    int type_order[LJMD_MAX_TYPES_DEVICE];
 };
 
 // ---------------------------------------------------------------- launchers

@@ -447,6 +447,14 @@ BvhArgs bvh_args(ljmd_system *s, const int *go, int cur) {
     b.npad = s->npad;
     b.cap = s->cap;
     b.lshift = s->lshift;
+    // types by decreasing widest list radius (ties by index): the longest walks start first
+    const int nt = s->ntypes;
+    std::vector<double> widest(nt, 0.0);
+    for (int a = 0; a < nt; ++a)
+        for (int c = 0; c < nt; ++c) widest[a] = std::max(widest[a], s->rc[a * nt + c]);
+    for (int k = 0; k < nt; ++k) b.type_order[k] = k;
+    std::stable_sort(b.type_order, b.type_order + nt,
+                     [&](int x, int y) { return widest[x] > widest[y]; });
     return b;
 }
 
