@@ -367,7 +367,9 @@ __global__ void __launch_bounds__(256) k_bvh_list(const BvhArgs b) {
         b.nl_count[p] = count;
         if (count > b.cap) atomicOr(&b.st->status, ST_OVERFLOW);
     }
-    // build statistics, one atomic each per wavefront
+    // build statistics, reduced over the workgroup: one atomic add per workgroup, an atomic
+    // max only where its longest list beats the recorded one (atomics on one word from every
+    // wavefront serialise, and a wavefront retires only once its atomics are acknowledged)
     int mx = count;
     unsigned long long ent = (unsigned long long)(count < b.cap ? count : b.cap);
     for (int o = 32; o > 0; o >>= 1) {
@@ -375,9 +377,21 @@ __global__ void __launch_bounds__(256) k_bvh_list(const BvhArgs b) {
         mx = om > mx ? om : mx;
         ent += __shfl_xor(ent, o);
     }
-    if ((threadIdx.x & 63) == 0 && mx > 0) {
-        atomicMax(&b.st->max_count, mx);
-        atomicAdd(&b.st->entries, ent);
+    __shared__ int s_mx[4];
+    __shared__ unsigned long long s_ent[4];
+    if ((threadIdx.x & 63) == 0) {
+        s_mx[threadIdx.x >> 6] = mx;
+        s_ent[threadIdx.x >> 6] = ent;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            mx = s_mx[w] > mx ? s_mx[w] : mx;
+            ent += s_ent[w];
+        }
+        if (mx > __hip_atomic_load(&b.st->max_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&b.st->max_count, mx);
+        if (ent) atomicAdd(&b.st->entries, ent);
     }
 }
 

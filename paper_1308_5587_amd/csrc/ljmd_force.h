@@ -341,7 +341,10 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
         if (MODE == MODE_FUSED) {
             // all particles of the workgroup belong to one replica: one atomic per wavefront
             const unsigned long long vote = __ballot(exceed);
-            if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1)
+            // set once: a plain read first spares the atomic once another wavefront set it
+            if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1 &&
+                __hip_atomic_load(&a.req[2 * rep + (a.cur ^ 1)], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT) == 0)
                 atomicOr(&a.req[2 * rep + (a.cur ^ 1)], 1);
         }
     }

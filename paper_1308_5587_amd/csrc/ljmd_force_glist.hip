@@ -66,7 +66,8 @@ __global__ void __launch_bounds__(512) k_force_glist(const ForceArgs a) {
         a, P, q, 0, active, lane, false, xi, acc, ue, w0, w1, w2, w3, w4, w5);
     if (MODE == MODE_FUSED) {
         const unsigned long long vote = __ballot(exceed);
-        if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1)
+        if (exceed && (threadIdx.x & 63) == __ffsll((long long)vote) - 1 &&
+            __hip_atomic_load(&a.req[a.cur ^ 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
             atomicOr(&a.req[a.cur ^ 1], 1);
     }
 }

@@ -104,6 +104,8 @@ constexpr size_t LDS_MAX_BYTES = 160 * 1024;  // LDS of one workgroup on gfx950
 constexpr int TILE_INDEX_MAX = 65535; // 16-bit tile indices
 constexpr int FORCE_BATCH = 2;  // neighbour positions requested together (1, 2, 4, 8)
 constexpr int BUILD_BATCH = 2;  // candidate rounds tested together in the build
+constexpr int FLAT_ROUNDS = 12; // rounds of 64 candidates a wavefront-per-particle build item holds
+constexpr int FLAT_RING = 128;  // list entries a build wavefront holds before writing them out
 
 enum { MODE_EVAL = 0, MODE_FUSED = 1, MODE_FINAL = 2 };
 // Pair forms (one per system; the batch uses LJ). The PairCoef fields lj1..lj4 hold each

@@ -109,7 +109,11 @@ __global__ void __launch_bounds__(256) k_kick_drift(const KickDriftArgs a) {
             exceed = r2_canon(dx, dy, dz) >= P.lim2;
         }
     }
-    if (exceed) atomicOr(&a.req[2 * rep + (a.cur ^ 1)], 1);
+    // lanes may belong to different replicas; a plain read first spares the atomic once the
+    // request is set (nothing clears it during this kernel)
+    if (exceed && __hip_atomic_load(&a.req[2 * rep + (a.cur ^ 1)], __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) == 0)
+        atomicOr(&a.req[2 * rep + (a.cur ^ 1)], 1);
 }
 
 hipError_t launch_kick_drift(hipStream_t s, const KickDriftArgs &a) {
@@ -359,6 +363,47 @@ struct ColumnShift {
     double shz1, shz2;
 };
 
+// Writes entry k of particle q's list (nl_slot in closed form with the particle's part
+// precomputed). The round stride npad << sh fits 32 bits (the host keeps npad x 8 x lanes
+// < 2^32), so the slot is one 32 x 32 + 64-bit multiply-add; for a list of less than 4 GiB
+// with npad < 2^24 (narrow) it is a 24-bit multiply and 32-bit byte offsets from the list base.
+struct ListWriter {
+    uint16_t *nlist;
+    uint32_t npad, rstride, qb32, lmask;
+    uint64_t qbase;
+    int sh, narrow;
+    __device__ __forceinline__ ListWriter(const RebuildArgs &a, const BuildParams &P, int q) {
+        nlist = a.nlist;
+        sh = 3 + a.lshift;
+        npad = (uint32_t)a.npad;
+        rstride = npad << sh;
+        qbase = (uint64_t)q << sh;
+        qb32 = (uint32_t)q << sh;
+        lmask = (1u << sh) - 1u;
+        narrow = P.narrow;
+    }
+    // eight entries 8g .. 8g + 7 of a narrow list (consecutive slots within one chunk,
+    // 16-byte aligned)
+    __device__ __forceinline__ void store8_narrow(int g, const uint4 &v) const {
+        const uint32_t k = (uint32_t)g << 3;
+        const uint32_t e = __umul24(k >> sh, npad);
+        const uint32_t slot = (e << sh) + qb32 + (k & lmask);
+        *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(nlist) + (slot << 1)) = v;
+    }
+    __device__ __forceinline__ void operator()(int k, int v) const {
+        if (narrow) {
+            const uint32_t e = __umul24((uint32_t)k >> sh, npad);
+            const uint32_t slot = (e << sh) + qb32 + ((uint32_t)k & lmask);
+            *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(nlist) + (slot << 1)) =
+                (uint16_t)v;
+        } else {
+            const uint64_t slot =
+                (uint64_t)((uint32_t)k >> sh) * rstride + qbase + (size_t)((uint32_t)k & lmask);
+            nlist[slot] = (uint16_t)v;
+        }
+    }
+};
+
 // Candidates of one range of tile atoms (a stencil cell, or a column of them) for the
 // particles of a wavefront's groups: each group of Ln lanes takes Ln atoms of the range at a
 // time and appends the hits of its particle in lane order, so entries follow the tile order.
@@ -374,27 +419,7 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
                                                 const double4 &xi, int ti, int q, int self,
                                                 bool active, int Ln, int lane,
                                                 unsigned long long gmask, int &count) {
-    // list slots (nl_slot in closed form with the particle's part precomputed)
-    const int sh = 3 + a.lshift;
-    // the round stride npad << sh fits 32 bits (the host keeps npad x 8 x lanes < 2^32), so
-    // the slot is one 32 x 32 + 64-bit multiply-add; for a list of less than 4 GiB with
-    // npad < 2^24 (P.narrow) it is a 24-bit multiply and 32-bit byte offsets from the list base
-    const uint32_t rstride = (uint32_t)a.npad << sh;
-    const uint64_t qbase = (uint64_t)q << sh;
-    const uint32_t qb32 = (uint32_t)q << sh;
-    const uint32_t lmask = (1u << sh) - 1u;
-    char *const nl_bytes = reinterpret_cast<char *>(a.nlist);
-    auto store = [&](int k, int v) {
-        if (P.narrow) {
-            const uint32_t e = __umul24((uint32_t)k >> sh, (uint32_t)a.npad);
-            const uint32_t slot = (e << sh) + qb32 + ((uint32_t)k & lmask);
-            *reinterpret_cast<uint16_t *>(nl_bytes + (slot << 1)) = (uint16_t)v;
-        } else {
-            const uint64_t slot = (uint64_t)((uint32_t)k >> sh) * rstride + qbase +
-                                  (size_t)((uint32_t)k & lmask);
-            a.nlist[slot] = (uint16_t)v;
-        }
-    };
+    const ListWriter store(a, P, q);
     // BUILD_BATCH rounds of Ln candidates per iteration: their positions are read and their
     // distances tested before any append, so the LDS reads and FP64 chains of the rounds
     // overlap; the appends then run round by round, in the order of a plain loop
@@ -516,6 +541,123 @@ __device__ __forceinline__ void nlist_scan(const RebuildArgs &a, const double4 *
                                                   q, self, active, Ln, lane, gmask, count);
 }
 
+// A particle's list is complete: its count, its work-order key, the overflow flags and the
+// wavefront's build statistics (one lane per particle).
+__device__ __forceinline__ void finish_particle(const RebuildArgs &a, int rep, int first, int q,
+                                                int count, uint8_t *s_cnt, int &my_max,
+                                                unsigned long long &my_entries) {
+    a.nl_count[q] = count;
+    if (q - first < WORK_SORT_MAX) {
+        const int chunks = (count + 7) >> 3;  // 8-entry list chunks, the work order's key
+        s_cnt[q - first] = (uint8_t)(chunks < 255 ? chunks : 255);
+    }
+    if (count > a.cap) {
+        atomicOr(&a.st->status, ST_OVERFLOW);
+        if (a.rep_status) atomicOr(&a.rep_status[rep], ST_OVERFLOW);
+    }
+    my_max = count > my_max ? count : my_max;
+    my_entries += (unsigned long long)(count < a.cap ? count : a.cap);
+}
+
+// The tile range [o, e) of stencil column h0 (its cells h0, h0 + 1, h0 + 2: z below, level,
+// above) that a work item needs: all of it, or with the z-half split (half 0 or 1) without the
+// far half of the cell above or below.
+__device__ __forceinline__ void column_bounds(const TileSmem &t, const int *s_lo, int h0,
+                                              int half, int &o, int &e) {
+    o = __builtin_amdgcn_readfirstlane(t.off[h0]);
+    e = __builtin_amdgcn_readfirstlane(t.off[h0 + 3]);
+    if (half == 1) o += __builtin_amdgcn_readfirstlane(s_lo[h0]);
+    if (half == 0)
+        e = __builtin_amdgcn_readfirstlane(t.off[h0 + 2]) +
+            __builtin_amdgcn_readfirstlane(s_lo[h0 + 2]);
+}
+
+// One work item with a whole wavefront per particle. The item's nine column ranges laid end
+// to end are its particles' common candidate list, in the order the columns give one after
+// another; lane l holds its candidates l, l + 64, ... as tile byte offsets in registers. Each
+// of the item's particles then takes all 64 lanes over that list, 64 candidates a round, so the
+// ballot and the running count are the same on every lane (scalar registers). Hits go to the
+// wavefront's ring of FLAT_RING entries in LDS (entry k at k mod FLAT_RING); whole groups of
+// eight entries are written to the list with one 16-byte store per group, once 64 entries are
+// pending and when the particle is done, instead of one 2-byte store per hit and round. The
+// entries are those of the column-by-column scan, in the same order. Used for narrow lists
+// (32-bit byte offsets) and items whose stencil cells all lie in the primary image and whose
+// candidates fit FLAT_ROUNDS rounds.
+template <bool MULTI>
+__device__ __forceinline__ void nlist_item_flat(const RebuildArgs &a,
+                                                const double4 *__restrict__ st,
+                                                const double *s_rl2, const BuildParams &P,
+                                                const int (&co)[9], const int (&ce)[9], int M,
+                                                int own, int beg, int cnt, int first, int rep,
+                                                uint16_t *ring, uint8_t *s_cnt, int &my_max,
+                                                unsigned long long &my_entries) {
+    const int wl = threadIdx.x & 63;
+    int tab[FLAT_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < FLAT_ROUNDS; ++r) {
+        // candidate f of the list: column c's atom co[c] + (f - start of column c)
+        const int f = r * 64 + wl;
+        int d = co[0], pre = ce[0] - co[0];
+#pragma unroll
+        for (int c = 1; c < 9; ++c) {
+            d = f >= pre ? co[c] - pre : d;
+            pre += ce[c] - co[c];
+        }
+        // byte offset in the tile; past the end: any tile atom (never a hit)
+        tab[r] = (f < M ? f + d : own) * (int)sizeof(double4);
+    }
+    const char *const stb = reinterpret_cast<const char *>(st);
+    const uint4 *const ring8 = reinterpret_cast<const uint4 *>(ring);
+    // entries below the cap, in whole groups of eight: the list's allocation holds the cap
+    // rounded up to whole chunks, so a last partial group may carry stale ring entries past
+    // the count (never read)
+    const int cap8 = a.cap >> 3;
+    for (int p = 0; p < cnt; ++p) {
+        const double4 xi = st[own + p];
+        const int ti = MULTI ? (int)xi.w : 0;
+        const int self_b = (own + p) * (int)sizeof(double4);
+        const int q = beg + p;
+        const ListWriter list(a, P, q);
+        int count = 0, done = 0;  // entries found, groups of eight written (both uniform)
+        auto flush = [&](int g_end) {
+            const int g = done + wl;
+            if (g < g_end) list.store8_narrow(g, ring8[g & (FLAT_RING / 8 - 1)]);
+            done = __builtin_amdgcn_readfirstlane(g_end);
+        };
+        // the next round's candidates are read before this round's appends (LDS latency)
+        double4 pn = *reinterpret_cast<const double4 *>(stb + tab[0]);
+#pragma unroll
+        for (int r = 0; r < FLAT_ROUNDS; ++r) {
+            if (r * 64 >= M) break;
+            const double4 pj = pn;
+            if (r + 1 < FLAT_ROUNDS && (r + 1) * 64 < M)
+                pn = *reinterpret_cast<const double4 *>(stb + tab[r + 1 < FLAT_ROUNDS ? r + 1 : r]);
+            const double r2 = r2_canon(pj.x - xi.x, pj.y - xi.y, pj.z - xi.z);
+            const double rl2 = MULTI ? s_rl2[ti * P.ntypes + (int)pj.w] : P.rl2;
+            const bool hit = r * 64 + wl < M && tab[r] != self_b && r2 < rl2;
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit);
+            // every lane writes, without a branch: a hit to its entry's slot, the others to
+            // the slot of entry count + 64, which no pending entry holds (at most 64 + 7 are
+            // pending) and a later hit overwrites before it is written out
+            const int k = (int)__builtin_amdgcn_mbcnt_hi(
+                (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)count));
+            ring[(hit ? k : count + 64) & (FLAT_RING - 1)] =
+                (uint16_t)(tab[r] / (int)sizeof(double4));
+            count += __popcll(bal);
+            // at most 64 + 7 entries pending: the ring never wraps onto unwritten ones
+            if (__builtin_amdgcn_readfirstlane(count - (done << 3)) >= 64) {
+                const int g_end = count >> 3;
+                flush(g_end < cap8 ? g_end : cap8);
+            }
+        }
+        {
+            const int g_end = (count + 7) >> 3;
+            flush(g_end < cap8 ? g_end : cap8);
+        }
+        if (wl == 0) finish_particle(a, rep, first, q, count, s_cnt, my_max, my_entries);
+    }
+}
+
 // The cells of one brick, one wavefront per work item; STAGED selects candidate positions
 // from the LDS tile or, for a tile larger than the LDS allocation, from global memory. With
 // the z-half split (s_lo: each halo cell's lower-half count) a work item is one half of a
@@ -528,7 +670,7 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                                             const int *s_lo, const BrickInfo &bi,
                                             const double4 *__restrict__ st,
                                             const double *s_rl2, const BuildParams &P,
-                                            int first, uint16_t *s_cnt, int &my_max,
+                                            int first, uint16_t *s_ring, uint8_t *s_cnt, int &my_max,
                                             unsigned long long &my_entries) {
     const int hy = (bi.dims >> 4) & 15, hz = (bi.dims >> 8) & 15;
     const int fpk = a.cell_xyz[bi.first_cell];
@@ -568,6 +710,24 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
         if (cnt == 0) continue;
         const int beg = cbeg + pb;
         const int own = STAGED ? __builtin_amdgcn_readfirstlane(t.off[hc]) + pb : 0;
+        if (STAGED && !P.canonical) {
+            int co[9], ce[9], M = 0;
+            bool plain = true;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                const int h0 = ((lx + c / 3) * hy + (ly + c % 3)) * hz + lz;
+                plain = plain && __builtin_amdgcn_readfirstlane(t.shift[h0]) == 21 &&
+                        __builtin_amdgcn_readfirstlane(t.shift[h0 + 1]) == 21 &&
+                        __builtin_amdgcn_readfirstlane(t.shift[h0 + 2]) == 21;
+                column_bounds(t, s_lo, h0, half, co[c], ce[c]);
+                M += ce[c] - co[c];
+            }
+            if (plain && P.narrow && M <= FLAT_ROUNDS * 64) {
+                nlist_item_flat<MULTI>(a, st, s_rl2, P, co, ce, M, own, beg, cnt, first, bi.rep,
+                                       s_ring + wave * FLAT_RING, s_cnt, my_max, my_entries);
+                continue;
+            }
+        }
         int Ln = 64 / cnt;
         Ln = Ln < 1 ? 1 : (Ln > 32 ? 32 : Ln);
         const int G = 64 / Ln;
@@ -600,12 +760,8 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                         cz.shz1 = (double)(((code1 >> 4) & 3) - 1) * P.L[2];
                         cz.shz2 = (double)(((code2 >> 4) & 3) - 1) * P.L[2];
                     }
-                    int o = __builtin_amdgcn_readfirstlane(t.off[h0]);
-                    int e = __builtin_amdgcn_readfirstlane(t.off[h0 + 3]);
-                    if (half == 1) o += __builtin_amdgcn_readfirstlane(s_lo[h0]);
-                    if (half == 0)
-                        e = __builtin_amdgcn_readfirstlane(t.off[h0 + 2]) +
-                            __builtin_amdgcn_readfirstlane(s_lo[h0 + 2]);
+                    int o, e;
+                    column_bounds(t, s_lo, h0, half, o, e);
                     nlist_scan<MULTI, STAGED>(a, st, s_rl2, P, o, e - o, 0, code, cz, xi, ti, q,
                                               self, active, Ln, lane, gmask, count);
                 }
@@ -635,16 +791,8 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
                                               self, active, Ln, lane, gmask, count);
                 }
             }
-            if (active && lane == 0) {
-                a.nl_count[q] = count;
-                if (q - first < WORK_SORT_MAX) s_cnt[q - first] = (uint16_t)(count < 65535 ? count : 65535);
-                if (count > a.cap) {
-                    atomicOr(&a.st->status, ST_OVERFLOW);
-                    if (a.rep_status) atomicOr(&a.rep_status[bi.rep], ST_OVERFLOW);
-                }
-                my_max = count > my_max ? count : my_max;
-                my_entries += (unsigned long long)(count < a.cap ? count : a.cap);
-            }
+            if (active && lane == 0)
+                finish_particle(a, bi.rep, first, q, count, s_cnt, my_max, my_entries);
         }
     }
 }
@@ -669,7 +817,7 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
 // have lists of similar length. Any order gives the same results: a particle's sum does not
 // depend on the lanes it runs on.
 __device__ __forceinline__ void work_order(const RebuildArgs &a, int first, int natoms,
-                                           const uint16_t *s_cnt, int *s_bin) {
+                                           const uint8_t *s_cnt, int *s_bin) {
     if (natoms > WORK_SORT_MAX) {
         for (int p = threadIdx.x; p < natoms; p += blockDim.x) a.work[first + p] = (uint16_t)p;
         return;
@@ -677,8 +825,7 @@ __device__ __forceinline__ void work_order(const RebuildArgs &a, int first, int 
     for (int k = threadIdx.x; k < 256; k += blockDim.x) s_bin[k] = 0;
     __syncthreads();  // also: every count is in s_cnt
     for (int p = threadIdx.x; p < natoms; p += blockDim.x) {
-        const int chunks = (s_cnt[p] + 7) >> 3;
-        atomicAdd(&s_bin[255 - (chunks < 255 ? chunks : 255)], 1);
+        atomicAdd(&s_bin[255 - s_cnt[p]], 1);
     }
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -700,8 +847,7 @@ __device__ __forceinline__ void work_order(const RebuildArgs &a, int first, int 
     }
     __syncthreads();
     for (int p = threadIdx.x; p < natoms; p += blockDim.x) {
-        const int chunks = (s_cnt[p] + 7) >> 3;
-        const int at = atomicAdd(&s_bin[255 - (chunks < 255 ? chunks : 255)], 1);
+        const int at = atomicAdd(&s_bin[255 - s_cnt[p]], 1);
         a.work[first + at] = (uint16_t)p;
     }
 }
@@ -765,27 +911,52 @@ k_nlist(const RebuildArgs a) {
     const int wl = threadIdx.x & 63;
     int my_max = 0;
     unsigned long long my_entries = 0ull;
-    __shared__ uint16_t s_cnt[WORK_SORT_MAX];
-    __shared__ int s_bin[256];
+    __shared__ uint8_t s_cnt[WORK_SORT_MAX];
+    // the wavefronts' list rings during the scan (8 x FLAT_RING entries), then the work
+    // order's 256 bins
+    __shared__ uint4 s_share[8 * FLAT_RING * sizeof(uint16_t) / sizeof(uint4)];
+    static_assert(sizeof(s_share) >= 256 * sizeof(int), "bins fit the shared array");
+    uint16_t *s_ring = reinterpret_cast<uint16_t *>(s_share);
+    int *s_bin = reinterpret_cast<int *>(s_share);
     const int first = a.cell_start[bi.first_cell];
     const int natoms = a.cell_start[bi.first_cell + bi.ncell] - first;
     if (staged)
-        nlist_cells<MULTI, true>(a, t, a.cell_lo ? s_lo : nullptr, bi, st, s_rl2, U, first, s_cnt,
-                                 my_max, my_entries);
+        nlist_cells<MULTI, true>(a, t, a.cell_lo ? s_lo : nullptr, bi, st, s_rl2, U, first,
+                                 s_ring, s_cnt, my_max, my_entries);
     else
         nlist_cells<MULTI, false>(a, t, a.cell_lo ? s_lo : nullptr, bi, st, s_rl2, U, first,
-                                  s_cnt, my_max, my_entries);
+                                  s_ring, s_cnt, my_max, my_entries);
     work_order(a, first, natoms, s_cnt, s_bin);
 
-    // wavefront reductions of the build statistics, one atomic each per wavefront
+    // The build statistics, reduced over the wavefront, then over the workgroup, then one
+    // atomic add per workgroup, and an atomic max only where the workgroup's longest list is
+    // longer than the one recorded. Atomics on one word from every wavefront of the chip
+    // serialise, and a wavefront does not retire before its atomics are acknowledged: per
+    // wavefront they held the workgroup slots idle for most of the build.
     for (int o = 32; o > 0; o >>= 1) {
         const int om = __shfl_xor(my_max, o);
         my_max = om > my_max ? om : my_max;
         my_entries += __shfl_xor(my_entries, o);
     }
-    if (wl == 0 && my_max > 0) {
-        atomicMax(&a.st->max_count, my_max);
-        atomicAdd(&a.st->entries, my_entries);
+    __syncthreads();  // the work order is done with the shared array
+    int *s_wmax = reinterpret_cast<int *>(s_share);
+    unsigned long long *s_went = reinterpret_cast<unsigned long long *>(s_share) + 8;
+    const int wave = threadIdx.x >> 6;
+    if (wl == 0) {
+        s_wmax[wave] = my_max;
+        s_went[wave] = my_entries;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int mx = 0;
+        unsigned long long ent = 0ull;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            mx = s_wmax[w] > mx ? s_wmax[w] : mx;
+            ent += s_went[w];
+        }
+        if (mx > __hip_atomic_load(&a.st->max_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&a.st->max_count, mx);
+        if (ent) atomicAdd(&a.st->entries, ent);
     }
 }
 
