@@ -225,6 +225,26 @@ int ljmd_set_nlist(ljmd_system *sys, int32_t method);
 #define LJMD_SHIFT_FORCE 1
 int ljmd_set_pair_shift(ljmd_system *sys, int32_t mode);
 
+/* Thermodynamic samples during ljmd_step (Section "Python package": a run's system
+ * quantities followed over time). With period > 0, every step whose number (the step
+ * counter, see ljmd_get_state) is a positive multiple of period is sampled on the device,
+ * with no host round trip: the potential energy, the virial and the kinetic energy at that
+ * full step, reduced in FP64 in a fixed order into a ring of `capacity` rows that keeps the
+ * latest ones. In NVT runs K is the thermostat's, after its closing half step. Sampled runs
+ * launch their steps one by one instead of as graphs. period = 0 turns sampling off;
+ * (re)configuring clears the ring. Errors: INVAL (period < 0, capacity outside
+ * [1, LJMD_THERMO_MAX_ROWS] with period > 0). */
+#define LJMD_THERMO_MAX_ROWS 1048576
+int ljmd_set_thermo(ljmd_system *sys, int32_t period, int32_t capacity);
+
+/* The latest min(available, max_rows) samples, oldest first, LJMD_THERMO_COLS doubles a row:
+ * step, K, U, E = K + U, T = 2K / (3n - 3), P = (2K + W_xx + W_yy + W_zz) / (3V), and the
+ * virial (xx, xy, xz, yy, yz, zz). rows = NULL only returns the number available in *nrows.
+ * The caller owns rows (max_rows x LJMD_THERMO_COLS doubles). Errors: INVAL (null handle or
+ * nrows, max_rows < 0), DEVICE. */
+#define LJMD_THERMO_COLS 12
+int ljmd_get_thermo(ljmd_system *sys, double *rows, int32_t max_rows, int32_t *nrows);
+
 /* The current neighbour list as unordered tag pairs (i < j), 2 x count int32, sorted by
  * (i, j); pairs = NULL only returns the count. build_pos (n x 3, tag order, nullable)
  * receives the positions the list was built from. */
@@ -411,7 +431,13 @@ int ljmd_tuning_set(const ljmd_tuning_entry *entries, int32_t n);
 /* Thread-local message for the last non-zero status returned on this thread. */
 const char *ljmd_last_error(void);
 
-/* Library version string. */
+/* Library version string; a debug build (compiled with LJMD_DEBUG_CHECKS=1, loaded by the
+ * Python binding when the environment sets LJMD_DEBUG_CHECKS=1) says "debug checks". Such a
+ * build checks on the device that every particle's cell and sorted slot lie in its replica's
+ * range, that every list entry written or read lies in its brick's tile and every list slot
+ * in the list allocation, and that no force is taken at a position half the skin or more
+ * from the list's build position (a dangerous build); a failed check makes the call that
+ * next reads the device status return DEVICE with the check's code in the message. */
 const char *ljmd_version(void);
 
 #ifdef __cplusplus

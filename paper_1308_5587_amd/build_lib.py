@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libljmd.so")
+LIB_DEBUG = os.path.join(HERE, "libljmd_debug.so")  # LJMD_DEBUG_CHECKS=1: device checks
 SOURCES = ["ljmd_kernels.hip", "ljmd_force_lj.hip", "ljmd_force_mie.hip", "ljmd_force_gauss.hip",
            "ljmd_force_yukawa.hip", "ljmd_force_lj_sf.hip", "ljmd_force_mie_sf.hip",
            "ljmd_force_gauss_sf.hip", "ljmd_force_yukawa_sf.hip", "ljmd_force_glist.hip",
@@ -30,16 +31,18 @@ def _hipcc():
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    """Compile the sources into the in-tree libljmd.so."""
+def build(verbose: bool = False, debug: bool = False) -> str:
+    """Compile the sources into the in-tree libljmd.so, or with debug into libljmd_debug.so,
+    the same sources with the device checks of LJMD_DEBUG_CHECKS compiled in."""
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    objdir = os.path.join(HERE, "_build")
+    objdir = os.path.join(HERE, "_build_debug" if debug else "_build")
     os.makedirs(objdir, exist_ok=True)
     hipcc = _hipcc()
+    flags = HIPFLAGS + (["-DLJMD_DEBUG_CHECKS=1"] if debug else [])
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc, *HIPFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc, *flags, "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -49,7 +52,7 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
         objs = list(ex.map(compile_one, srcs))
-    out = LIB
+    out = LIB_DEBUG if debug else LIB
     tmp = out + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,4 +63,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, debug="--debug" in sys.argv[1:]))

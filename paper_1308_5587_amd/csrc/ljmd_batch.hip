@@ -424,6 +424,15 @@ int write_params(ljmd_batch *b, int s) {
 int read_status(ljmd_batch *b) {
     HIPCHK(hipMemcpyAsync(b->h_status.data(), b->d_rep_status, sizeof(int) * b->max_slots,
                           hipMemcpyDeviceToHost, b->stream));
+    if (LJMD_DEBUG_CHECKS) {
+        // the device checks of a debug build report through the batch's status block
+        DevStatus st{};
+        HIPCHK(hipMemcpyAsync(&st, b->d_st, sizeof st, hipMemcpyDeviceToHost, b->stream));
+        CHK(sync(b));
+        if (st.status & ST_DEBUG)
+            return set_err(LJMD_E_DEVICE, "device check %d failed (debug build)", st.debug);
+        return LJMD_OK;
+    }
     return sync(b);
 }
 

@@ -8,6 +8,12 @@
 
 namespace ljmd {
 
+// A failed check of a debug build: the status bit, and the code of the first failure.
+__device__ __forceinline__ void debug_fail(DevStatus *st, int code) {
+    atomicOr(&st->status, ST_DEBUG);
+    atomicCAS(&st->debug, 0, code);
+}
+
 // ---------------------------------------------------------------- arithmetic helpers
 
 // Minimum image of a coordinate difference d in (-L, L): subtract k L with k = rint(d/L).

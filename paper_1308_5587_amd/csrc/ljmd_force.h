@@ -240,6 +240,14 @@ __device__ __forceinline__ bool finish_particle(const ForceArgs &a, const RepPar
                 a.vel[q] = v;
                 if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
                 const double4 b_pre = a.xb[q];
+                if (LJMD_DEBUG_CHECKS) {
+                    // the forces were taken at xi: within half the skin of the list's build
+                    const double ox = mi_rint(xi.x - b_pre.x, L0, iL0);
+                    const double oy = mi_rint(xi.y - b_pre.y, L1, iL1);
+                    const double oz = mi_rint(xi.z - b_pre.z, L2, iL2);
+                    if (r2_canon(ox, oy, oz) >= P.lim2)
+                        debug_fail(reinterpret_cast<DevStatus *>(a.status), DBG_DANGEROUS);
+                }
                 const double ex = mi_rint(x.x - b_pre.x, L0, iL0);
                 const double ey = mi_rint(x.y - b_pre.y, L1, iL1);
                 const double ez = mi_rint(x.z - b_pre.z, L2, iL2);
@@ -307,6 +315,8 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                 for (int v = 0; v < FB; ++v) {
                     const int u = u0 + v;
                     pv[v] = k0 + u < cnt && e[u] < t.total;
+                    if (LJMD_DEBUG_CHECKS && k0 + u < cnt && e[u] >= t.total)
+                        debug_fail(reinterpret_cast<DevStatus *>(a.status), DBG_READ);
                     const int idx = pv[v] ? e[u] : 0;
                     pt[v] = 0;
                     if (STAGED) {

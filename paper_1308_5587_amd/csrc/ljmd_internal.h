@@ -30,7 +30,7 @@ struct DevStatus {
     int max_count;           // longest list seen at a build
     unsigned long long builds;
     unsigned long long entries;  // list entries written at the last build
-    int pad;
+    int debug;               // first failed check of a debug build (DBG_*), else 0
 };
 
 // Parameters of one replica (a single system is a batch of one). Replica r owns particles
@@ -53,7 +53,21 @@ struct RepParams {
                              // so the choice never depends on what shares a batch
 };
 
-enum { ST_OVERFLOW = 1, ST_NONFINITE = 2, ST_TILE = 4 };
+enum { ST_OVERFLOW = 1, ST_NONFINITE = 2, ST_TILE = 4, ST_DEBUG = 8 };
+
+// Debug builds (LJMD_DEBUG_CHECKS=1) check indices and capacities on the device; a failed
+// check sets ST_DEBUG and records its code (the first one), and the access is skipped.
+#ifndef LJMD_DEBUG_CHECKS
+#define LJMD_DEBUG_CHECKS 0
+#endif
+enum {
+    DBG_CELL = 1,       // a particle's cell outside its replica's cells (binning)
+    DBG_SCATTER = 2,    // a particle's sorted slot outside its replica's range
+    DBG_TILE = 3,       // a list entry written outside the brick's tile
+    DBG_SLOT = 4,       // a list slot outside the list allocation
+    DBG_READ = 5,       // a list entry read outside the brick's tile (force kernel)
+    DBG_DANGEROUS = 6,  // forces at a position half the skin or more from the list's build
+};
 
 // Bricks: aligned groups of up to 2 x 2 x 2 cells whose cells are consecutive in the cell
 // order. A brick's halo is every cell within one cell of it (up to 4 x 4 x 4 = 64 cells);
@@ -316,6 +330,7 @@ hipError_t launch_ke_partials(hipStream_t s, const double4 *vel, int poff, int n
 hipError_t launch_nvt_thermo(hipStream_t s, const double *partials, const NvtParams &p,
                              double *th);
 hipError_t launch_nvt_finalize(hipStream_t s, double4 *vel, int poff, int n, double *th);
+hipError_t launch_thermo_nvt_k(hipStream_t s, double *row, const double *th);
 hipError_t launch_negate_vel(hipStream_t s, double4 *vel, int poff, int n);
 hipError_t launch_unsort_vec(hipStream_t s, const double4 *src, const int4 *img, int poff,
                              int n, double *dst);

@@ -179,6 +179,10 @@ __global__ void __launch_bounds__(256) k_bin(const RebuildArgs a) {
             const int cz = cell_coord(x.z * P.inv_w[2], P.nc[2]);
             const int tcell = a.typed_cells ? (int)x.w * a.typed_cells : 0;
             r = a.cell_rank[P.coff + tcell + (cx * P.nc[1] + cy) * P.nc[2] + cz];
+            if (LJMD_DEBUG_CHECKS && (r < P.coff || r >= P.coff + P.ncell)) {
+                debug_fail(a.st, DBG_CELL);
+                r = -1;
+            }
             if (a.cell_lo) up = upper_half(x.z, P.inv_w[2], cz);
         }
     }
@@ -260,7 +264,15 @@ __global__ void __launch_bounds__(256) k_scatter(const RebuildArgs a) {
     if (!rebuilds(a, a.prep ? a.prep[q] : 0)) return;
     // perm holds 2 q + (upper z half): particle slots are below 2^26
     const int sl = a.slot[q];
-    a.perm[a.cell_start[a.key[q]] + (sl & 0x3FFFFFFF)] = (q << 1) | (sl >> 30);
+    const int dst = a.cell_start[a.key[q]] + (sl & 0x3FFFFFFF);
+    if (LJMD_DEBUG_CHECKS) {
+        const RepParams &P = a.reps[a.prep ? a.prep[q] : 0];
+        if (dst < P.poff || dst >= P.poff + P.n) {
+            debug_fail(a.st, DBG_SCATTER);
+            return;
+        }
+    }
+    a.perm[dst] = (q << 1) | (sl >> 30);
 }
 
 // Order each cell's members and gather their state into the new order. One workgroup of 64
@@ -338,6 +350,7 @@ struct BuildParams {
     double rl2;  // (r_cut + skin)^2 of pair (0,0)
     int canonical, ntypes;
     int narrow;  // npad < 2^24 and every list slot below 2^31 (byte offsets fit 32 bits)
+    int tile_total;  // atoms of the brick's tile (debug checks)
 };
 
 __device__ __forceinline__ double uniform_f64(double x) {
@@ -370,10 +383,13 @@ struct ColumnShift {
 struct ListWriter {
     uint16_t *nlist;
     uint32_t npad, rstride, qb32, lmask;
-    uint64_t qbase;
+    uint64_t qbase, limit;  // limit: slots of the allocation (debug checks)
     int sh, narrow;
+    DevStatus *st;
     __device__ __forceinline__ ListWriter(const RebuildArgs &a, const BuildParams &P, int q) {
         nlist = a.nlist;
+        st = a.st;
+        limit = (uint64_t)a.npad * (uint64_t)a.cap;
         sh = 3 + a.lshift;
         npad = (uint32_t)a.npad;
         rstride = npad << sh;
@@ -388,17 +404,29 @@ struct ListWriter {
         const uint32_t k = (uint32_t)g << 3;
         const uint32_t e = __umul24(k >> sh, npad);
         const uint32_t slot = (e << sh) + qb32 + (k & lmask);
+        if (LJMD_DEBUG_CHECKS && slot + 8 > limit) {
+            debug_fail(st, DBG_SLOT);
+            return;
+        }
         *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(nlist) + (slot << 1)) = v;
     }
     __device__ __forceinline__ void operator()(int k, int v) const {
         if (narrow) {
             const uint32_t e = __umul24((uint32_t)k >> sh, npad);
             const uint32_t slot = (e << sh) + qb32 + ((uint32_t)k & lmask);
+            if (LJMD_DEBUG_CHECKS && slot >= limit) {
+                debug_fail(st, DBG_SLOT);
+                return;
+            }
             *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(nlist) + (slot << 1)) =
                 (uint16_t)v;
         } else {
             const uint64_t slot =
                 (uint64_t)((uint32_t)k >> sh) * rstride + qbase + (size_t)((uint32_t)k & lmask);
+            if (LJMD_DEBUG_CHECKS && slot >= limit) {
+                debug_fail(st, DBG_SLOT);
+                return;
+            }
             nlist[slot] = (uint16_t)v;
         }
     }
@@ -473,6 +501,8 @@ __device__ __forceinline__ void nlist_scan_cell(const RebuildArgs &a,
 #pragma unroll
         for (int u = 0; u < BUILD_BATCH; ++u) {
             const bool hit = hv[u];
+            if (LJMD_DEBUG_CHECKS && hit && STAGED && o + ttv[u] >= P.tile_total)
+                debug_fail(a.st, DBG_TILE);
             if (SOLO) {
                 // one lane per particle: its hits are appended in order, no group prefix
                 if (hit) {
@@ -641,6 +671,8 @@ __device__ __forceinline__ void nlist_item_flat(const RebuildArgs &a,
             // pending) and a later hit overwrites before it is written out
             const int k = (int)__builtin_amdgcn_mbcnt_hi(
                 (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)count));
+            if (LJMD_DEBUG_CHECKS && hit && tab[r] / (int)sizeof(double4) >= P.tile_total)
+                debug_fail(a.st, DBG_TILE);
             ring[(hit ? k : count + 64) & (FLAT_RING - 1)] =
                 (uint16_t)(tab[r] / (int)sizeof(double4));
             count += __popcll(bal);
@@ -880,6 +912,7 @@ k_nlist(const RebuildArgs a) {
     tile_setup(bi, a.halo + (size_t)b * HALO_MAX, a.cell_start, t, a.cell_lo ? s_lo : nullptr,
                a.cell_lo);
     tile_save(t, a.tile_tab + (size_t)b * TILE_TAB);
+    U.tile_total = t.total;
     // the permuted state of the brick's particles becomes the main state and the new build
     // point (coalesced copy; tile staging below reads pos_scr, not pos)
     {
@@ -1155,6 +1188,17 @@ __global__ void __launch_bounds__(RED_BLOCK) k_nvt_thermo(const double *partials
     th[TH_ETAB] = eta;
 }
 
+// A thermo sample of an NVT step: its kinetic energy is the thermostat's, after the closing
+// half step (the stored velocities are scaled only when the next step opens).
+__global__ void k_thermo_nvt_k(double *row, const double *th) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) row[RED_QUANT - 1] = th[TH_K];
+}
+
+hipError_t launch_thermo_nvt_k(hipStream_t s, double *row, const double *th) {
+    hipLaunchKernelGGL(k_thermo_nvt_k, dim3(1), dim3(64), 0, s, row, th);
+    return hipGetLastError();
+}
+
 // End of a call: the stored velocities take the pending scale factor ...
 __global__ void k_nvt_scale(double4 *vel, int poff, int n, const double *th) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1265,7 +1309,7 @@ __global__ void k_fill_status(DevStatus *st) {
         st->max_count = 0;
         st->builds = 0ull;
         st->entries = 0ull;
-        st->pad = 0;
+        st->debug = 0;
     }
 }
 

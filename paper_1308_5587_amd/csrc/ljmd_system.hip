@@ -106,6 +106,12 @@ struct ljmd_system {
     double nvt_kT = 0.0, nvt_invQ = 0.0, nvt_g = 0.0;
     double *d_th = nullptr, *d_snap_th = nullptr, *d_kpart = nullptr;
     DevStatus *d_st = nullptr;
+    // thermodynamic samples (ljmd_set_thermo): U, W[6], K of every period-th step, reduced on
+    // the device into a ring of thermo_cap rows; the step of each row is kept on the host
+    int thermo_period = 0, thermo_cap = 0;
+    double *d_thermo = nullptr;
+    std::vector<int64_t> thermo_step;
+    int64_t thermo_written = 0;
     int cur = 0;
     bool list_valid = false, force_valid = false;
     int64_t steps = 0, overflow_retries = 0;
@@ -142,6 +148,8 @@ void drop_graphs(ljmd_system *s) {
 int sync_status(ljmd_system *s, DevStatus *out) {
     HIPCHK(hipMemcpyAsync(out, s->d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
+    if (out->status & ST_DEBUG)
+        return set_err(LJMD_E_DEVICE, "device check %d failed (debug build)", out->debug);
     return LJMD_OK;
 }
 
@@ -693,6 +701,27 @@ NvtParams nvt_params(ljmd_system *s, int np, bool begin_only) {
 }
 
 // The thermostat half step that opens the next step, from the stored velocities.
+// Whether the step that ends at absolute step number `step` is sampled.
+bool thermo_due(const ljmd_system *s, int64_t step) {
+    return s->thermo_period > 0 && step > 0 && step % s->thermo_period == 0;
+}
+
+// The sample of a full step whose per-particle energies and virials are in d_u and d_w: K
+// from the full-step kinetic energies of the fused step kernel (ke), else from the stored
+// velocities; with NVT, K is then replaced by the thermostat's kinetic energy after its
+// closing half step (the stored velocities still owe that half step's scaling).
+int enqueue_thermo_sample(ljmd_system *s, hipStream_t st, int64_t step, const double *ke) {
+    const int slot = (int)(s->thermo_written % s->thermo_cap);
+    double *row = s->d_thermo + (size_t)slot * RED_QUANT;
+    CHK(launch_chk(launch_reduce(st, s->d_u, s->d_w, ke, s->d_vel, 0, s->n, s->d_partials,
+                                 s->red_blocks, row),
+                   "thermo reduce"));
+    if (s->nvt) CHK(launch_chk(launch_thermo_nvt_k(st, row, s->d_th), "thermo K"));
+    s->thermo_step[slot] = step;
+    s->thermo_written += 1;
+    return LJMD_OK;
+}
+
 int enqueue_nvt_begin(ljmd_system *s, hipStream_t st) {
     int np = 0;
     CHK(launch_chk(launch_ke_partials(st, s->d_vel, 0, s->n, s->d_kpart, s->red_blocks, &np),
@@ -705,7 +734,9 @@ int enqueue_nvt_begin(ljmd_system *s, hipStream_t st) {
 // half step's scaling with the first kick and the drift, the gated rebuild, the forces and
 // second kick, then the kinetic energy and the thermostat (end half step, and the opening
 // half step of the next one).
-int enqueue_nvt_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_index) {
+// `sample` >= 0: the step number this unit completes, sampled into the thermo ring.
+int enqueue_nvt_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_index,
+                     int64_t sample) {
     KickDriftArgs ka = kick_drift_args(s, cur);
     ka.scale = s->d_th + TH_SPEND;  // TH_SPEND, TH_SB
     CHK(launch_chk(launch_kick_drift(st, ka), "kick-drift"));
@@ -715,19 +746,26 @@ int enqueue_nvt_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev
     if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index], st));
     CHK(launch_chk(launch_forces(s, st, fa, MODE_FINAL, false), "force"));
     if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index + 1], st));
+    // a sampled step: the energies and virials at the same positions (an evaluation that
+    // rewrites the same forces)
+    if (sample >= 0) CHK(launch_chk(launch_forces(s, st, fa, MODE_EVAL, true), "thermo eval"));
     int np = 0;
     CHK(launch_chk(launch_ke_partials(st, s->d_vel, 0, s->n, s->d_kpart, s->red_blocks, &np),
                    "kinetic energy"));
-    return launch_chk(launch_nvt_thermo(st, s->d_kpart, nvt_params(s, np, false), s->d_th),
-                      "thermostat");
+    CHK(launch_chk(launch_nvt_thermo(st, s->d_kpart, nvt_params(s, np, false), s->d_th),
+                   "thermostat"));
+    if (sample >= 0) CHK(enqueue_thermo_sample(s, st, sample, nullptr));
+    return LJMD_OK;
 }
 
-int enqueue_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_index) {
-    if (s->nvt) return enqueue_nvt_unit(s, st, cur, timed, ev_index);
+int enqueue_unit(ljmd_system *s, hipStream_t st, int cur, bool timed, int ev_index,
+                 int64_t sample = -1) {
+    if (s->nvt) return enqueue_nvt_unit(s, st, cur, timed, ev_index, sample);
     ForceArgs fa = force_args(s, cur);
     if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index], st));
-    CHK(launch_chk(launch_forces(s, st, fa, MODE_FUSED, false), "fused step"));
+    CHK(launch_chk(launch_forces(s, st, fa, MODE_FUSED, sample >= 0), "fused step"));
     if (timed) HIPCHK(hipEventRecord(s->ev[EV_PER_UNIT * ev_index + 1], st));
+    if (sample >= 0) CHK(enqueue_thermo_sample(s, st, sample, s->d_ke));
     hipEvent_t *rev = timed ? &s->ev[EV_PER_UNIT * ev_index + 2] : nullptr;
     return launch_chk(launch_list_rebuild(s, st, s->d_req + (cur ^ 1), cur ^ 1, rev), "rebuild");
 }
@@ -817,7 +855,8 @@ int run_nvt_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinit
         CHK(enqueue_nvt_begin(s, s->stream));
         s->nvt_ready = true;
     }
-    const bool use_graph = s->graph_steps > 0 && !s->timing;
+    // sampled runs launch step by step (a graph's steps have no fixed step numbers)
+    const bool use_graph = s->graph_steps > 0 && !s->timing && s->thermo_period == 0;
     if (s->timing) CHK(ensure_events(s, nsteps));
     int64_t done = 0;
     while (done < nsteps) {
@@ -826,7 +865,9 @@ int run_nvt_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinit
             HIPCHK(hipGraphLaunch(s->graph[s->cur], s->stream));
             done += s->graph_steps;
         } else {
-            CHK(enqueue_nvt_unit(s, s->stream, s->cur, s->timing, (int)done));
+            const int64_t step = s->steps + done + 1;
+            CHK(enqueue_nvt_unit(s, s->stream, s->cur, s->timing, (int)done,
+                                 thermo_due(s, step) ? step : -1));
             s->cur ^= 1;
             done += 1;
         }
@@ -855,7 +896,8 @@ int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
         CHK(launch_chk(launch_list_rebuild(s, s->stream, s->d_req + s->cur, s->cur), "rebuild"));
     }
     const int64_t units = nsteps - 1;
-    const bool use_graph = s->graph_steps > 0 && !s->timing;
+    // sampled runs launch step by step (a graph's steps have no fixed step numbers)
+    const bool use_graph = s->graph_steps > 0 && !s->timing && s->thermo_period == 0;
     if (s->timing) CHK(ensure_events(s, units));
     int64_t done = 0;
     while (done < units) {
@@ -864,13 +906,21 @@ int run_steps(ljmd_system *s, int64_t nsteps, bool *overflow, bool *nonfinite) {
             HIPCHK(hipGraphLaunch(s->graph[s->cur], s->stream));
             done += s->graph_steps;  // graph_steps is even: cur is unchanged
         } else {
-            CHK(enqueue_unit(s, s->stream, s->cur, s->timing, (int)done));
+            // the fused kernel of unit `done` completes step s->steps + done + 1
+            const int64_t step = s->steps + done + 1;
+            CHK(enqueue_unit(s, s->stream, s->cur, s->timing, (int)done,
+                             thermo_due(s, step) ? step : -1));
             s->cur ^= 1;
             done += 1;
         }
     }
     ForceArgs fa = force_args(s, s->cur);
+    const int64_t last = s->steps + nsteps;
     CHK(launch_chk(launch_forces(s, s->stream, fa, MODE_FINAL, false), "final"));
+    if (thermo_due(s, last)) {
+        CHK(launch_chk(launch_forces(s, s->stream, fa, MODE_EVAL, true), "thermo eval"));
+        CHK(enqueue_thermo_sample(s, s->stream, last, nullptr));
+    }
     DevStatus st{};
     CHK(sync_status(s, &st));
     if (s->timing) CHK(collect_timing(s, units));
@@ -957,7 +1007,9 @@ extern "C" {
 
 const char *ljmd_last_error(void) { return ljmd::g_last_error.c_str(); }
 
-const char *ljmd_version(void) { return "ljmd 0.2 (gfx950)"; }
+const char *ljmd_version(void) {
+    return LJMD_DEBUG_CHECKS ? "ljmd 0.2 (gfx950, debug checks)" : "ljmd 0.2 (gfx950)";
+}
 
 int ljmd_tuning_get(ljmd_tuning_entry *out, int32_t capacity, int32_t *count) {
     if (!count || capacity < 0 || (capacity > 0 && !out))
@@ -1239,13 +1291,16 @@ int ljmd_step(ljmd_system *s, int64_t nsteps) {
             s->nvt_ready = true;
         }
         CHK(snapshot(s));
+        const int64_t thermo0 = s->thermo_written;
         for (int attempt = 0;; ++attempt) {
             bool over = false, nonfin = false;
+            s->thermo_written = thermo0;  // a re-run rewrites the samples of the failed one
             CHK(run_steps(s, k, &over, &nonfin));
             if (nonfin) {
                 DevStatus st{};
                 CHK(sync_status(s, &st));
                 CHK(restore(s, cur0));
+                s->thermo_written = thermo0;
                 if (st.status & ST_TILE)
                     return set_err(LJMD_E_BOX, "a brick holds more than %d atoms in its halo "
                                                "cells; state restored", TILE_INDEX_MAX);
@@ -1418,6 +1473,62 @@ int ljmd_set_pair_shift(ljmd_system *s, int32_t mode) {
     s->table_dirty = true;  // coefficients change; the list radii do not
     s->force_valid = false;
     drop_graphs(s);
+    return LJMD_OK;
+}
+
+int ljmd_set_thermo(ljmd_system *s, int32_t period, int32_t capacity) {
+    if (!s) return set_err(LJMD_E_INVAL, "null handle");
+    if (period < 0) return set_err(LJMD_E_INVAL, "thermo period %d is negative", period);
+    if (period > 0 && (capacity < 1 || capacity > LJMD_THERMO_MAX_ROWS))
+        return set_err(LJMD_E_INVAL, "thermo capacity %d outside [1, %d]", capacity,
+                       LJMD_THERMO_MAX_ROWS);
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->d_thermo) dfree(s, s->d_thermo);
+    s->d_thermo = nullptr;
+    s->thermo_period = 0;
+    s->thermo_cap = 0;
+    s->thermo_written = 0;
+    s->thermo_step.clear();
+    if (period == 0) return LJMD_OK;
+    CHK(dalloc_t(s, &s->d_thermo, (size_t)capacity * RED_QUANT));
+    s->thermo_step.assign((size_t)capacity, 0);
+    s->thermo_period = period;
+    s->thermo_cap = capacity;
+    return LJMD_OK;
+}
+
+int ljmd_get_thermo(ljmd_system *s, double *rows, int32_t max_rows, int32_t *nrows) {
+    if (!s || !nrows) return set_err(LJMD_E_INVAL, "null argument");
+    const int avail = (int)std::min<int64_t>(s->thermo_written, s->thermo_cap);
+    if (!rows) {
+        *nrows = avail;
+        return LJMD_OK;
+    }
+    if (max_rows < 0) return set_err(LJMD_E_INVAL, "max_rows %d is negative", max_rows);
+    const int take = std::min(avail, (int)max_rows);
+    *nrows = take;
+    if (take == 0) return LJMD_OK;
+    std::vector<double> raw((size_t)s->thermo_cap * RED_QUANT);
+    HIPCHK(hipMemcpyAsync(raw.data(), s->d_thermo, raw.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const double vol = s->L[0] * s->L[1] * s->L[2];
+    const double ndof = 3.0 * (double)s->n - 3.0;
+    for (int r = 0; r < take; ++r) {
+        // the most recent `take` samples, oldest first
+        const int64_t idx = s->thermo_written - take + r;
+        const int slot = (int)(idx % s->thermo_cap);
+        const double *q = raw.data() + (size_t)slot * RED_QUANT;  // U, W[6], K
+        double *o = rows + (size_t)r * LJMD_THERMO_COLS;
+        const double U = q[0], K = q[7];
+        o[0] = (double)s->thermo_step[slot];
+        o[1] = K;
+        o[2] = U;
+        o[3] = K + U;
+        o[4] = ndof > 0.0 ? 2.0 * K / ndof : 0.0;
+        o[5] = (2.0 * K + q[1] + q[4] + q[6]) / (3.0 * vol);
+        for (int c = 0; c < 6; ++c) o[6 + c] = q[1 + c];
+    }
     return LJMD_OK;
 }
 

@@ -16,6 +16,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libljmd.so")
+# the same sources built with the device checks of LJMD_DEBUG_CHECKS (build_lib, debug=True),
+# loaded instead when the environment sets LJMD_DEBUG_CHECKS=1
+LIB_DEBUG_PATH = os.path.join(HERE, "libljmd_debug.so")
 
 LJMD_OK = 0
 LJMD_E_INVAL = -1
@@ -97,7 +100,7 @@ EXPORTED = [
     "ljmd_get_forces", "ljmd_get_energy", "ljmd_get_virial", "ljmd_get_per_particle",
     "ljmd_get_state", "ljmd_set_state", "ljmd_get_neighbor_pairs", "ljmd_get_neighbor_list",
     "ljmd_get_stats", "ljmd_set_nlist", "ljmd_set_pair_shift", "ljmd_set_nvt", "ljmd_set_nve", "ljmd_get_thermostat",
-    "ljmd_set_thermostat", "ljmd_negate_velocities",
+    "ljmd_set_thermostat", "ljmd_negate_velocities", "ljmd_set_thermo", "ljmd_get_thermo",
     "ljmd_set_kernel_timing", "ljmd_kernel_time", "ljmd_kernel_durations", "ljmd_last_error", "ljmd_version",
     "ljmd_batch_create", "ljmd_batch_destroy", "ljmd_batch_footprint", "ljmd_batch_admit",
     "ljmd_batch_run_block", "ljmd_batch_poll", "ljmd_batch_read", "ljmd_batch_slot_steps",
@@ -106,11 +109,14 @@ EXPORTED = [
 ]
 
 
-def load(path: str = LIB_PATH):
-    """Load libljmd.so; raises if it has not been built."""
+def load(path: str | None = None):
+    """Load libljmd.so (libljmd_debug.so when LJMD_DEBUG_CHECKS=1); raises if it has not been
+    built. A process keeps the first library it loads."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = LIB_DEBUG_PATH if os.environ.get("LJMD_DEBUG_CHECKS") == "1" else LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with paper_1308_5587_amd.build_lib.build()")
     lib = C.CDLL(path)
@@ -137,6 +143,8 @@ def load(path: str = LIB_PATH):
         "ljmd_set_nve": ([vp], C.c_int),
         "ljmd_get_thermostat": ([vp, dp, dp, dp], C.c_int),
         "ljmd_set_thermostat": ([vp, C.c_double, C.c_double], C.c_int),
+        "ljmd_set_thermo": ([vp, C.c_int32, C.c_int32], C.c_int),
+        "ljmd_get_thermo": ([vp, dp, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
         "ljmd_negate_velocities": ([vp], C.c_int),
         "ljmd_set_kernel_timing": ([vp, C.c_int32], C.c_int),
         "ljmd_kernel_time": ([vp, lp, dp], C.c_int),
@@ -371,6 +379,23 @@ class System:
 
     def negate_velocities(self):
         _check(self._lib.ljmd_negate_velocities(self._h))
+
+    THERMO_COLUMNS = ("step", "K", "U", "E", "T", "P", "Wxx", "Wxy", "Wxz", "Wyy", "Wyz", "Wzz")
+
+    def set_thermo(self, period, capacity=1024):
+        """Sample (step, K, U, E, T, P, W) every `period` steps into a device ring of
+        `capacity` rows (period 0: off)."""
+        _check(self._lib.ljmd_set_thermo(self._h, int(period), int(capacity)))
+
+    def thermo(self, max_rows=None):
+        """The latest samples, oldest first: an array of rows with THERMO_COLUMNS."""
+        n = C.c_int32(0)
+        _check(self._lib.ljmd_get_thermo(self._h, None, 0, C.byref(n)))
+        k = n.value if max_rows is None else min(n.value, int(max_rows))
+        out = np.zeros((k, len(self.THERMO_COLUMNS)))
+        if k:
+            _check(self._lib.ljmd_get_thermo(self._h, _dp(out), k, C.byref(n)))
+        return out[: n.value]
 
     def neighbor_list(self):
         """The full list: (counts[n], neighbours[total]) with rows in tag order and each
