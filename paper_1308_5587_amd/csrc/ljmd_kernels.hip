@@ -602,17 +602,51 @@ __device__ __forceinline__ void column_bounds(const TileSmem &t, const int *s_lo
             __builtin_amdgcn_readfirstlane(s_lo[h0 + 2]);
 }
 
+// One particle's list built by a whole wavefront, 64 candidates a round: the ballot and the
+// running count are the same on every lane (scalar registers). Hits go to the wavefront's ring
+// of FLAT_RING entries in LDS (entry k at k mod FLAT_RING); whole groups of eight entries are
+// written to the list with one 16-byte store per group, once 64 entries are pending and when
+// the particle is done, instead of one 2-byte store per hit and round. Narrow lists only
+// (32-bit byte offsets).
+struct RingList {
+    const ListWriter list;
+    uint16_t *ring;
+    int cap8;             // whole groups of eight below the cap
+    int count = 0;        // entries found (uniform)
+    int done = 0;         // groups of eight written (uniform)
+    __device__ __forceinline__ RingList(const RebuildArgs &a, const BuildParams &P, int q,
+                                        uint16_t *ring_)
+        : list(a, P, q), ring(ring_), cap8(a.cap >> 3) {}
+    // groups [done, g_end) of the ring to the list, one lane per group. The list's allocation
+    // holds the cap rounded up to whole chunks, so a last partial group may carry stale ring
+    // entries past the count (never read).
+    __device__ __forceinline__ void flush(int g_end, int wl) {
+        g_end = g_end < cap8 ? g_end : cap8;
+        const int g = done + wl;
+        if (g < g_end)
+            list.store8_narrow(g, reinterpret_cast<const uint4 *>(ring)[g & (FLAT_RING / 8 - 1)]);
+        done = __builtin_amdgcn_readfirstlane(g_end);
+    }
+    // one round: every lane writes, without a branch, a hit to its entry's slot and the others
+    // to the slot of entry count + 64, which no pending entry holds (at most 64 + 7 are
+    // pending) and a later hit overwrites before it is written out
+    __device__ __forceinline__ void round(bool hit, int value, int wl) {
+        const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit);
+        const int k = (int)__builtin_amdgcn_mbcnt_hi(
+            (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)count));
+        ring[(hit ? k : count + 64) & (FLAT_RING - 1)] = (uint16_t)value;
+        count += __popcll(bal);
+        if (__builtin_amdgcn_readfirstlane(count - (done << 3)) >= 64) flush(count >> 3, wl);
+    }
+    __device__ __forceinline__ void finish(int wl) { flush((count + 7) >> 3, wl); }
+};
+
 // One work item with a whole wavefront per particle. The item's nine column ranges laid end
 // to end are its particles' common candidate list, in the order the columns give one after
-// another; lane l holds its candidates l, l + 64, ... as tile byte offsets in registers. Each
-// of the item's particles then takes all 64 lanes over that list, 64 candidates a round, so the
-// ballot and the running count are the same on every lane (scalar registers). Hits go to the
-// wavefront's ring of FLAT_RING entries in LDS (entry k at k mod FLAT_RING); whole groups of
-// eight entries are written to the list with one 16-byte store per group, once 64 entries are
-// pending and when the particle is done, instead of one 2-byte store per hit and round. The
-// entries are those of the column-by-column scan, in the same order. Used for narrow lists
-// (32-bit byte offsets) and items whose stencil cells all lie in the primary image and whose
-// candidates fit FLAT_ROUNDS rounds.
+// another; lane l holds its candidates l, l + 64, ... as tile byte offsets in registers, and
+// each of the item's particles takes all 64 lanes over that list (RingList). The entries are
+// those of the column-by-column scan, in the same order. Used for narrow lists and items whose
+// stencil cells all lie in the primary image and whose candidates fit FLAT_ROUNDS rounds.
 template <bool MULTI>
 __device__ __forceinline__ void nlist_item_flat(const RebuildArgs &a,
                                                 const double4 *__restrict__ st,
@@ -637,23 +671,12 @@ __device__ __forceinline__ void nlist_item_flat(const RebuildArgs &a,
         tab[r] = (f < M ? f + d : own) * (int)sizeof(double4);
     }
     const char *const stb = reinterpret_cast<const char *>(st);
-    const uint4 *const ring8 = reinterpret_cast<const uint4 *>(ring);
-    // entries below the cap, in whole groups of eight: the list's allocation holds the cap
-    // rounded up to whole chunks, so a last partial group may carry stale ring entries past
-    // the count (never read)
-    const int cap8 = a.cap >> 3;
     for (int p = 0; p < cnt; ++p) {
         const double4 xi = st[own + p];
         const int ti = MULTI ? (int)xi.w : 0;
         const int self_b = (own + p) * (int)sizeof(double4);
         const int q = beg + p;
-        const ListWriter list(a, P, q);
-        int count = 0, done = 0;  // entries found, groups of eight written (both uniform)
-        auto flush = [&](int g_end) {
-            const int g = done + wl;
-            if (g < g_end) list.store8_narrow(g, ring8[g & (FLAT_RING / 8 - 1)]);
-            done = __builtin_amdgcn_readfirstlane(g_end);
-        };
+        RingList rl(a, P, q, ring);
         // the next round's candidates are read before this round's appends (LDS latency)
         double4 pn = *reinterpret_cast<const double4 *>(stb + tab[0]);
 #pragma unroll
@@ -665,28 +688,63 @@ __device__ __forceinline__ void nlist_item_flat(const RebuildArgs &a,
             const double r2 = r2_canon(pj.x - xi.x, pj.y - xi.y, pj.z - xi.z);
             const double rl2 = MULTI ? s_rl2[ti * P.ntypes + (int)pj.w] : P.rl2;
             const bool hit = r * 64 + wl < M && tab[r] != self_b && r2 < rl2;
-            const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit);
-            // every lane writes, without a branch: a hit to its entry's slot, the others to
-            // the slot of entry count + 64, which no pending entry holds (at most 64 + 7 are
-            // pending) and a later hit overwrites before it is written out
-            const int k = (int)__builtin_amdgcn_mbcnt_hi(
-                (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)count));
-            if (LJMD_DEBUG_CHECKS && hit && tab[r] / (int)sizeof(double4) >= P.tile_total)
-                debug_fail(a.st, DBG_TILE);
-            ring[(hit ? k : count + 64) & (FLAT_RING - 1)] =
-                (uint16_t)(tab[r] / (int)sizeof(double4));
-            count += __popcll(bal);
-            // at most 64 + 7 entries pending: the ring never wraps onto unwritten ones
-            if (__builtin_amdgcn_readfirstlane(count - (done << 3)) >= 64) {
-                const int g_end = count >> 3;
-                flush(g_end < cap8 ? g_end : cap8);
+            const int j = tab[r] / (int)sizeof(double4);
+            if (LJMD_DEBUG_CHECKS && hit && j >= P.tile_total) debug_fail(a.st, DBG_TILE);
+            rl.round(hit, j, wl);
+        }
+        rl.finish(wl);
+        if (wl == 0) finish_particle(a, rep, first, q, rl.count, s_cnt, my_max, my_entries);
+    }
+}
+
+// A brick of a box too small for the stencil's fixed images (fewer than three cells on some
+// axis): every particle's candidates are the brick's whole tile, in tile order, with the
+// branch-form minimum image, as the cell-by-cell scan takes them. The wavefronts take the
+// brick's particles in turn, each with the whole wavefront (RingList), so a brick of many
+// particles is spread over all of them instead of one wavefront per cell.
+template <bool MULTI>
+__device__ __forceinline__ void nlist_brick_whole(const RebuildArgs &a, const TileSmem &t,
+                                                  const BrickInfo &bi,
+                                                  const double4 *__restrict__ st,
+                                                  const double *s_rl2, const BuildParams &P,
+                                                  int first, uint16_t *ring, uint8_t *s_cnt,
+                                                  int &my_max, unsigned long long &my_entries) {
+    const int wl = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwave = blockDim.x >> 6;
+    const int total = t.total;
+    const int R = (total + 63) >> 6;
+    for (int ci = 0; ci < bi.ncell; ++ci) {
+        const int rank = bi.first_cell + ci;
+        const int cbeg = __builtin_amdgcn_readfirstlane(a.cell_start[rank]);
+        const int ccnt = __builtin_amdgcn_readfirstlane(a.cell_start[rank + 1]) - cbeg;
+        if (ccnt == 0) continue;
+        // the cell as a halo cell: the one holding its range
+        int hc = 0;
+        for (int h = 0; h < t.nhalo; ++h)
+            if (t.start[h] == cbeg && t.off[h + 1] - t.off[h] == ccnt) hc = h;
+        const int own = __builtin_amdgcn_readfirstlane(t.off[hc]);
+        for (int p = wave; p < ccnt; p += nwave) {
+            const int self = own + p;
+            const double4 xi = st[self];
+            const int ti = MULTI ? (int)xi.w : 0;
+            const int q = cbeg + p;
+            RingList rl(a, P, q, ring);
+            double4 pn = st[wl < total ? wl : total - 1];
+            for (int r = 0; r < R; ++r) {
+                const int j = r * 64 + wl;
+                const double4 pj = pn;
+                if (r + 1 < R) pn = st[j + 64 < total ? j + 64 : total - 1];
+                const double dx = mi_branch(pj.x - xi.x, P.L[0]);
+                const double dy = mi_branch(pj.y - xi.y, P.L[1]);
+                const double dz = mi_branch(pj.z - xi.z, P.L[2]);
+                const double r2 = r2_canon(dx, dy, dz);
+                const double rl2 = MULTI ? s_rl2[ti * P.ntypes + (int)pj.w] : P.rl2;
+                rl.round(j < total && j != self && r2 < rl2, j, wl);
             }
+            rl.finish(wl);
+            if (wl == 0) finish_particle(a, bi.rep, first, q, rl.count, s_cnt, my_max, my_entries);
         }
-        {
-            const int g_end = (count + 7) >> 3;
-            flush(g_end < cap8 ? g_end : cap8);
-        }
-        if (wl == 0) finish_particle(a, rep, first, q, count, s_cnt, my_max, my_entries);
     }
 }
 
@@ -717,6 +775,11 @@ __device__ __forceinline__ void nlist_cells(const RebuildArgs &a, const TileSmem
     // ranges of an item's particles, and each range costs a fixed setup. The list is the
     // same either way: a split only skips atoms beyond the list radius, and entries keep the
     // tile order within each column
+    if (STAGED && P.canonical && P.narrow) {
+        nlist_brick_whole<MULTI>(a, t, bi, st, s_rl2, P, first, s_ring + wave * FLAT_RING,
+                                 s_cnt, my_max, my_entries);
+        return;
+    }
     const bool split = s_lo != nullptr && a.split_halves && !P.canonical && bi.ncell < nwave;
     const int nitem = split ? 2 * bi.ncell : bi.ncell;
     for (int it = wave; it < nitem; it += nwave) {
