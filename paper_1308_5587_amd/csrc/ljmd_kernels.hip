@@ -644,9 +644,11 @@ struct RingList {
 // One work item with a whole wavefront per particle. The item's nine column ranges laid end
 // to end are its particles' common candidate list, in the order the columns give one after
 // another; lane l holds its candidates l, l + 64, ... as tile byte offsets in registers, and
-// each of the item's particles takes all 64 lanes over that list (RingList). The entries are
-// those of the column-by-column scan, in the same order. Used for narrow lists and items whose
-// stencil cells all lie in the primary image and whose candidates fit FLAT_ROUNDS rounds.
+// each of the item's particles takes all 64 lanes over that list, appending through the
+// wavefront's ring as RingList does (written out inline here: the list build's hottest loop).
+// The entries are those of the column-by-column scan, in the same order. Used for narrow lists
+// and items whose stencil cells all lie in the primary image and whose candidates fit
+// FLAT_ROUNDS rounds.
 template <bool MULTI>
 __device__ __forceinline__ void nlist_item_flat(const RebuildArgs &a,
                                                 const double4 *__restrict__ st,
@@ -671,12 +673,23 @@ __device__ __forceinline__ void nlist_item_flat(const RebuildArgs &a,
         tab[r] = (f < M ? f + d : own) * (int)sizeof(double4);
     }
     const char *const stb = reinterpret_cast<const char *>(st);
+    const uint4 *const ring8 = reinterpret_cast<const uint4 *>(ring);
+    // entries below the cap, in whole groups of eight: the list's allocation holds the cap
+    // rounded up to whole chunks, so a last partial group may carry stale ring entries past
+    // the count (never read)
+    const int cap8 = a.cap >> 3;
     for (int p = 0; p < cnt; ++p) {
         const double4 xi = st[own + p];
         const int ti = MULTI ? (int)xi.w : 0;
         const int self_b = (own + p) * (int)sizeof(double4);
         const int q = beg + p;
-        RingList rl(a, P, q, ring);
+        const ListWriter list(a, P, q);
+        int count = 0, done = 0;  // entries found, groups of eight written (both uniform)
+        auto flush = [&](int g_end) {
+            const int g = done + wl;
+            if (g < g_end) list.store8_narrow(g, ring8[g & (FLAT_RING / 8 - 1)]);
+            done = __builtin_amdgcn_readfirstlane(g_end);
+        };
         // the next round's candidates are read before this round's appends (LDS latency)
         double4 pn = *reinterpret_cast<const double4 *>(stb + tab[0]);
 #pragma unroll
@@ -688,12 +701,28 @@ __device__ __forceinline__ void nlist_item_flat(const RebuildArgs &a,
             const double r2 = r2_canon(pj.x - xi.x, pj.y - xi.y, pj.z - xi.z);
             const double rl2 = MULTI ? s_rl2[ti * P.ntypes + (int)pj.w] : P.rl2;
             const bool hit = r * 64 + wl < M && tab[r] != self_b && r2 < rl2;
-            const int j = tab[r] / (int)sizeof(double4);
-            if (LJMD_DEBUG_CHECKS && hit && j >= P.tile_total) debug_fail(a.st, DBG_TILE);
-            rl.round(hit, j, wl);
+            const unsigned long long bal = __builtin_amdgcn_ballot_w64(hit);
+            // every lane writes, without a branch: a hit to its entry's slot, the others to
+            // the slot of entry count + 64, which no pending entry holds (at most 64 + 7 are
+            // pending) and a later hit overwrites before it is written out
+            const int k = (int)__builtin_amdgcn_mbcnt_hi(
+                (unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, (unsigned)count));
+            if (LJMD_DEBUG_CHECKS && hit && tab[r] / (int)sizeof(double4) >= P.tile_total)
+                debug_fail(a.st, DBG_TILE);
+            ring[(hit ? k : count + 64) & (FLAT_RING - 1)] =
+                (uint16_t)(tab[r] / (int)sizeof(double4));
+            count += __popcll(bal);
+            // at most 64 + 7 entries pending: the ring never wraps onto unwritten ones
+            if (__builtin_amdgcn_readfirstlane(count - (done << 3)) >= 64) {
+                const int g_end = count >> 3;
+                flush(g_end < cap8 ? g_end : cap8);
+            }
         }
-        rl.finish(wl);
-        if (wl == 0) finish_particle(a, rep, first, q, rl.count, s_cnt, my_max, my_entries);
+        {
+            const int g_end = (count + 7) >> 3;
+            flush(g_end < cap8 ? g_end : cap8);
+        }
+        if (wl == 0) finish_particle(a, rep, first, q, count, s_cnt, my_max, my_entries);
     }
 }
 
