@@ -338,7 +338,9 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                     const double dx = (MIF & 1) ? px[v] - xc.x : mi_rint(px[v] - xc.x, L0, iL0);
                     const double dy = (MIF & 2) ? py[v] - xc.y : mi_rint(py[v] - xc.y, L1, iL1);
                     const double dz = (MIF & 4) ? pz[v] - xc.z : mi_rint(pz[v] - xc.z, L2, iL2);
-                    const double r2 = r2_canon(dx, dy, dz);
+                    // fused: the force kernel's r^2 may differ from the canonical one by a
+                    // rounding (the list decision stays canonical in the build)
+                    const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
                     const PairCoef &c = MULTI ? s_pair[ti * P.ntypes + pt[v]] : single;
                     if (pv[v] && r2 < c.rc2)
                         pair_term<STYLE, PREC, ENERGY>(c, dx, dy, dz, r2, acc, ue, w0, w1, w2, w3, w4, w5);

@@ -55,7 +55,8 @@ __global__ void __launch_bounds__(512) k_force_glist(const ForceArgs a) {
             const double dx = mi_rint(px[u] - xi.x, L0, iL0);
             const double dy = mi_rint(py[u] - xi.y, L1, iL1);
             const double dz = mi_rint(pz[u] - xi.z, L2, iL2);
-            const double r2 = r2_canon(dx, dy, dz);
+            // fused, as in the cell-list force kernel (the list decision stays canonical)
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
             const PairCoef &c = MULTI ? s_pair[ti * P.ntypes + pt[u]] : single;
             if (pv[u] && r2 < c.rc2)
                 pair_term<STYLE_LJ, PREC, ENERGY>(c, dx, dy, dz, r2, acc, ue, w0, w1, w2, w3, w4,
