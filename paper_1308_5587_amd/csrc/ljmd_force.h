@@ -304,8 +304,12 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
                               (cur.y >> 16) & 0xffff, cur.z & 0xffff, (cur.z >> 16) & 0xffff,
                               cur.w & 0xffff, (cur.w >> 16) & 0xffff};
             // entries in groups of FB: all neighbour positions of the group are requested
-            // first, then the arithmetic runs on them
+            // first, then the arithmetic runs on them. The builder writes only tile indices;
+            // an entry is clamped to the tile (not tested against it) so that the read stays
+            // inside the tile whatever the word holds: one compare and one clamp per entry.
             constexpr int FB = FORCE_BATCH;
+            const int left = cnt - k0;
+            const int top = t.total - 1;
 #pragma unroll
             for (int u0 = 0; u0 < 8; u0 += FB) {
                 double px[FB], py[FB], pz[FB];
@@ -314,10 +318,10 @@ __device__ __forceinline__ void force_passes(const ForceArgs &a, const TileSmem 
 #pragma unroll
                 for (int v = 0; v < FB; ++v) {
                     const int u = u0 + v;
-                    pv[v] = k0 + u < cnt && e[u] < t.total;
-                    if (LJMD_DEBUG_CHECKS && k0 + u < cnt && e[u] >= t.total)
+                    pv[v] = u < left;
+                    if (LJMD_DEBUG_CHECKS && pv[v] && e[u] > top)
                         debug_fail(reinterpret_cast<DevStatus *>(a.status), DBG_READ);
-                    const int idx = pv[v] ? e[u] : 0;
+                    const int idx = e[u] < top ? e[u] : top;
                     pt[v] = 0;
                     if (STAGED) {
                         const double4 pj = st[idx];
