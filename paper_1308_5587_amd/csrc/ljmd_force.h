@@ -231,14 +231,21 @@ __device__ __forceinline__ bool finish_particle(const ForceArgs &a, const RepPar
                 x.x = __builtin_fma(P.dt, v.x, x.x);
                 x.y = __builtin_fma(P.dt, v.y, x.y);
                 x.z = __builtin_fma(P.dt, v.z, x.z);
-                int4 im = a.img[q];
-                const int4 im0 = im;
-                wrap_coord(x.x, im.x, L0);
-                wrap_coord(x.y, im.y, L1);
-                wrap_coord(x.z, im.z, L2);
+                // the image counters change only where a coordinate wraps: they are read
+                // and written there alone
+                int4 d = make_int4(0, 0, 0, 0);
+                wrap_coord(x.x, d.x, L0);
+                wrap_coord(x.y, d.y, L1);
+                wrap_coord(x.z, d.z, L2);
                 a.pos_out[q] = x;
                 a.vel[q] = v;
-                if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
+                if (d.x | d.y | d.z) {
+                    int4 im = a.img[q];
+                    im.x += d.x;
+                    im.y += d.y;
+                    im.z += d.z;
+                    a.img[q] = im;
+                }
                 const double4 b_pre = a.xb[q];
                 if (LJMD_DEBUG_CHECKS) {
                     // the forces were taken at xi: within half the skin of the list's build

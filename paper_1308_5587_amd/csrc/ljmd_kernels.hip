@@ -91,17 +91,23 @@ __global__ void __launch_bounds__(256) k_kick_drift(const KickDriftArgs a) {
             v.x = __builtin_fma(hm, f.x, v.x);
             v.y = __builtin_fma(hm, f.y, v.y);
             v.z = __builtin_fma(hm, f.z, v.z);
-            int4 im = a.img[q];
-            const int4 im0 = im;
             x.x = __builtin_fma(P.dt, v.x, x.x);
             x.y = __builtin_fma(P.dt, v.y, x.y);
             x.z = __builtin_fma(P.dt, v.z, x.z);
-            wrap_coord(x.x, im.x, P.L[0]);
-            wrap_coord(x.y, im.y, P.L[1]);
-            wrap_coord(x.z, im.z, P.L[2]);
+            // the image counters are read and written only where a coordinate wraps
+            int4 d = make_int4(0, 0, 0, 0);
+            wrap_coord(x.x, d.x, P.L[0]);
+            wrap_coord(x.y, d.y, P.L[1]);
+            wrap_coord(x.z, d.z, P.L[2]);
             a.pos_out[q] = x;
             a.vel[q] = v;
-            if (im.x != im0.x || im.y != im0.y || im.z != im0.z) a.img[q] = im;
+            if (d.x | d.y | d.z) {
+                int4 im = a.img[q];
+                im.x += d.x;
+                im.y += d.y;
+                im.z += d.z;
+                a.img[q] = im;
+            }
             const double4 b = a.xb[q];
             const double dx = mi_rint(x.x - b.x, P.L[0], P.invL[0]);
             const double dy = mi_rint(x.y - b.y, P.L[1], P.invL[1]);
